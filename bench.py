@@ -1,0 +1,179 @@
+#!/usr/bin/env python3
+"""Benchmark: one step = forward MC + residual + adjoint MC + gradient on the
+256x256 disc phantom (four collimated line sources, 1e8 + 1e8 packets, N = 16
+harmonics), on one MI355X.  Prints one JSON line.
+
+The hot path follows Hochuli et al. (arXiv:1608.05238): forward radiance MC
+with the harmonic tally (Sec. 3, 3.1), adjoint source q* = mua (Hmeas - H)
+(Sec. 6), adjoint radiance MC (Sec. 4), gradients from harmonic products
+(Sec. 5).  Inputs are synthetic and resident in HBM before timing starts.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(n_packets: int, threads: int) -> dict:
+    """The FP64 oracle on a bounded sample of the same workload: forward,
+    residual, adjoint and gradient with n_packets each, timed on host cores."""
+    import numpy as np
+    import oracle as O
+    import phantoms as P
+    c = P.config2()
+    ph, true = c.phantom, c.extra["true"]
+    om = O.medium_from(ph)
+    # measured data: the oracle's own forward on the true phantom (untimed)
+    ht, _ = O.run_mc(O.medium_from(true), O.sources_from(c.sources), O.Run(n_packets, 1, 16), n_threads=threads)
+    hm = true.mua.astype(np.float64) * ht[0]
+    t0 = time.perf_counter()
+    fo, _ = O.run_mc(om, O.sources_from(c.sources), O.Run(n_packets, 0, 16), n_threads=threads)
+    _, q = O.residual(om, fo, hm)
+    ao, _ = O.run_mc(om, [O.Source(O.MAP, map=q)], O.Run(n_packets, 0, 16, stream_tag=1, adjoint=1),
+                     n_threads=threads)
+    O.gradient(om, 16, fo, ao, hm)
+    dt = time.perf_counter() - t0
+    return {"value": 2 * n_packets / dt, "unit": "packets/s", "cores": threads, "kind": "oracle",
+            "sample": f"disc256 forward+adjoint+gradient, {n_packets}+{n_packets} packets, N=16, FP64, "
+                      f"{dt:.1f} s"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--packets", type=float, default=1e8, help="packets per MC run (forward and adjoint each)")
+    ap.add_argument("--cpu-packets", type=int, default=60_000, help="oracle sample size (0: skip)")
+    ap.add_argument("--hmeas-packets", type=float, default=2e7)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run one plain device copy of this size first (calibrates HBM counters)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the Monte Carlo runs on a single MI355X; "
+              "multi-GPU packet sharding is described in DESIGN.md but not built.", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+    import phantoms as P
+    from paper_1608_05238_amd import rmc
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    if args.copy_probe_mib > 0:
+        a = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    c = P.config2()
+    N = c.n_harm
+    K = 2 * N + 1
+    Np = int(args.packets)
+    ph, true = c.phantom, c.extra["true"]
+    med = rmc.Medium.from_phantom(ph, dev)
+    # measured data Hmeas = mua Phi on the true phantom (untimed set-up)
+    log(f"set-up: Hmeas from {int(args.hmeas_packets)} packets on the true phantom")
+    tmed = rmc.Medium.from_phantom(true, dev)
+    ht, _ = rmc.mc_forward(tmed, c.sources, rmc.make_run(int(args.hmeas_packets), N, seed=1), ledger=False)
+    hmeas = (tmed.mua.double() * ht[0]).contiguous()
+    ws_f = torch.empty(rmc.mc_workspace_bytes(med, c.sources, rmc.make_run(Np, N)) + 256, dtype=torch.uint8,
+                       device=dev)
+    fwd = torch.empty((K, ph.nz, ph.nx), dtype=torch.float64, device=dev)
+    adj = torch.empty_like(fwd)
+    torch.cuda.synchronize()
+
+    ledgers = []
+
+    def step(i: int, keep: bool):
+        f, lf = rmc.mc_forward(med, c.sources, rmc.make_run(Np, N, seed=100 + i), out=fwd, workspace=ws_f)
+        q, eps = rmc.mc_residual(med, f, hmeas)
+        a, la = rmc.mc_adjoint(med, [P.SourceSpec("map", map=q)], rmc.make_run(Np, N, seed=100 + i, stream_tag=1),
+                               out=adj)
+        g = rmc.mc_gradient(med, N, f, a, hmeas)
+        if keep:
+            ledgers.append((lf, la))
+        return g
+
+    for i in range(args.warmup):
+        log(f"warmup step {i}")
+        step(i, False)
+    torch.cuda.synchronize()
+    rmc.mc_profile_read(reset=True)
+    rmc.mc_profile_enable(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for i in range(args.steps):
+        step(args.warmup + i, True)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    rmc.mc_profile_enable(False)
+    tr_ms, tr_launches = rmc.mc_profile_read(reset=True)
+    ms_total = e0.elapsed_time(e1)
+    ms_step = ms_total / args.steps
+    log(f"timed {args.steps} steps: {ms_step:.1f} ms/step (wall {wall:.2f} s)")
+
+    visits = segments = scatters = 0
+    for lf, la in ledgers:
+        for l in (rmc.ledger_dict(lf), rmc.ledger_dict(la)):
+            visits += l["visits"]
+            segments += l["segments"]
+            scatters += l["scatters"]
+    # algorithmic bytes per pixel visit: the K-channel FP64 tally update the
+    # method accumulates plus the two medium coefficients of the pixel
+    bytes_per_visit = K * 8 + 8
+    avg_launch_ms = tr_ms / max(tr_launches, 1)
+    achieved = visits * bytes_per_visit / tr_launches / (avg_launch_ms * 1e-3) / 1e9 if tr_launches else 0.0
+    value = 2 * Np * args.steps / (ms_total * 1e-3)
+    out = {
+        "metric": "packets/s fwd+adj MC (N=16 harmonics)",
+        "value": value,
+        "unit": "packets/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "disc256: 256x256 pixels of 0.1 mm, 3-6 seeded disc inclusions, 4 line sources, "
+                               "forward + adjoint + gradient",
+                   "packets_forward": Np, "packets_adjoint": Np, "n_harm": N, "tally": "fp32 chunks -> fp64"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_transport", "avg_launch_ms": avg_launch_ms, "launches": tr_launches,
+                     "bytes_per_visit": bytes_per_visit,
+                     "visits_per_packet": visits / (2 * Np * args.steps),
+                     "segments_per_packet": segments / (2 * Np * args.steps),
+                     "scatters_per_packet": scatters / (2 * Np * args.steps),
+                     "transport_share_of_step": tr_ms / ms_total},
+    }
+    if args.cpu_packets > 0:
+        threads = min(16, os.cpu_count() or 1)
+        log(f"cpu baseline: oracle with {args.cpu_packets}+{args.cpu_packets} packets on {threads} threads")
+        out["cpu_baseline"] = cpu_baseline(args.cpu_packets, threads)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,209 @@
+/*
+ * mcrad.h -- C ABI of librmc.so: forward and adjoint Monte Carlo of radiance
+ * in a 2D pixelated medium with a harmonic angular tally, and the functional
+ * gradients built from it, on one AMD Instinct MI355X (gfx950).
+ *
+ * The method is that of Hochuli, Powell, Arridge & Cox, "Quantitative
+ * photoacoustic tomography using forward and adjoint Monte Carlo models of
+ * radiance" (arXiv:1608.05238).  Each entry point names the section and
+ * equation it implements.
+ *
+ * General rules
+ *  - Every array argument whose name ends in _d is a DEVICE pointer owned by
+ *    the caller; the library never allocates, frees or keeps it.  Host
+ *    pointers end in _h.
+ *  - Calls that take a stream only enqueue work on that stream and return;
+ *    results are valid after the caller synchronises the stream.  Calls on
+ *    different streams with different workspaces may run concurrently.
+ *  - Return value: MC_OK, or an error code; no call throws.  Invalid
+ *    arguments are detected on the host before anything is enqueued.
+ *    MC_ERR_DEVICE reports a failed launch; faults inside a kernel surface at
+ *    the caller's next synchronisation.
+ *  - Maps are row-major [nz][nx]: x (lateral) is the column, z (depth) the
+ *    row.  Pixel (ix,iz) covers [ix dx,(ix+1) dx) x [iz dx,(iz+1) dx).
+ *  - Harmonic coefficient maps are planar [2N+1][nz][nx] FP64 in the order
+ *    a0, a1..aN, b1..bN, with the radiance expansion of Sec. 3.1
+ *    (eq. radiance_Fourier): phi = a0/2pi + (1/pi) sum_n (a_n cos n t + b_n sin n t),
+ *    t measured from +z towards +x, so a_n = int phi cos(n t) dt.  Each value
+ *    is the average over the pixel, per unit source power.
+ */
+#ifndef MCRAD_H
+#define MCRAD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MC_NHARM_MAX 32
+
+typedef enum {
+    MC_OK = 0,
+    MC_ERR_INVALID_ARG = 1,   /* a size, pointer or parameter is out of range */
+    MC_ERR_UNSUPPORTED = 2,   /* a valid request this build does not serve */
+    MC_ERR_DEVICE = 3,        /* a HIP call or launch failed */
+    MC_ERR_WORKSPACE = 4      /* workspace missing or smaller than mc_workspace_bytes() */
+} mc_status;
+
+/* Optical properties (Sec. 2 and 3): device FP32 maps [nz][nx] of the
+ * absorption and scattering coefficients (1/mm, >= 0) and the 2D
+ * Henyey-Greenstein anisotropy g in (-1, 1].  dx: pixel side in mm. */
+typedef struct {
+    int32_t nx, nz;
+    float dx;
+    const float *mua_d, *mus_d, *g_d;
+} mc_medium;
+
+typedef enum {
+    MC_SRC_PENCIL = 0,   /* collimated beam at (x0,z0) along (dir_x,dir_z) */
+    MC_SRC_LINE = 1,     /* segment (x0,z0)-(x1,z1); collimated along dir, or Lambertian about it */
+    MC_SRC_POINT = 2,    /* point (x0,z0) with angular profile prof (default isotropic) */
+    MC_SRC_MAP = 3       /* volumetric q(x) per unit angle per unit area, angular profile prof */
+} mc_source_kind;
+
+/* A light source (Sec. 3, 3.2, 4.1, 6.1) or, for mc_adjoint, an adjoint
+ * source (Sec. 4, 6).  Positions in mm, inside [0, nx dx] x [0, nz dx].
+ * Several non-MAP sources may be given together: each packet picks one with
+ * probability proportional to its power.  A MAP source must be the only one.
+ *  prof_h: host array [2 n_prof + 1] = c0, c1..cn, s1..sn giving the angular
+ *    profile p(t) = c0/2pi + (1/pi) sum (c_n cos n t + s_n sin n t); NULL
+ *    means isotropic (p = 1/2pi).  A POINT source emits power * p(t) per unit
+ *    angle; a MAP source emits map(x) * 2pi p(t).  Packets of these two kinds
+ *    are launched at a uniform angle with weight 2pi p(t) (times the sign of
+ *    the map value), so p may be signed.
+ *  map_d: device FP64 [nz][nx] (MAP only), may be signed (adjoint source). */
+typedef struct {
+    int32_t kind;            /* mc_source_kind */
+    float x0, z0, x1, z1;
+    float dir_x, dir_z;      /* unit vector */
+    int32_t lambertian;      /* LINE: 0 collimated, 1 Lambertian about dir */
+    double power;            /* PENCIL/LINE/POINT: > 0 */
+    const double *map_d;
+    int32_t n_prof;          /* 0..MC_NHARM_MAX */
+    const double *prof_h;
+} mc_source;
+
+#define MC_FLAG_LITERAL_TRUNCATION 1u  /* stop below the threshold (Sec. 3) instead of roulette */
+
+/* One Monte Carlo run.  Packet p (first_packet_id <= p < first_packet_id +
+ * n_packets) draws its random numbers from Philox4x32-10 with key = seed and
+ * counter = (j, stream_tag, p_lo, p_hi): block j = 0 launches it, block k >= 1
+ * gives the k-th free path (u0), the scattering angle at its end (u1) and the
+ * roulette draw there (u2); u = ((x >> 9) + 0.5) 2^-23.  The result is a
+ * pure function of (inputs, seed, stream_tag, packet range). */
+typedef struct {
+    uint64_t n_packets;        /* >= 1 */
+    uint64_t seed;
+    uint64_t first_packet_id;
+    uint32_t stream_tag;
+    int32_t n_harm;            /* N in [0, MC_NHARM_MAX]: K = 2N+1 channels */
+    float w_threshold;         /* roulette below w_threshold * |W0| (e.g. 1e-4) */
+    float roulette_m;          /* > 1: survive with probability 1/m, weight * m */
+    uint32_t flags;            /* MC_FLAG_* */
+} mc_run;
+
+/* Energy ledger of one run (device struct written by mc_forward/mc_adjoint).
+ * Weight sums are raw packet-weight sums; multiply by `scale` (total source
+ * measure / n_packets) for power.  launched + roulette_gain - roulette_loss
+ * equals absorbed + escaped up to FP32 rounding. */
+typedef struct {
+    double launched, absorbed, escaped, roulette_gain, roulette_loss;
+    double scale;
+    uint64_t packets, segments, visits, scatters;
+} mc_ledger;
+
+/* Bytes of device workspace a forward/adjoint run needs (tallies, packet
+ * counter, source tables).  0 on invalid arguments. */
+size_t mc_workspace_bytes(const mc_medium *medium, const mc_source *src, int n_src, const mc_run *run);
+
+/* Forward radiance MC (Sec. 3, 3.1): launch, exponential free paths through
+ * the pixels, continuous absorption weighting, roulette, 2D Henyey-Greenstein
+ * scattering (eqs. scattering2D, scattering_angle), and the harmonic
+ * track-length tally (eq. Fourier_terms) normalised by the packet count
+ * (Sec. 6).  coeffs_d: FP64 [2N+1][nz][nx] (overwritten).  ledger_d: device
+ * mc_ledger or NULL.  workspace_d: >= mc_workspace_bytes() bytes, 256-byte
+ * aligned; its contents are scratch. */
+mc_status mc_forward(const mc_medium *medium, const mc_source *src, int n_src, const mc_run *run,
+                     double *coeffs_d, mc_ledger *ledger_d, void *workspace_d, size_t workspace_bytes,
+                     void *stream);
+
+/* Adjoint radiance MC (Sec. 4, eq. adjoint_RTE1; Sec. 6): solves the adjoint
+ * RTE with source `src` (typically one MAP source q* from mc_residual).  The
+ * adjoint field equals the forward field of the direction-mirrored source
+ * read at the mirrored direction: source profiles and collimated directions
+ * are mirrored on input and the output orders n >= 1 are multiplied by
+ * (-1)^n, so coeffs_d holds the adjoint radiance phi*(x, s) itself. */
+mc_status mc_adjoint(const mc_medium *medium, const mc_source *src, int n_src, const mc_run *run,
+                     double *coeffs_d, mc_ledger *ledger_d, void *workspace_d, size_t workspace_bytes,
+                     void *stream);
+
+/* Residual (Sec. 2 eq. error_function3, Sec. 6): H = mua a0 (Grueneisen 1),
+ * r = hmeas - H, q* = mua r (per unit angle), eps = (dx^2 / 2) sum r^2.
+ * coeffs_d: forward FP64 [>=1][nz][nx] (only a0 is read); hmeas_d FP64
+ * [nz][nx]; q_star_d FP64 [nz][nx] out (may be NULL); eps_d device double out. */
+mc_status mc_residual(const mc_medium *medium, const double *coeffs_d, const double *hmeas_d,
+                      double *q_star_d, double *eps_d, void *stream);
+
+/* Gradients (Sec. 5): with a', b' the adjoint coefficients, per pixel dx^2 times
+ *   d eps/d mua = -a0 (hmeas - mua a0) + a0 a0' / 2pi + (1/pi) sum_n (a_n a_n' + b_n b_n')
+ *                 (eq. grad_2D_abs_integral3)
+ *   d eps/d mus = (1/pi) sum_{n>=1} (a_n a_n' + b_n b_n') (1 - g^n)
+ *                 (eq. scattering_gradient3)
+ * fwd_d, adj_d: FP64 [2N+1][nz][nx] from mc_forward / mc_adjoint.
+ * dmua_d, dmus_d: FP64 [nz][nx] out (either may be NULL). */
+mc_status mc_gradient(const mc_medium *medium, int n_harm, const double *fwd_d, const double *adj_d,
+                      const double *hmeas_d, double *dmua_d, double *dmus_d, void *stream);
+
+/* Detector readout <phi, b> (Sec. 4.1, eq. adj_definition): the integral over
+ * the domain and angle of a radiance times a detector weight function b, both
+ * given by harmonic maps with the same convention:
+ *   sum_i dx^2 [a0 d0/2pi + (1/pi) sum_n (a_n dc_n + b_n ds_n)].
+ * det_d: FP64 [2N+1][nz][nx].  out_d: device double. */
+mc_status mc_detect(const mc_medium *medium, int n_harm, const double *coeffs_d, const double *det_d,
+                    double *out_d, void *stream);
+
+/* Event record of mc_trace. */
+typedef struct {
+    uint64_t pid;
+    int32_t k;        /* index of the free path the event ends (0: launch) */
+    int32_t type;     /* 0 launch, 1 pixel crossing, 2 scatter, 3 escape, 4 roulette kill */
+    int32_t ix, iz;   /* pixel of the segment that ends here (launch: start pixel) */
+    float x, z;       /* position (mm) */
+    float sx, sz;     /* direction after the event */
+    float w;          /* weight after the event (escape/kill: the weight lost) */
+    float t;          /* track-length deposit of the segment (mm) */
+} mc_event;
+
+/* Per-event trace of selected packets, run by the same device transport code
+ * as mc_forward (adjoint != 0: as mc_adjoint).  Synchronous: allocates its own
+ * device buffers, runs on the null stream and copies back.  pids_h: host
+ * packet ids; events_h: host buffer of cap events; *n_events_h receives the
+ * number of events produced (may exceed cap; only cap are stored). */
+mc_status mc_trace(const mc_medium *medium, const mc_source *src, int n_src, const mc_run *run,
+                   int adjoint, const uint64_t *pids_h, int n_pids, mc_event *events_h, size_t cap,
+                   size_t *n_events_h);
+
+/* Philox4x32-10 blocks (j, tag, pid0 + i) under key seed, i < n, written to
+ * out_d[4i..4i+3] (device uint32).  Exposes the generator for checking. */
+mc_status mc_philox_fill(uint64_t seed, uint32_t tag, uint64_t pid0, uint64_t n, uint32_t j,
+                         uint32_t *out_d, void *stream);
+
+/* Timing of the transport kernel launches: when enabled, every transport
+ * launch made by mc_forward / mc_adjoint is bracketed by two HIP events
+ * recorded on the caller's stream.  mc_profile_read waits for the pending
+ * events, adds their elapsed times to a running total and returns the total
+ * time (ms) and the number of launches since the last reset.  Host-side
+ * bookkeeping only; thread-safe. */
+void mc_profile_enable(int on);
+mc_status mc_profile_read(double *transport_ms, uint64_t *launches, int reset);
+
+const char *mc_status_string(mc_status s);
+/* Library build identifier (architecture and tally configuration). */
+const char *mc_build_info(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MCRAD_H */

@@ -1,0 +1,106 @@
+"""ctypes declarations of the C ABI in include/mcrad.h (librmc.so).
+
+Loading fails loudly if the in-tree library has not been built: there is no
+CPU fallback anywhere in this package.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librmc.so")
+
+MC_OK, MC_ERR_INVALID_ARG, MC_ERR_UNSUPPORTED, MC_ERR_DEVICE, MC_ERR_WORKSPACE = range(5)
+MC_SRC_PENCIL, MC_SRC_LINE, MC_SRC_POINT, MC_SRC_MAP = range(4)
+MC_FLAG_LITERAL_TRUNCATION = 1
+MC_NHARM_MAX = 32
+
+# exported symbols declared in include/mcrad.h
+SYMBOLS = ("mc_workspace_bytes", "mc_forward", "mc_adjoint", "mc_residual", "mc_gradient", "mc_detect",
+           "mc_trace", "mc_philox_fill", "mc_profile_enable", "mc_profile_read", "mc_status_string",
+           "mc_build_info")
+
+
+class mc_medium(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("nz", C.c_int32), ("dx", C.c_float),
+                ("mua_d", C.c_void_p), ("mus_d", C.c_void_p), ("g_d", C.c_void_p)]
+
+
+class mc_source(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("x0", C.c_float), ("z0", C.c_float), ("x1", C.c_float),
+                ("z1", C.c_float), ("dir_x", C.c_float), ("dir_z", C.c_float),
+                ("lambertian", C.c_int32), ("power", C.c_double), ("map_d", C.c_void_p),
+                ("n_prof", C.c_int32), ("prof_h", C.POINTER(C.c_double))]
+
+
+class mc_run(C.Structure):
+    _fields_ = [("n_packets", C.c_uint64), ("seed", C.c_uint64), ("first_packet_id", C.c_uint64),
+                ("stream_tag", C.c_uint32), ("n_harm", C.c_int32), ("w_threshold", C.c_float),
+                ("roulette_m", C.c_float), ("flags", C.c_uint32)]
+
+
+class mc_ledger(C.Structure):
+    _fields_ = [("launched", C.c_double), ("absorbed", C.c_double), ("escaped", C.c_double),
+                ("roulette_gain", C.c_double), ("roulette_loss", C.c_double), ("scale", C.c_double),
+                ("packets", C.c_uint64), ("segments", C.c_uint64), ("visits", C.c_uint64),
+                ("scatters", C.c_uint64)]
+
+
+class mc_event(C.Structure):
+    _fields_ = [("pid", C.c_uint64), ("k", C.c_int32), ("type", C.c_int32), ("ix", C.c_int32),
+                ("iz", C.c_int32), ("x", C.c_float), ("z", C.c_float), ("sx", C.c_float),
+                ("sz", C.c_float), ("w", C.c_float), ("t", C.c_float)]
+
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Load librmc.so (raises if it is missing: build it with paper_1608_05238_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing; build it with `python -m paper_1608_05238_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    P, V, St = C.POINTER, C.c_void_p, C.c_int
+    lib.mc_workspace_bytes.argtypes = [P(mc_medium), P(mc_source), C.c_int, P(mc_run)]
+    lib.mc_workspace_bytes.restype = C.c_size_t
+    for name in ("mc_forward", "mc_adjoint"):
+        f = getattr(lib, name)
+        f.argtypes = [P(mc_medium), P(mc_source), C.c_int, P(mc_run), V, V, V, C.c_size_t, V]
+        f.restype = St
+    lib.mc_residual.argtypes = [P(mc_medium), V, V, V, V, V]
+    lib.mc_residual.restype = St
+    lib.mc_gradient.argtypes = [P(mc_medium), C.c_int, V, V, V, V, V, V]
+    lib.mc_gradient.restype = St
+    lib.mc_detect.argtypes = [P(mc_medium), C.c_int, V, V, V, V]
+    lib.mc_detect.restype = St
+    lib.mc_trace.argtypes = [P(mc_medium), P(mc_source), C.c_int, P(mc_run), C.c_int, P(C.c_uint64), C.c_int,
+                             P(mc_event), C.c_size_t, P(C.c_size_t)]
+    lib.mc_trace.restype = St
+    lib.mc_philox_fill.argtypes = [C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint64, C.c_uint32, V, V]
+    lib.mc_philox_fill.restype = St
+    lib.mc_profile_enable.argtypes = [C.c_int]
+    lib.mc_profile_enable.restype = None
+    lib.mc_profile_read.argtypes = [P(C.c_double), P(C.c_uint64), C.c_int]
+    lib.mc_profile_read.restype = St
+    lib.mc_status_string.argtypes = [C.c_int]
+    lib.mc_status_string.restype = C.c_char_p
+    lib.mc_build_info.argtypes = []
+    lib.mc_build_info.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+class MCError(RuntimeError):
+    def __init__(self, fn: str, code: int):
+        msg = load().mc_status_string(code).decode()
+        super().__init__(f"{fn} failed: {msg} (status {code})")
+        self.code = code
+
+
+def check(fn: str, code: int) -> None:
+    if code != MC_OK:
+        raise MCError(fn, code)

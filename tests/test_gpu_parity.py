@@ -1,0 +1,394 @@
+"""GPU path (librmc.so through its C ABI) against the FP64 CPU oracle.
+
+Bar: bit-exact for the random-number generator; per packet trajectory within
+1e-5 relative; coefficient maps within max(1e-4 relative, 3 MC standard
+errors); FP64 post-processing (residual, gradient, readout) within 1e-12.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import phantoms as P
+
+pytestmark = pytest.mark.gpu
+
+OUT = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+
+
+def _rmc():
+    import torch  # noqa: F401
+    from paper_1608_05238_amd import rmc
+    return rmc
+
+
+def _record(name, payload):
+    os.makedirs(OUT, exist_ok=True)
+    with open(os.path.join(OUT, "parity_stats.jsonl"), "a") as f:
+        f.write(json.dumps({"test": name, **payload}) + "\n")
+
+
+def _oracle():
+    import oracle
+    oracle.build(force=False)
+    return oracle
+
+
+def _gpu_run(rmc, ph, specs, n, N, seed=0, adjoint=False, first=0, tag=0, **kw):
+    med = rmc.Medium.from_phantom(ph)
+    run = rmc.make_run(n, N, seed=seed, first_packet_id=first, stream_tag=tag, **kw)
+    fn = rmc.mc_adjoint if adjoint else rmc.mc_forward
+    co, led = fn(med, specs, run)
+    return co.cpu().numpy(), rmc.ledger_dict(led)
+
+
+def _oracle_batches(O, ph, specs, n, N, B, seed=0, adjoint=False, first=0, tag=0, **kw):
+    med = O.medium_from(ph)
+    src = O.sources_from(specs)
+    outs = []
+    for b in range(B):
+        a = first + (n * b) // B
+        e = first + (n * (b + 1)) // B
+        r = O.Run(e - a, seed, N, first_packet_id=a, stream_tag=tag, adjoint=int(adjoint), **kw)
+        outs.append(O.run_mc(med, src, r, n_threads=min(16, os.cpu_count() or 8))[0] * (e - a) / n)
+    outs = np.array(outs)
+    total = outs.sum(axis=0)
+    se = outs.std(axis=0, ddof=1) * np.sqrt(B)     # SE of the total from B equal batches
+    return total, se
+
+
+def _assert_maps(name, gpu, ora, se):
+    tol = np.maximum(1e-4 * np.abs(ora), 3 * se)
+    bad = np.abs(gpu - ora) > tol + 1e-300
+    rel = np.abs(gpu - ora) / np.maximum(np.abs(ora), 1e-300)
+    big = np.abs(ora) > 1e-3 * np.abs(ora).max()
+    stats = {"max_rel_err_significant": float(rel[big].max()), "median_rel_err": float(np.median(rel[big])),
+             "frac_outside_tol": float(bad.mean())}
+    _record(name, stats)
+    assert not bad.any(), (name, stats, np.argwhere(bad)[:5])
+
+
+# ---------------------------------------------------------------- RNG
+def test_philox_bit_exact():
+    rmc = _rmc()
+    O = _oracle()
+    for seed, tag, pid0, n, j in [(0, 0, 0, 1 << 18, 0), (0xDEADBEEF12345, 1, (1 << 32) - 1000, 1 << 17, 3),
+                                  (7, 5, 123_456_789_012, 1 << 16, 1 << 20)]:
+        g = rmc.mc_philox_fill(seed, tag, pid0, n, j).cpu().numpy().view(np.uint32)
+        o = O.philox_fill(seed, tag, pid0, n, j)
+        assert np.array_equal(g, o)
+
+
+# ---------------------------------------------------------------- per-trajectory parity
+def _face_dist(v, dx):
+    """Distance (mm) from a coordinate to the nearest pixel face."""
+    r = v / dx
+    return abs(r - np.round(r)) * dx
+
+
+def _is_tie(ev, dx, tol):
+    """A decision the FP32 and FP64 paths may take differently: the event sits at a
+    pixel corner (which face is crossed first), or a scatter / kill sits on a face
+    (scatter inside the pixel or cross first)."""
+    nx_, nz_ = _face_dist(ev["x"], dx) < tol, _face_dist(ev["z"], dx) < tol
+    if nx_ and nz_:
+        return True
+    return ev["type"] in (2, 4) and (nx_ or nz_)
+
+
+K_TIGHT = 256   # interactions over which the 1e-5 bar applies; FP32 drift grows beyond
+
+
+def _compare_traces(g, o, dx, width):
+    """Compare event sequences packet by packet, up to the first divergence.
+
+    Errors: positions relative to the domain extent, directions absolute,
+    weights relative, and the packet's summed deposit relative.  A divergence
+    (a branch taken differently) is accepted only at a near-tie whose margin
+    is within 1e-3 pixel plus ten times the position error reached so far.
+    Returns (n_packets, n_divergent, n_bad_divergences, tight errors [pos, dir,
+    w, T-sum] over k <= K_TIGHT, loose errors over the whole matched prefix)."""
+    div = bad = 0
+    pids = np.unique(o["pid"])
+    tight, loose = [], []
+    for pid in pids:
+        ge, oe = g[g["pid"] == pid], o[o["pid"] == pid]
+        n = min(len(ge), len(oe))
+        et, el = np.zeros(4), np.zeros(4)
+        tg = to = 0.0
+        tg_t = to_t = 0.0
+        perr = 0.0
+        diverged = None
+        for i in range(n):
+            a, b = ge[i], oe[i]
+            if a["type"] != b["type"] or a["ix"] != b["ix"] or a["iz"] != b["iz"] or a["k"] != b["k"]:
+                diverged = i
+                break
+            tg += a["t"]
+            to += b["t"]
+            perr = max(abs(a["x"] - b["x"]), abs(a["z"] - b["z"]))
+            e = np.array([perr / width, max(abs(a["sx"] - b["sx"]), abs(a["sz"] - b["sz"])),
+                          abs(a["w"] - b["w"]) / max(abs(b["w"]), 1e-30), 0.0])
+            el = np.maximum(el, e)
+            if b["k"] <= K_TIGHT:
+                tg_t, to_t = tg, to
+                et = np.maximum(et, e)
+        et[3] = abs(tg_t - to_t) / max(abs(to_t), dx)
+        el[3] = abs(tg - to) / max(abs(to), dx)
+        if diverged is None and len(ge) != len(oe):
+            diverged = n
+        if diverged is not None:
+            div += 1
+            i = min(diverged, n - 1)
+            tol = 1e-3 * dx + 10 * perr
+            if not (_is_tie(ge[i], dx, tol) or _is_tie(oe[i], dx, tol)):
+                bad += 1
+        tight.append(et)
+        loose.append(el)
+    return len(pids), div, bad, np.array(tight), np.array(loose)
+
+
+def _trace_case(rmc, O, ph, specs, N, pids, adjoint=False, tag=0, seed=0):
+    med = rmc.Medium.from_phantom(ph)
+    run = rmc.make_run(1, N, seed=seed, stream_tag=tag)
+    g = rmc.mc_trace(med, specs, run, pids, adjoint=adjoint)
+    o = O.trace(O.medium_from(ph), O.sources_from(specs), O.Run(1, seed, N, stream_tag=tag, adjoint=int(adjoint)),
+                pids)
+    return _compare_traces(g, o, ph.dx, max(ph.width, ph.depth))
+
+
+@pytest.mark.parametrize("case", ["pencil32", "disc256", "adjoint_map"])
+def test_trajectory_parity(case):
+    rmc = _rmc()
+    O = _oracle()
+    rng = np.random.default_rng(21)
+    if case == "pencil32":
+        c = P.config1()
+        ph, specs, N, adj, tag = c.phantom, c.sources, 8, False, 0
+        pids = rng.choice(100_000, 200, replace=False)
+    elif case == "disc256":
+        c = P.config2()
+        ph, specs, N, adj, tag = c.phantom, c.sources, 16, False, 0
+        pids = np.concatenate([rng.integers(0, 100_000_000, 60), [0, 1, 99_999_999]])
+    else:
+        c = P.config2()
+        ph = c.phantom
+        specs = [P.map_source(P.residual_like_map(ph))]
+        N, adj, tag = 16, True, 1
+        pids = rng.integers(0, 100_000_000, 60)
+    n, div, bad, tight, loose = _trace_case(rmc, O, ph, specs, N, pids, adjoint=adj, tag=tag)
+    stats = {"packets": n, "divergent_at_ties": div, "divergent_not_at_ties": bad}
+    for j, nm in enumerate(("pos", "dir", "w", "tsum")):
+        stats[nm + f"_max_k{K_TIGHT}"] = float(tight[:, j].max())
+        stats[nm + "_max_all"] = float(loose[:, j].max())
+        stats[nm + "_median_all"] = float(np.median(loose[:, j]))
+    _record("trace_" + case, stats)
+    assert bad == 0, stats
+    assert div <= max(2, n // 4), stats
+    # FP32 transport against the FP64 oracle: 1e-5 over the first K_TIGHT interactions,
+    # FP32 drift beyond (direction error ~1e-7 per scatter) bounded by 1e-3
+    assert tight.max() < 1e-5, stats
+    assert loose.max() < 1e-3, stats
+
+
+# ---------------------------------------------------------------- coefficient maps
+def test_forward_maps_pencil32_full():
+    """The 32x32 pencil-beam workload at its full 1e5 packets, N = 8."""
+    rmc = _rmc()
+    O = _oracle()
+    c = P.config1()
+    gpu, led = _gpu_run(rmc, c.phantom, c.sources, c.n_packets, c.n_harm)
+    ora, se = _oracle_batches(O, c.phantom, c.sources, c.n_packets, c.n_harm, B=10)
+    _assert_maps("forward_pencil32", gpu, ora, se)
+    bal = led["launched"] + led["roulette_gain"] - led["roulette_loss"] - led["absorbed"] - led["escaped"]
+    assert abs(bal) < 1e-5 * led["launched"]
+    assert led["packets"] == c.n_packets
+
+
+def test_forward_maps_disc256_subsample():
+    """The 256x256 disc-phantom workload (four line sources, N = 16) on 3e4 packets."""
+    rmc = _rmc()
+    O = _oracle()
+    c = P.config2()
+    n = 30_000
+    gpu, _ = _gpu_run(rmc, c.phantom, c.sources, n, 16)
+    ora, se = _oracle_batches(O, c.phantom, c.sources, n, 16, B=10)
+    _assert_maps("forward_disc256_3e4", gpu, ora, se)
+
+
+def test_adjoint_maps_disc256_subsample():
+    rmc = _rmc()
+    O = _oracle()
+    c = P.config2()
+    specs = [P.map_source(P.residual_like_map(c.phantom))]
+    n = 30_000
+    gpu, led = _gpu_run(rmc, c.phantom, specs, n, 16, adjoint=True, tag=1)
+    ora, se = _oracle_batches(O, c.phantom, specs, n, 16, B=10, adjoint=True, tag=1)
+    _assert_maps("adjoint_disc256_3e4", gpu, ora, se)
+    assert led["packets"] == n
+
+
+@pytest.mark.parametrize("N", [0, 1, 5, 32])
+def test_forward_maps_harmonic_orders(N):
+    rmc = _rmc()
+    O = _oracle()
+    ph = P.disc_phantom(24, 0.25, 0.05, 6.0, 0.85, seed=3, radius=(0.5, 1.5))
+    specs = [P.point_source(3.1, 2.2), P.SourceSpec("line", 0.0, 0.0, 6.0, 0.0, 0.0, 1.0, 0, 0.5)]
+    n = 20_000
+    gpu, _ = _gpu_run(rmc, ph, specs, n, N, seed=3)
+    ora, se = _oracle_batches(O, ph, specs, n, N, B=10, seed=3)
+    _assert_maps(f"forward_orders_N{N}", gpu, ora, se)
+
+
+def test_forward_global_tally_across_chunks():
+    """More packets than one launch chunk (2^22) on a grid that uses the HBM tally.
+
+    The run over [0, n) equals the packet-weighted combination of runs over
+    sub-ranges (the same packets), up to the FP32 rounding of the per-chunk
+    tallies, which must stay far below the Monte Carlo standard error; and a
+    sub-range straddling the chunk edge matches the oracle."""
+    rmc = _rmc()
+    O = _oracle()
+    ph = P.disc_phantom(96, 0.1, 0.02, 8.0, 0.9, seed=4)
+    specs = P.four_side_lines(ph)
+    n = (1 << 22) + 5000
+    full, _ = _gpu_run(rmc, ph, specs, n, 16, seed=9)
+    B = 8
+    parts = []
+    for b in range(B):
+        a0, a1 = n * b // B, n * (b + 1) // B
+        parts.append(_gpu_run(rmc, ph, specs, a1 - a0, 16, seed=9, first=a0)[0] * (a1 - a0) / n)
+    parts = np.array(parts)
+    comb = parts.sum(axis=0)
+    se = parts.std(axis=0, ddof=1) * np.sqrt(B)
+    gap = np.abs(full - comb)
+    _record("chunk_additivity", {"max_gap_over_se": float((gap / np.maximum(se, 1e-300)).max()),
+                                 "median_gap_over_se": float(np.median(gap / np.maximum(se, 1e-300)))})
+    assert np.all(gap <= 0.05 * se + 1e-12 * np.abs(full).max())
+    m = 8000
+    first = (1 << 22) - 4000
+    gpu, _ = _gpu_run(rmc, ph, specs, m, 16, seed=9, first=first)
+    ora, se = _oracle_batches(O, ph, specs, m, 16, B=8, seed=9, first=first)
+    _assert_maps("forward_chunk_edge", gpu, ora, se)
+
+
+def test_edge_cases_small_runs():
+    rmc = _rmc()
+    O = _oracle()
+    # one packet; non-scattering and non-absorbing pixels; g = 1 region
+    ph = P.homogeneous(6, 5, 0.4, 0.0, 3.0, 0.5)
+    ph.mus[:, 2] = 0.0
+    ph.g[3:, :] = 1.0
+    ph.mua[1, :] = 0.7
+    specs = [P.point_source(1.0, 1.0)]
+    for n in (1, 7, 1000):
+        gpu, led = _gpu_run(rmc, ph, specs, n, 3, seed=11)
+        ora, se = _oracle_batches(O, ph, specs, n, 3, B=1 if n < 2 else min(n, 8), seed=11)
+        if n == 1:
+            np.testing.assert_allclose(gpu, ora, rtol=1e-4, atol=1e-6 * np.abs(ora).max())
+        else:
+            _assert_maps(f"edge_n{n}", gpu, ora, se)
+        assert led["packets"] == n
+    # a packet launched on the outer boundary pointing outwards escapes at once
+    out = [P.SourceSpec("pencil", 1.0, 0.0, 0, 0, 0.0, -1.0, 0, 1.0)]
+    gpu, led = _gpu_run(rmc, ph, out, 100, 2)
+    assert np.all(gpu == 0.0) and led["escaped"] == pytest.approx(100.0)
+
+
+def test_literal_truncation_flag():
+    rmc = _rmc()
+    O = _oracle()
+    ph = P.homogeneous(10, 10, 0.5, 1.5, 10.0, 0.3)
+    specs = P.pencil_top_centre(ph)
+    n = 20_000
+    gpu, led = _gpu_run(rmc, ph, specs, n, 2, w_threshold=0.01, flags=1)
+    ora, se = _oracle_batches(O, ph, specs, n, 2, B=8, w_threshold=0.01, flags=1)
+    _assert_maps("literal_truncation", gpu, ora, se)
+    assert led["roulette_gain"] == 0 and led["roulette_loss"] > 0
+
+
+# ---------------------------------------------------------------- FP64 post-processing
+def test_residual_gradient_detect_fp64():
+    import torch
+    rmc = _rmc()
+    O = _oracle()
+    rng = np.random.default_rng(12)
+    ph = P.disc_phantom(64, 0.25, 0.02, 5.0, 0.8, seed=5)
+    N = 16
+    fwd = rng.uniform(0, 2, (2 * N + 1, 64, 64))
+    adj = rng.normal(0, 1, (2 * N + 1, 64, 64))
+    hm = P.smooth_hmeas(ph)
+    med = rmc.Medium.from_phantom(ph)
+    tf = torch.as_tensor(fwd, device="cuda")
+    ta = torch.as_tensor(adj, device="cuda")
+    th = torch.as_tensor(hm, device="cuda")
+    q, eps = rmc.mc_residual(med, tf, th)
+    dmua, dmus = rmc.mc_gradient(med, N, tf, ta, th)
+    det = rmc.mc_detect(med, N, tf, ta)
+    om = O.medium_from(ph)
+    e_o, q_o = O.residual(om, fwd, hm)
+    da_o, ds_o = O.gradient(om, N, fwd, adj, hm)
+    d_o = O.detect(om, N, fwd, adj)
+    assert float(eps) == pytest.approx(e_o, rel=1e-12)
+    # the device may contract mua*a0 into an FMA: compare on the scale of the terms
+    scale = np.abs(ph.mua.astype(np.float64) * hm).max()
+    np.testing.assert_allclose(q.cpu().numpy(), q_o, rtol=1e-12, atol=1e-14 * scale)
+    np.testing.assert_allclose(dmua.cpu().numpy(), da_o, rtol=1e-11, atol=1e-14 * np.abs(da_o).max())
+    np.testing.assert_allclose(dmus.cpu().numpy(), ds_o, rtol=1e-11, atol=1e-14 * np.abs(ds_o).max())
+    assert float(det) == pytest.approx(d_o, rel=1e-12)
+
+
+def test_full_chain_disc256_subsample():
+    """forward -> residual -> adjoint -> gradient on the 256x256 workload at 4e4 + 4e4
+    packets, against the same chain in the oracle."""
+    import torch
+    rmc = _rmc()
+    O = _oracle()
+    c = P.config2()
+    ph = c.phantom
+    N, n = 16, 40_000
+    hm = P.smooth_hmeas(ph, level=0.02)
+    med = rmc.Medium.from_phantom(ph)
+    fwd, _ = rmc.mc_forward(med, c.sources, rmc.make_run(n, N, seed=0))
+    q, eps = rmc.mc_residual(med, fwd, torch.as_tensor(hm, device="cuda"))
+    adj, _ = rmc.mc_adjoint(med, [P.SourceSpec("map", map=q)], rmc.make_run(n, N, seed=0, stream_tag=1))
+    dmua, dmus = rmc.mc_gradient(med, N, fwd, adj, torch.as_tensor(hm, device="cuda"))
+    om = O.medium_from(ph)
+    fo, _ = O.run_mc(om, O.sources_from(c.sources), O.Run(n, 0, N), n_threads=min(16, os.cpu_count() or 8))
+    e_o, q_o = O.residual(om, fo, hm)
+    ao, _ = O.run_mc(om, [O.Source(O.MAP, map=q_o)], O.Run(n, 0, N, stream_tag=1, adjoint=1),
+                     n_threads=min(16, os.cpu_count() or 8))
+    ga, gs = O.gradient(om, N, fo, ao, hm)
+    # the MC noise of the gradient: the same chain with an independent adjoint stream
+    ao2, _ = O.run_mc(om, [O.Source(O.MAP, map=q_o)], O.Run(n, 7, N, stream_tag=1, adjoint=1),
+                      n_threads=min(16, os.cpu_count() or 8))
+    ga2, gs2 = O.gradient(om, N, fo, ao2, hm)
+    assert float(eps) == pytest.approx(e_o, rel=1e-4)
+    for name, g, o, o2 in (("dmua", dmua, ga, ga2), ("dmus", dmus, gs, gs2)):
+        g = g.cpu().numpy()
+        diff = np.linalg.norm(g - o)
+        noise = np.linalg.norm(o - o2) / np.sqrt(2)
+        _record("chain_" + name, {"rel_l2_vs_oracle": float(diff / np.linalg.norm(o)),
+                                  "rel_l2_mc_noise": float(noise / np.linalg.norm(o))})
+        # same random numbers: the GPU/oracle gap must be far below the MC noise
+        assert diff < 0.2 * noise, (name, diff, noise)
+
+
+def test_full_size_disc256_properties():
+    """The benchmark's launch: 1e8 packets, N = 16, 256x256.  Checked through what
+    holds at any size (energy balance, absorbed power = sum mua a0 A) and against
+    the oracle on packet sub-ranges taken from the same full-size run's range."""
+    rmc = _rmc()
+    O = _oracle()
+    c = P.config2()
+    gpu, led = _gpu_run(rmc, c.phantom, c.sources, c.n_packets, 16)
+    assert led["packets"] == c.n_packets
+    bal = led["launched"] + led["roulette_gain"] - led["roulette_loss"] - led["absorbed"] - led["escaped"]
+    assert abs(bal) < 1e-5 * led["launched"]
+    absorbed = (c.phantom.mua.astype(np.float64) * gpu[0]).sum() * c.phantom.dx ** 2
+    assert absorbed == pytest.approx(led["absorbed"] * led["scale"], rel=1e-4)
+    for first in (0, 57_000_000, c.n_packets - 20_000):
+        g, _ = _gpu_run(rmc, c.phantom, c.sources, 20_000, 16, first=first)
+        o, se = _oracle_batches(O, c.phantom, c.sources, 20_000, 16, B=8, first=first)
+        _assert_maps(f"full_size_subrange_{first}", g, o, se)

@@ -1,0 +1,113 @@
+"""Host-side checks of librmc.so that need no GPU: it loads, exports every entry
+point declared in include/mcrad.h, its structs match the binding, and invalid
+arguments are rejected on the host before anything touches a device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_1608_05238_amd import _lib as L
+    if not os.path.exists(L.LIB_PATH):
+        from paper_1608_05238_amd import build
+        build.build()
+    return L, L.load()
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "mcrad.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mc_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_entry_point():
+    L, lib = _lib()
+    declared = _declared_functions()
+    assert "mc_forward" in declared and "mc_adjoint" in declared and "mc_gradient" in declared
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(declared) == set(L.SYMBOLS)
+
+
+def test_struct_layouts():
+    L, _ = _lib()
+    assert C.sizeof(L.mc_event) == 48
+    assert C.sizeof(L.mc_ledger) == 80
+    assert C.sizeof(L.mc_run) == 48
+    assert C.sizeof(L.mc_medium) == 40
+
+
+def test_status_strings_and_build_info():
+    L, lib = _lib()
+    assert lib.mc_status_string(0) == b"ok"
+    assert b"invalid" in lib.mc_status_string(1)
+    assert b"gfx950" in lib.mc_build_info()
+
+
+def _medium(L, nx=4, nz=4, dx=0.5, ptr=0x1000):
+    return L.mc_medium(nx, nz, dx, ptr, ptr, ptr)
+
+
+def _pencil(L):
+    s = L.mc_source()
+    s.kind, s.x0, s.z0, s.dir_x, s.dir_z, s.power = L.MC_SRC_PENCIL, 1.0, 0.0, 0.0, 1.0, 1.0
+    return s
+
+
+@pytest.mark.parametrize("bad", ["nx", "harm", "packets", "power", "outside", "dir", "roulette", "nsrc"])
+def test_invalid_arguments_rejected_on_host(bad):
+    """Every check runs before any HIP call, so these need no GPU."""
+    L, lib = _lib()
+    m = _medium(L)
+    src = (L.mc_source * 1)(_pencil(L))
+    run = L.mc_run(1000, 0, 0, 0, 4, 1e-4, 10.0, 0)
+    n_src = 1
+    if bad == "nx":
+        m.nx = 0
+    elif bad == "harm":
+        run.n_harm = L.MC_NHARM_MAX + 1
+    elif bad == "packets":
+        run.n_packets = 0
+    elif bad == "power":
+        src[0].power = 0.0
+    elif bad == "outside":
+        src[0].x0 = 5.0
+    elif bad == "dir":
+        src[0].dir_x = 1.0
+    elif bad == "roulette":
+        run.roulette_m = 1.0
+    elif bad == "nsrc":
+        n_src = 9
+    assert lib.mc_workspace_bytes(C.byref(m), src, n_src, C.byref(run)) == 0
+    rc = lib.mc_forward(C.byref(m), src, n_src, C.byref(run), 0x2000, None, 0x3000, 1 << 30, None)
+    assert rc == L.MC_ERR_INVALID_ARG
+
+
+def test_map_source_must_be_alone_and_workspace_checked():
+    L, lib = _lib()
+    m = _medium(L)
+    a = L.mc_source()
+    a.kind, a.map_d = L.MC_SRC_MAP, 0x4000
+    srcs = (L.mc_source * 2)(a, _pencil(L))
+    run = L.mc_run(1000, 0, 0, 0, 4, 1e-4, 10.0, 0)
+    assert lib.mc_workspace_bytes(C.byref(m), srcs, 2, C.byref(run)) == 0
+    one = (L.mc_source * 1)(_pencil(L))
+    need = lib.mc_workspace_bytes(C.byref(m), one, 1, C.byref(run))
+    assert need > 0
+    rc = lib.mc_forward(C.byref(m), one, 1, C.byref(run), 0x2000, None, 0x3000, need - 1, None)
+    assert rc == L.MC_ERR_WORKSPACE
+    rc = lib.mc_forward(C.byref(m), one, 1, C.byref(run), 0x2000, None, 0x3001, need + 256, None)
+    assert rc == L.MC_ERR_WORKSPACE
+
+
+def test_workspace_grows_with_grid_and_harmonics():
+    L, lib = _lib()
+    one = (L.mc_source * 1)(_pencil(L))
+    small = lib.mc_workspace_bytes(C.byref(_medium(L, 4, 4)), one, 1, C.byref(L.mc_run(10, 0, 0, 0, 2, 1e-4, 10.0, 0)))
+    big = lib.mc_workspace_bytes(C.byref(_medium(L, 256, 256, 0.1)), one, 1,
+                                 C.byref(L.mc_run(10, 0, 0, 0, 16, 1e-4, 10.0, 0)))
+    assert big > 65536 * 33 * 8 > small > 0
