@@ -186,6 +186,11 @@ static void record(or_sink *k, uint64_t pid, int kk, int type, int ix, int iz, d
 static void locate(const or_medium *m, double x, double z, double sx, double sz, int *ix, int *iz)
 {
     double fx = x / m->dx, fz = z / m->dx;
+    /* a point given on the outer boundary lies on it, whatever the rounding of x / dx */
+    if (fabs(fx) < 1e-9) fx = 0.0;
+    if (fabs(fz) < 1e-9) fz = 0.0;
+    if (fabs(fx - m->nx) < 1e-9 * m->nx) fx = m->nx;
+    if (fabs(fz - m->nz) < 1e-9 * m->nz) fz = m->nz;
     int i = (int)floor(fx), j = (int)floor(fz);
     if (fx == (double)i && sx < 0) i -= 1;
     if (fz == (double)j && sz < 0) j -= 1;

@@ -474,3 +474,21 @@ def test_gradient_chain_matches_finite_differences(oracle_lib):
     g, se = batch_mean_se((Gs * v).sum(axis=(1, 2)))
     assert g > 0 and fm > 0
     assert abs(g - fm) < 4 * np.hypot(se, fse) + 5e-3 * abs(fm), (g, fm, se, fse)
+
+
+def test_side_sources_deliver_equal_power(oracle_lib):
+    """Four collimated line sources, one per side of a homogeneous square whose side
+    (96 x 0.1 mm) is not exactly representable: by the square's symmetry each side
+    delivers the same absorbed power.  Guards the rule that a source on the outer
+    boundary, pointing inward, starts inside the domain."""
+    O = oracle_lib
+    ph = P.homogeneous(96, 96, 0.1, 0.05, 4.0, 0.8)
+    med = O.medium_from(ph)
+    specs = P.four_side_lines(ph)
+    vals = []
+    for s in specs:
+        _, L = O.run_mc(med, O.sources_from([s]), O.Run(4000, 0, 0), n_threads=8)
+        vals.append(L.absorbed / L.launched)
+    vals = np.array(vals)
+    assert np.all(vals > 0.05)
+    assert vals.max() - vals.min() < 0.1 * vals.mean(), vals
