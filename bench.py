@@ -157,7 +157,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": "disc256: 256x256 pixels of 0.1 mm, 3-6 seeded disc inclusions, 4 line sources, "
                                "forward + adjoint + gradient",
-                   "packets_forward": Np, "packets_adjoint": Np, "n_harm": N, "tally": "fp32 chunks -> fp64"},
+                   "packets_forward": Np, "packets_adjoint": Np, "n_harm": N, "tally": "fp64 LDS tiles, packet migration"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_transport", "avg_launch_ms": avg_launch_ms, "launches": tr_launches,

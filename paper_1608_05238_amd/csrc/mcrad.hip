@@ -29,6 +29,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <algorithm>
 #include <mutex>
@@ -40,11 +41,15 @@ namespace {
 
 constexpr int kMaxSrc = 8;
 constexpr int kMaxProf = 2 * (2 * MC_NHARM_MAX + 1);  // profile coefficients over all sources
-constexpr int kBlock = 256;                            // global mode: threads per workgroup (4 waves)
-constexpr int kWaves = kBlock / 64;
-constexpr int kBlockLds = 512;                         // LDS mode: threads sharing one LDS tally copy
-constexpr uint64_t kChunk = 1ull << 22;                // packets per launch
-constexpr size_t kLdsTallyMax = 144 * 1024;            // LDS bytes for the in-LDS tally mode
+// whole-grid mode: 12 waves share one LDS tally (8 for high orders, whose
+// harmonic vectors need more registers)
+constexpr int grid_block(int nh) { return nh <= 16 ? 768 : 512; }
+constexpr int kBlockTile = 384;                        // tiled mode: 6 waves per workgroup, 2 workgroups per CU
+constexpr uint64_t kChunk = 1ull << 22;                // whole-grid mode: packets per launch
+constexpr size_t kLdsGridMax = 144 * 1024;             // whole-grid mode: FP64 tally bytes in LDS
+constexpr size_t kLdsTileMax = 72 * 1024;              // tiled mode: tile tally + medium bytes (2 WGs/CU)
+constexpr uint32_t kInvalidTile = 0xFFFFFFFFu;
+constexpr uint32_t kSlice = 256;                       // queue slots a wave reserves at a time
 constexpr float kPi = 3.14159265358979323846f;
 constexpr uint32_t kMaxInteractions = 1u << 24;         // hard cap per packet (guards invalid media)
 
@@ -69,8 +74,16 @@ struct Params {
     const float *g;
     const double *map;          // MAP source values (sign)
     const double *cdf;          // MAP: inclusive prefix of |map|
-    float *t32;                 // global mode FP32 tally [npix][K]
     double *t64;                // FP64 tally [npix][K]
+    // tiled mode: packets migrate between square tiles whose tallies live in LDS
+    int tw, th, ntx, ntiles;
+    struct PacketRec *qa;       // unsorted records (appended by launches and leavers)
+    struct PacketRec *qb;       // records sorted by tile
+    uint32_t *qcnt;             // [0] raw records in qa, [1] records to scatter, [2] jobs, [3] job cursor,
+                                // [4] overflow flag
+    uint32_t *tile_count, *tile_cursor;
+    uint4 *jobs;                // (tile, first record in qb, count, 0)
+    uint32_t cap_a, cap_b, job_size, max_visits, tail_visits;
     unsigned long long *counter;
     double *led;                // 5 doubles
     unsigned long long *ledc;   // 4 counters
@@ -117,6 +130,19 @@ struct Packet {
     bool alive;
 };
 
+// A packet between two stays in tiles (64 bytes, four 16-byte words).
+struct alignas(16) PacketRec {
+    float fx, fz, sx, sz;
+    float w, w0abs, tau, uh;
+    float ur;
+    uint32_t k;
+    int32_t ix, iz;
+    uint64_t pid;
+    uint32_t tile;
+    uint32_t spare;
+};
+static_assert(sizeof(PacketRec) == 64, "packet record layout");
+
 struct LedgerRegs {
     double launched = 0, absorbed = 0, escaped = 0, gain = 0, loss = 0;
     uint32_t packets = 0, segments = 0, visits = 0, scatters = 0;
@@ -156,8 +182,9 @@ __device__ __forceinline__ float profile(const Params &P, const SrcDev &s, float
 __device__ __forceinline__ void set_dir(Packet &p, float sx, float sz) {
     p.sx = sx;
     p.sz = sz;
-    p.isx = sx != 0.f ? 1.f / sx : INFINITY;
-    p.isz = sz != 0.f ? 1.f / sz : INFINITY;
+    // hardware reciprocal (1 ulp): enough for distances to pixel faces
+    p.isx = sx != 0.f ? __builtin_amdgcn_rcpf(sx) : INFINITY;
+    p.isz = sz != 0.f ? __builtin_amdgcn_rcpf(sz) : INFINITY;
 }
 
 // Draw block k: free path (optical depth) and the uniforms used at its end.
@@ -189,8 +216,7 @@ __device__ __forceinline__ void locate1(double a, int n, float s, int &i, float 
 
 // Launch (Sec. 3; Sec. 6 for the volumetric signed source).  Returns false
 // if the packet starts outside the grid (it then escapes at once).
-template <int NH>
-__device__ bool launch(const Params &P, uint64_t pid, Packet &p, float *h, LedgerRegs &L) {
+__device__ bool launch_state(const Params &P, uint64_t pid, Packet &p, LedgerRegs &L) {
     const uint4 r = rng_block(P, pid, 0);
     const float u0 = u01(r.x), u1 = u01(r.y), u2 = u01(r.z), u3 = u01(r.w);
     int s = 0;
@@ -247,8 +273,14 @@ __device__ bool launch(const Params &P, uint64_t pid, Packet &p, float *h, Ledge
         return false;
     }
     p.alive = true;
-    harmonics<NH>(sx, sz, h);
     new_leg(P, p);
+    return true;
+}
+
+template <int NH>
+__device__ bool launch(const Params &P, uint64_t pid, Packet &p, float *h, LedgerRegs &L) {
+    if (!launch_state(P, pid, p, L)) return false;
+    harmonics<NH>(p.sx, p.sz, h);
     return true;
 }
 
@@ -256,10 +288,7 @@ __device__ bool launch(const Params &P, uint64_t pid, Packet &p, float *h, Ledge
 // depositing the track length weighted by the decaying weight (Sec. 3).
 // Returns EV_CROSS, EV_ESCAPE or EV_SCATTER; T (pixel units) and the pixel
 // of the segment are returned through the references.
-__device__ __forceinline__ int step(const Params &P, Packet &p, float &T, float &dw, int &pix) {
-    pix = p.iz * P.nx + p.ix;
-    const float4 m = P.med[pix];
-    const float dfx = p.sx > 0.f ? (1.f - p.fx) * p.isx : (p.sx < 0.f ? -p.fx * p.isx : INFINITY);
+__device__ __forceinline__ int step(const Params &P, Packet &p, const float4 m, float &T, float &dw) {    const float dfx = p.sx > 0.f ? (1.f - p.fx) * p.isx : (p.sx < 0.f ? -p.fx * p.isx : INFINITY);
     const float dfz = p.sz > 0.f ? (1.f - p.fz) * p.isz : (p.sz < 0.f ? -p.fz * p.isz : INFINITY);
     const float d = fminf(dfx, dfz);
     const float od = m.y * d;
@@ -293,8 +322,7 @@ __device__ __forceinline__ int step(const Params &P, Packet &p, float &T, float 
 // a = (1+g) cos(pi(u-1/2)), b = (1-g) sin(pi(u-1/2)), tan(dt/2) = b/a, so
 // cos dt = (a^2-b^2)/(a^2+b^2), sin dt = 2ab/(a^2+b^2).  Returns false if
 // the packet was killed.
-template <int NH>
-__device__ __forceinline__ bool scatter(const Params &P, Packet &p, float *h, LedgerRegs &L) {
+__device__ __forceinline__ bool scatter_dir(const Params &P, Packet &p, const float g, LedgerRegs &L) {
     if (p.k >= kMaxInteractions) {
         L.loss += p.w;
         p.alive = false;
@@ -309,11 +337,10 @@ __device__ __forceinline__ bool scatter(const Params &P, Packet &p, float *h, Le
         L.gain += (double)((P.rm - 1.f) * p.w);
         p.w *= P.rm;
     }
-    const float g = P.g[p.iz * P.nx + p.ix];
     float sp, cp;
     sincospif(p.uh - 0.5f, &sp, &cp);
     const float a = (1.f + g) * cp, b = (1.f - g) * sp;
-    const float inv = 1.f / (a * a + b * b);
+    const float inv = __builtin_amdgcn_rcpf(a * a + b * b);
     const float cd = (a * a - b * b) * inv, sd = 2.f * a * b * inv;
     float nx_ = p.sx * cd + p.sz * sd;
     float nz_ = p.sz * cd - p.sx * sd;
@@ -321,11 +348,36 @@ __device__ __forceinline__ bool scatter(const Params &P, Packet &p, float *h, Le
     nx_ *= rn;
     nz_ *= rn;
     set_dir(p, nx_, nz_);
-    harmonics<NH>(nx_, nz_, h);
     L.scatters += 1;
     p.k += 1;
     new_leg(P, p);
     return true;
+}
+
+template <int NH>
+__device__ __forceinline__ bool scatter(const Params &P, Packet &p, const float g, float *h, LedgerRegs &L) {
+    if (!scatter_dir(P, p, g, L)) return false;
+    harmonics<NH>(p.sx, p.sz, h);
+    return true;
+}
+
+// Recompute the harmonic vector of the lanes whose direction changed.  One
+// call site per loop keeps h in place (a select per channel instead of
+// register copies at control-flow joins).
+template <int NH>
+__device__ __forceinline__ void refresh_harmonics(bool dirty, const Packet &p, float *h) {
+    if (!__ballot(dirty)) return;
+    h[0] = 1.f;
+    float re = p.sz, im = p.sx;
+#pragma unroll
+    for (int n = 1; n <= NH; ++n) {
+        h[n] = dirty ? re : h[n];
+        h[NH + n] = dirty ? im : h[NH + n];
+        const float nre = re * p.sz - im * p.sx;
+        const float nim = re * p.sx + im * p.sz;
+        re = nre;
+        im = nim;
+    }
 }
 
 __device__ __forceinline__ void ledger_flush(const Params &P, LedgerRegs &L) {
@@ -344,34 +396,32 @@ __device__ __forceinline__ void ledger_flush(const Params &P, LedgerRegs &L) {
     }
 }
 
-// ------------------------------------------------------------------ transport kernel
-// LDS_TALLY: the FP32 tally [npix][K] lives in LDS for the workgroup's life.
-// Otherwise flushes go to the FP32 HBM tally through per-wave LDS staging.
-template <int NH, bool LDS_TALLY>
-__global__ void __launch_bounds__(LDS_TALLY ? kBlockLds : kBlock) k_transport(Params P) {
+// ------------------------------------------------------------------ whole-grid transport
+// Small grids: the whole FP64 tally [npix][K] lives in LDS for the
+// workgroup's life (LDS FP64 atomics), flushed to the HBM FP64 tally with
+// coalesced atomics at the end.  Persistent waves refill dead lanes from a
+// global packet counter with one wave-aggregated atomic.
+template <int NH>
+__global__ void __launch_bounds__(grid_block(NH)) k_transport_grid(Params P) {
     constexpr int K = 2 * NH + 1;
-    extern __shared__ float smem[];
+    extern __shared__ double tally[];
     const int lane = __lane_id();
-    const int wave = threadIdx.x >> 6;
-    float *stage = smem + wave * 64 * K;                              // global mode
-    int *stage_pix = reinterpret_cast<int *>(smem + kWaves * 64 * K) + wave * 64;
-
-    if (LDS_TALLY) {
-        for (int i = threadIdx.x; i < P.npix * K; i += blockDim.x) smem[i] = 0.f;
-        __syncthreads();
-    }
+    for (int i = threadIdx.x; i < P.npix * K; i += blockDim.x) tally[i] = 0.0;
+    __syncthreads();
 
     Packet p;
     p.alive = false;
     float h[K], acc[K];
 #pragma unroll
-    for (int j = 0; j < K; ++j) acc[j] = 0.f;
+    for (int j = 0; j < K; ++j) {
+        h[j] = 0.f;
+        acc[j] = 0.f;
+    }
     LedgerRegs L;
-    bool more = true;
+    bool more = true, dirty = false;
     const unsigned long long lt_mask = (1ull << lane) - 1ull;
 
     for (;;) {
-        // refill dead lanes with one wave-aggregated atomic on the packet counter
         if (more) {
             const unsigned long long dead = __ballot(!p.alive);
             if (dead) {
@@ -383,81 +433,421 @@ __global__ void __launch_bounds__(LDS_TALLY ? kBlockLds : kBlock) k_transport(Pa
                 if (base + ndead >= P.npk) more = false;
                 if (!p.alive) {
                     const unsigned long long my = base + __popcll(dead & lt_mask);
-                    if (my < P.npk) launch<NH>(P, P.pid0 + my, p, h, L);
+                    if (my < P.npk && launch_state(P, P.pid0 + my, p, L)) dirty = true;
                 }
             }
         }
         if (!__ballot(p.alive)) {
             if (!more) break;
-            continue;
         }
-        bool flush = false;
-        int pix = 0;
+        refresh_harmonics<NH>(dirty, p, h);
+        dirty = false;
+        int ev = EV_NONE, pix = 0;
+        float T = 0.f, dw = 0.f;
         if (p.alive) {
-            float T, dw;
-            const int ev = step(P, p, T, dw, pix);
-#pragma unroll
-            for (int j = 0; j < K; ++j) acc[j] = fmaf(T, h[j], acc[j]);
+            pix = p.iz * P.nx + p.ix;
+            ev = step(P, p, P.med[pix], T, dw);
             L.absorbed += (double)dw;
             L.segments += 1;
+        }
+#pragma unroll
+        for (int j = 0; j < K; ++j) acc[j] = fmaf(T, h[j], acc[j]);
+        bool flush = false;
+        if (ev == EV_SCATTER) {
+            if (scatter_dir(P, p, P.g[pix], L)) dirty = true;
+            else flush = true;
+        } else if (ev != EV_NONE) {
+            flush = true;
+            if (ev == EV_ESCAPE) {
+                L.escaped += p.w;
+                p.alive = false;
+            }
+        }
+        if (flush) {
+            L.visits += 1;
+            double *t = tally + pix * K;
+#pragma unroll
+            for (int j = 0; j < K; ++j) atomicAdd(t + j, (double)acc[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < K; ++j) acc[j] = flush ? 0.f : acc[j];
+    }
+    ledger_flush(P, L);
+    __syncthreads();
+    for (int i = threadIdx.x; i < P.npix * K; i += blockDim.x) {
+        const double v = tally[i];
+        if (v != 0.0) unsafeAtomicAdd(P.t64 + i, v);
+    }
+}
+
+// ------------------------------------------------------------------ tiled transport
+// Larger grids: the grid is cut into tw x th tiles whose FP64 tallies fit in
+// LDS.  A run proceeds in generations.  Each generation, the live packets
+// (sorted by tile) are split into jobs of at most job_size packets of one
+// tile; a workgroup takes a job, keeps that tile's tally and medium in LDS,
+// and moves each packet until it leaves the tile, dies, or has made
+// max_visits visits there.  Packets that leave (or pause) are written back as
+// records and sorted by tile for the next generation; new packets are
+// launched to keep the population up.  Every tally update is an LDS atomic;
+// HBM sees one coalesced flush of the tile per job.
+
+__device__ __forceinline__ uint32_t tile_of(const Params &P, int ix, int iz) {
+    return (uint32_t)((iz / P.th) * P.ntx + ix / P.tw);
+}
+
+__device__ __forceinline__ void rec_store(PacketRec *r, const Packet &p, uint32_t tile, uint32_t nvis) {
+    float4 *q = reinterpret_cast<float4 *>(r);
+    q[0] = make_float4(p.fx, p.fz, p.sx, p.sz);
+    q[1] = make_float4(p.w, p.w0abs, p.tau, p.uh);
+    uint4 *u = reinterpret_cast<uint4 *>(r);
+    u[2] = make_uint4(__float_as_uint(p.ur), p.k, (uint32_t)p.ix, (uint32_t)p.iz);
+    u[3] = make_uint4((uint32_t)p.pid, (uint32_t)(p.pid >> 32), tile, nvis);
+}
+
+__device__ __forceinline__ void rec_decode(const uint4 a, const uint4 b, const uint4 c, const uint4 d, Packet &p) {
+    p.fx = __uint_as_float(a.x);
+    p.fz = __uint_as_float(a.y);
+    set_dir(p, __uint_as_float(a.z), __uint_as_float(a.w));
+    p.w = __uint_as_float(b.x);
+    p.w0abs = __uint_as_float(b.y);
+    p.tau = __uint_as_float(b.z);
+    p.uh = __uint_as_float(b.w);
+    p.ur = __uint_as_float(c.x);
+    p.k = c.y;
+    p.ix = (int)c.z;
+    p.iz = (int)c.w;
+    p.pid = (uint64_t)d.x | ((uint64_t)d.y << 32);
+    p.alive = true;
+}
+
+__device__ __forceinline__ uint32_t rec_load(const PacketRec *r, Packet &p) {
+    const float4 *q = reinterpret_cast<const float4 *>(r);
+    const float4 a = q[0], b = q[1];
+    const uint4 *u = reinterpret_cast<const uint4 *>(r);
+    const uint4 c = u[2], d = u[3];
+    p.fx = a.x; p.fz = a.y;
+    set_dir(p, a.z, a.w);
+    p.w = b.x; p.w0abs = b.y; p.tau = b.z; p.uh = b.w;
+    p.ur = __uint_as_float(c.x);
+    p.k = c.y;
+    p.ix = (int)c.z;
+    p.iz = (int)c.w;
+    p.pid = (uint64_t)d.x | ((uint64_t)d.y << 32);
+    p.alive = true;
+    return d.w;
+}
+
+// Wave-private slices of the unsorted queue: a wave reserves kSlice slots
+// with one atomic on the queue counter (shared by every wave of the device,
+// so it is touched rarely) and fills them; unused slots are marked invalid.
+struct QueueSlice {
+    uint32_t base = 0, used = kSlice;
+    bool valid = false;
+};
+
+__device__ __forceinline__ void slice_close(const Params &P, QueueSlice &q) {
+    if (!q.valid) return;
+    const int lane = __lane_id();
+    for (uint32_t i = q.used + lane; i < kSlice; i += 64)
+        if (q.base + i < P.cap_a) P.qa[q.base + i].tile = kInvalidTile;
+}
+
+// Appends the packet of every lane with `put` set to the unsorted queue.
+__device__ __forceinline__ void slice_put(const Params &P, QueueSlice &q, bool put, const Packet &p, uint32_t tile,
+                                          uint32_t nvis) {
+    const unsigned long long m = __ballot(put);
+    if (!m) return;
+    const int n = __popcll(m);
+    const int lane = __lane_id();
+    if (q.used + n > kSlice) {
+        slice_close(P, q);
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(P.qcnt, kSlice);
+        q.base = __shfl(base, 0);
+        q.used = 0;
+        q.valid = true;
+    }
+    if (put) {
+        const uint32_t pos = q.base + q.used + __popcll(m & ((1ull << lane) - 1ull));
+        if (pos < P.cap_a) rec_store(P.qa + pos, p, tile, nvis);
+        else atomicOr(P.qcnt + 4, 1u);   // overflow: reported to the host, never written
+    }
+    q.used += n;
+}
+
+// Launch n_new packets (ids pid_base..) and append those inside the grid.
+__global__ void __launch_bounds__(256) k_tile_launch(Params P, uint64_t pid_base, uint32_t n_new) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    LedgerRegs L;
+    Packet p;
+    p.alive = false;
+    if (i < n_new) launch_state(P, pid_base + i, p, L);
+    // exact reservation per wave (one atomic per wave of new packets)
+    const unsigned long long m = __ballot(p.alive);
+    if (m) {
+        const int lane = __lane_id();
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(P.qcnt, (uint32_t)__popcll(m));
+        base = __shfl(base, 0);
+        if (p.alive) {
+            const uint32_t pos = base + __popcll(m & ((1ull << lane) - 1ull));
+            if (pos < P.cap_a) rec_store(P.qa + pos, p, tile_of(P, p.ix, p.iz), 0u);
+            else atomicOr(P.qcnt + 4, 1u);
+        }
+    }
+    if (__ballot(i < n_new)) ledger_flush(P, L);
+}
+
+// Counting sort of the unsorted queue by tile: counts.
+__global__ void __launch_bounds__(256) k_bin_count(Params P) {
+    const uint32_t n = P.qcnt[0] < P.cap_a ? P.qcnt[0] : P.cap_a;
+    const int lane = __lane_id();
+    for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+        const uint32_t i = base + threadIdx.x;
+        uint32_t t = i < n ? P.qa[i].tile : kInvalidTile;
+        bool pend = t != kInvalidTile;
+        for (;;) {
+            const unsigned long long m = __ballot(pend);
+            if (!m) break;
+            const int leader = __ffsll((long long)m) - 1;
+            const uint32_t t0 = __shfl(t, leader);
+            const unsigned long long same = __ballot(pend && t == t0);
+            if (lane == leader) atomicAdd(P.tile_count + t0, (uint32_t)__popcll(same));
+            if (pend && t == t0) pend = false;
+        }
+    }
+}
+
+// Single block: exclusive scan of the tile counts, job list, counters for the
+// next phase.  Tile counts are reset for the next generation.
+__global__ void __launch_bounds__(1024) k_bin_scan(Params P) {
+    __shared__ uint32_t s_rec[1024], s_job[1024];
+    const int t = threadIdx.x;
+    const int per = (P.ntiles + 1023) / 1024;
+    const int a = t * per, b = min(P.ntiles, a + per);
+    uint32_t nrec = 0, njob = 0;
+    for (int i = a; i < b; ++i) {
+        const uint32_t c = P.tile_count[i];
+        nrec += c;
+        njob += (c + P.job_size - 1) / P.job_size;
+    }
+    s_rec[t] = nrec;
+    s_job[t] = njob;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {   // inclusive Hillis-Steele scan
+        const uint32_t vr = t >= off ? s_rec[t - off] : 0u, vj = t >= off ? s_job[t - off] : 0u;
+        __syncthreads();
+        s_rec[t] += vr;
+        s_job[t] += vj;
+        __syncthreads();
+    }
+    const bool fits = s_rec[1023] <= P.cap_b;   // holds by construction; checked so nothing is written past it
+    uint32_t roff = s_rec[t] - nrec, joff = s_job[t] - njob;
+    for (int i = a; i < b; ++i) {
+        const uint32_t c = P.tile_count[i];
+        P.tile_cursor[i] = roff;
+        if (fits)
+            for (uint32_t s0 = 0; s0 < c; s0 += P.job_size)
+                P.jobs[joff++] = make_uint4((uint32_t)i, roff + s0, min(P.job_size, c - s0), 0u);
+        roff += c;
+        P.tile_count[i] = 0;
+    }
+    __syncthreads();
+    if (t == 1023) {
+        P.qcnt[1] = P.qcnt[0] < P.cap_a ? P.qcnt[0] : P.cap_a;
+        P.qcnt[0] = 0;
+        P.qcnt[2] = fits ? s_job[1023] : 0u;
+        P.qcnt[3] = 0;
+        if (!fits) P.qcnt[4] = 1u;
+    }
+}
+
+// Counting sort: scatter records to their tile's range of the sorted queue.
+__global__ void __launch_bounds__(256) k_bin_scatter(Params P) {
+    const uint32_t n = P.qcnt[1];
+    const int lane = __lane_id();
+    for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+        const uint32_t i = base + threadIdx.x;
+        uint32_t t = i < n ? P.qa[i].tile : kInvalidTile;
+        bool pend = t != kInvalidTile;
+        uint32_t pos = 0;
+        for (;;) {
+            const unsigned long long m = __ballot(pend);
+            if (!m) break;
+            const int leader = __ffsll((long long)m) - 1;
+            const uint32_t t0 = __shfl(t, leader);
+            const unsigned long long same = __ballot(pend && t == t0);
+            uint32_t b0 = 0;
+            if (lane == leader) b0 = atomicAdd(P.tile_cursor + t0, (uint32_t)__popcll(same));
+            b0 = __shfl(b0, leader);
+            if (pend && t == t0) {
+                pos = b0 + __popcll(same & ((1ull << lane) - 1ull));
+                pend = false;
+            }
+        }
+        if (t != kInvalidTile && pos < P.cap_b) {
+            const uint4 *src = reinterpret_cast<const uint4 *>(P.qa + i);
+            uint4 *dst = reinterpret_cast<uint4 *>(P.qb + pos);
+            dst[0] = src[0];
+            dst[1] = src[1];
+            dst[2] = src[2];
+            dst[3] = src[3];
+        }
+    }
+}
+
+template <int NH>
+__global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu(NH <= 16 ? 3 : 2))) k_transport_tile(Params P) {
+    constexpr int K = 2 * NH + 1;
+    extern __shared__ double tally[];                  // [tw*th][K]
+    float4 *smed = reinterpret_cast<float4 *>(tally + (((size_t)P.tw * P.th * K + 1) & ~size_t(1)));
+    float *sg = reinterpret_cast<float *>(smed + P.tw * P.th);
+    __shared__ uint32_t s_job[4];
+    __shared__ uint32_t s_next;
+    const int lane = __lane_id();
+    const int ntp = P.tw * P.th;
+    const unsigned long long lt_mask = (1ull << lane) - 1ull;
+    LedgerRegs L;
+    QueueSlice q;
+
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const uint32_t j = atomicAdd(P.qcnt + 3, 1u);
+            const bool ok = j < P.qcnt[2];
+            const uint4 jb = ok ? P.jobs[j] : make_uint4(0u, 0u, 0u, 0u);
+            s_job[0] = ok ? 1u : 0u;
+            s_job[1] = jb.x;
+            s_job[2] = jb.y;
+            s_job[3] = jb.z;
+            s_next = 0;
+        }
+        __syncthreads();
+        if (!s_job[0]) break;
+        const uint32_t tile = s_job[1], first = s_job[2], cnt = s_job[3];
+        const int tx0 = (int)(tile % P.ntx) * P.tw, tz0 = (int)(tile / P.ntx) * P.th;
+        for (int i = threadIdx.x; i < ntp * K; i += blockDim.x) tally[i] = 0.0;
+        for (int i = threadIdx.x; i < ntp; i += blockDim.x) {
+            const int gx = tx0 + i % P.tw, gz = tz0 + i / P.tw;
+            const bool in = gx < P.nx && gz < P.nz;
+            smed[i] = in ? P.med[gz * P.nx + gx] : make_float4(0.f, 0.f, 0.f, 0.f);
+            sg[i] = in ? P.g[gz * P.nx + gx] : 0.f;
+        }
+        __syncthreads();
+
+        Packet p;
+        p.alive = false;
+        uint32_t nvis = 0;
+        float h[K], acc[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            h[j] = 0.f;
+            acc[j] = 0.f;
+        }
+        // Each lane holds the record of its next packet in registers, loaded
+        // one whole stay ahead, so a refill never waits for memory.
+        bool more = true, dirty = false, has_next = false;
+        uint32_t tail_nvis = 0;   // visits of the current stay when the job ran out of packets
+        uint4 nr0 = make_uint4(0u, 0u, 0u, 0u), nr1 = nr0, nr2 = nr0, nr3 = nr0;
+        for (;;) {
+            if (more || __ballot(has_next)) {
+                if (!p.alive && has_next) {
+                    rec_decode(nr0, nr1, nr2, nr3, p);
+                    has_next = false;
+                    nvis = 0;
+                    tail_nvis = 0;
+                    dirty = true;
+                }
+                const unsigned long long want = more ? __ballot(!has_next) : 0ull;
+                if (want) {
+                    const int nw = __popcll(want);
+                    const int leader = __ffsll((long long)want) - 1;
+                    uint32_t base = 0;
+                    if (lane == leader) base = atomicAdd(&s_next, (uint32_t)nw);
+                    base = __shfl(base, leader);
+                    if (base + nw >= cnt) {
+                        more = false;
+                        tail_nvis = nvis;
+                    }
+                    if (!has_next) {
+                        const uint32_t my = base + __popcll(want & lt_mask);
+                        if (my < cnt) {
+                            const uint4 *r = reinterpret_cast<const uint4 *>(P.qb + first + my);
+                            nr0 = r[0];
+                            nr1 = r[1];
+                            nr2 = r[2];
+                            nr3 = r[3];
+                            has_next = true;
+                        }
+                    }
+                }
+                if (!p.alive && has_next) {   // no packet at all yet: take the one just loaded
+                    rec_decode(nr0, nr1, nr2, nr3, p);
+                    has_next = false;
+                    nvis = 0;
+                    tail_nvis = 0;
+                    dirty = true;
+                }
+            }
+            if (!__ballot(p.alive)) {
+                if (!more && !__ballot(has_next)) break;
+            }
+            refresh_harmonics<NH>(dirty, p, h);
+            dirty = false;
+            int ev = EV_NONE, lp = 0;
+            float T = 0.f, dw = 0.f;
+            if (p.alive) {
+                lp = (p.iz - tz0) * P.tw + (p.ix - tx0);
+                ev = step(P, p, smed[lp], T, dw);
+                L.absorbed += (double)dw;
+                L.segments += 1;
+            }
+#pragma unroll
+            for (int j = 0; j < K; ++j) acc[j] = fmaf(T, h[j], acc[j]);
+            bool flush = false;
             if (ev == EV_SCATTER) {
-                if (!scatter<NH>(P, p, h, L)) flush = true;
-            } else {
+                if (scatter_dir(P, p, sg[lp], L)) dirty = true;
+                else flush = true;
+            } else if (ev != EV_NONE) {
                 flush = true;
                 if (ev == EV_ESCAPE) {
                     L.escaped += p.w;
                     p.alive = false;
                 }
             }
-            if (flush) L.visits += 1;
-        }
-        if (LDS_TALLY) {
+            bool leave = false;
             if (flush) {
-                float *t = smem + pix * K;
+                L.visits += 1;
+                nvis += 1;
+                double *t = tally + lp * K;
 #pragma unroll
-                for (int j = 0; j < K; ++j) {
-                    atomicAdd(t + j, acc[j]);
-                    acc[j] = 0.f;
+                for (int j = 0; j < K; ++j) atomicAdd(t + j, (double)acc[j]);
+                if (ev == EV_CROSS) {
+                    const bool out = p.ix < tx0 || p.ix >= tx0 + P.tw || p.iz < tz0 || p.iz >= tz0 + P.th;
+                    // once the job has no packets left to hand out, a packet pauses
+                    // after tail_visits more visits so the workgroup is not held by
+                    // its longest stay (it resumes next generation)
+                    leave = out || nvis >= (more ? P.max_visits : min(P.max_visits, tail_nvis + P.tail_visits));
                 }
             }
-        } else {
-            const unsigned long long fm = __ballot(flush);
-            if (fm) {
-                const int nf = __popcll(fm);
-                if (flush) {
-                    const int slot = __popcll(fm & lt_mask);
-                    float *st = stage + slot * K;
 #pragma unroll
-                    for (int j = 0; j < K; ++j) {
-                        st[j] = acc[j];
-                        acc[j] = 0.f;
-                    }
-                    stage_pix[slot] = pix;
-                }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                const int total = nf * K;
-                for (int e = lane; e < total; e += 64) {
-                    const int v = e / K;
-                    const int j = e - v * K;
-                    const float val = stage[e];
-                    if (val != 0.f) unsafeAtomicAdd(P.t32 + (size_t)stage_pix[v] * K + j, val);
-                }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (int j = 0; j < K; ++j) acc[j] = flush ? 0.f : acc[j];
+            slice_put(P, q, leave, p, leave ? tile_of(P, p.ix, p.iz) : 0u, 0u);
+            if (leave) {
+                p.alive = false;
+                nvis = 0;
             }
         }
-    }
-    ledger_flush(P, L);
-    if (LDS_TALLY) {
         __syncthreads();
-        for (int i = threadIdx.x; i < P.npix * K; i += blockDim.x) {
-            const float v = smem[i];
-            if (v != 0.f) unsafeAtomicAdd(P.t64 + i, (double)v);
+        for (int i = threadIdx.x; i < ntp * K; i += blockDim.x) {
+            const double v = tally[i];
+            const int lp = i / K, c = i - lp * K;
+            const int gx = tx0 + lp % P.tw, gz = tz0 + lp / P.tw;
+            if (v != 0.0 && gx < P.nx && gz < P.nz) unsafeAtomicAdd(P.t64 + (size_t)(gz * P.nx + gx) * K + c, v);
         }
+        __syncthreads();
     }
+    slice_close(P, q);
+    ledger_flush(P, L);
 }
 
 // ------------------------------------------------------------------ trace kernel
@@ -500,10 +890,10 @@ __global__ void k_trace(Params P, const uint64_t *pids, int n_pids, mc_event *ev
         while (p.alive) {
             const int ix = p.ix, iz = p.iz, k = (int)p.k;
             float T, dw;
-            int pix;
-            const int e = step(P, p, T, dw, pix);
+            const int pix = p.iz * P.nx + p.ix;
+            const int e = step(P, p, P.med[pix], T, dw);
             if (e == EV_SCATTER) {
-                if (scatter<NH>(P, p, h, L)) rec(p, EV_SCATTER, k, ix, iz, p.w, T);
+                if (scatter<NH>(P, p, P.g[pix], h, L)) rec(p, EV_SCATTER, k, ix, iz, p.w, T);
                 else rec(p, EV_KILL, k, ix, iz, p.w, T);
             } else if (e == EV_ESCAPE) {
                 p.alive = false;
@@ -553,16 +943,6 @@ __global__ void __launch_bounds__(1024) k_map_cdf(int n, const double *map, doub
     for (int i = a; i < b; ++i) {
         s += fabs(map[i]);
         cdf[i] = s;
-    }
-}
-
-__global__ void k_fold(size_t n, float *t32, double *t64) {
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const float v = t32[i];
-        if (v != 0.f) {
-            t64[i] += (double)v;
-            t32[i] = 0.f;
-        }
     }
 }
 
@@ -675,18 +1055,18 @@ using TraceFn = void (*)(Params, const uint64_t *, int, mc_event *, size_t, unsi
 
 template <int NH>
 struct Table {
-    static void fill(TransportFn *lds, TransportFn *glb, TraceFn *tr) {
-        lds[NH] = k_transport<NH, true>;
-        glb[NH] = k_transport<NH, false>;
+    static void fill(TransportFn *grid, TransportFn *tile, TraceFn *tr) {
+        grid[NH] = k_transport_grid<NH>;
+        tile[NH] = k_transport_tile<NH>;
         tr[NH] = k_trace<NH>;
-        if constexpr (NH > 0) Table<NH - 1>::fill(lds, glb, tr);
+        if constexpr (NH > 0) Table<NH - 1>::fill(grid, tile, tr);
     }
 };
 
 struct Kernels {
-    TransportFn lds[MC_NHARM_MAX + 1], glb[MC_NHARM_MAX + 1];
+    TransportFn grid[MC_NHARM_MAX + 1], tile[MC_NHARM_MAX + 1];
     TraceFn tr[MC_NHARM_MAX + 1];
-    Kernels() { Table<MC_NHARM_MAX>::fill(lds, glb, tr); }
+    Kernels() { Table<MC_NHARM_MAX>::fill(grid, tile, tr); }
 };
 
 const Kernels &kernels() {
@@ -711,22 +1091,58 @@ Profile &profile_state() {
     return p;
 }
 
+// Tiled-mode sizing.  Tiles are square, as large as lets two workgroups of a
+// CU hold their tile's FP64 tally and medium in LDS.
+constexpr uint64_t kLiveMax = 1ull << 22;     // live packets per generation
+constexpr uint32_t kJobSize = 2048;           // packets per job
+constexpr uint32_t kMaxVisitsPerStay = 256;   // a packet pauses after this many visits in one job
+constexpr int kTileWavesMax = 256 * 16;       // bound on resident waves of the tiled kernel
+
+// Tuning knobs of the tiled mode, overridable through the environment
+// (RMC_LIVE, RMC_JOB, RMC_MAXVIS, RMC_TAILVIS, RMC_TILE) for measurement sweeps.
+struct TileTuning {
+    uint64_t live = kLiveMax;
+    uint32_t job = kJobSize, maxvis = kMaxVisitsPerStay, tailvis = 1u << 30;
+    int tile = 0;   // 0: largest square tile for two workgroups per CU
+};
+const TileTuning &tile_tuning() {
+    static TileTuning t = [] {
+        TileTuning v;
+        auto get = [](const char *n, uint64_t lo, uint64_t hi, uint64_t def) {
+            const char *e = std::getenv(n);
+            if (!e) return def;
+            const unsigned long long x = std::strtoull(e, nullptr, 10);
+            return (x >= lo && x <= hi) ? (uint64_t)x : def;
+        };
+        v.live = get("RMC_LIVE", 1024, 1ull << 26, v.live);
+        v.job = (uint32_t)get("RMC_JOB", 64, 1u << 20, v.job);
+        v.maxvis = (uint32_t)get("RMC_MAXVIS", 1, 1u << 30, v.maxvis);
+        v.tailvis = (uint32_t)get("RMC_TAILVIS", 1, 1u << 30, v.tailvis);
+        v.tile = (int)get("RMC_TILE", 1, 256, 0);
+        return v;
+    }();
+    return t;
+}
+
 struct Layout {
-    size_t med, cdf, t64, t32, led, ledc, counters, total;
+    size_t med, cdf, t64, led, ledc, counters, qa, qb, tcount, tcursor, jobs, qcnt, total;
     uint64_t n_chunks;
-    bool lds_mode;
+    bool tiled;
+    int tw, th, ntx, ntz, ntiles;
+    uint64_t live, cap_a, max_jobs;
+    size_t tile_lds;
 };
 
-bool lds_fits(int npix, int K) {
-    return (size_t)npix * K * sizeof(float) <= kLdsTallyMax;
+size_t tile_lds_bytes(int tw, int th, int K) {
+    const size_t tal = ((size_t)tw * th * K * sizeof(double) + 15) & ~size_t(15);
+    return tal + (size_t)tw * th * (sizeof(float4) + sizeof(float));
 }
 
 Layout layout(const mc_medium *m, const mc_source *src, const mc_run *run) {
     Layout L{};
     const size_t npix = (size_t)m->nx * m->nz;
     const int K = 2 * run->n_harm + 1;
-    L.lds_mode = lds_fits((int)npix, K);
-    L.n_chunks = (run->n_packets + kChunk - 1) / kChunk;
+    L.tiled = npix * K * sizeof(double) > kLdsGridMax;
     size_t off = 0;
     L.med = off;
     off = align_up(off + npix * sizeof(float4));
@@ -734,14 +1150,43 @@ Layout layout(const mc_medium *m, const mc_source *src, const mc_run *run) {
     if (src[0].kind == MC_SRC_MAP) off = align_up(off + npix * sizeof(double));
     L.t64 = off;
     off = align_up(off + npix * K * sizeof(double));
-    L.t32 = off;
-    if (!L.lds_mode) off = align_up(off + npix * K * sizeof(float));
     L.led = off;
     off = align_up(off + 8 * sizeof(double));
     L.ledc = off;
     off = align_up(off + 8 * sizeof(unsigned long long));
-    L.counters = off;
-    off = align_up(off + L.n_chunks * sizeof(unsigned long long));
+    if (!L.tiled) {
+        L.n_chunks = (run->n_packets + kChunk - 1) / kChunk;
+        L.counters = off;
+        off = align_up(off + L.n_chunks * sizeof(unsigned long long));
+    } else {
+        int t = 1;
+        while (tile_lds_bytes(t + 1, t + 1, K) <= kLdsTileMax) ++t;
+        if (tile_tuning().tile && tile_lds_bytes(tile_tuning().tile, tile_tuning().tile, K) <= kLdsTileMax)
+            t = tile_tuning().tile;
+        L.tw = std::min(t, m->nx);
+        L.th = std::min(t, m->nz);
+        L.ntx = (m->nx + L.tw - 1) / L.tw;
+        L.ntz = (m->nz + L.th - 1) / L.th;
+        L.ntiles = L.ntx * L.ntz;
+        L.tile_lds = tile_lds_bytes(L.tw, L.th, K);
+        L.live = std::min<uint64_t>(run->n_packets, tile_tuning().live);
+        L.cap_a = 2 * L.live + (uint64_t)kSlice * kTileWavesMax + 64ull * 64;
+        L.max_jobs = L.ntiles + L.live / tile_tuning().job + 2;
+        L.counters = off;
+        off = align_up(off + 8 * sizeof(unsigned long long));
+        L.qcnt = off;
+        off = align_up(off + 8 * sizeof(uint32_t));
+        L.tcount = off;
+        off = align_up(off + L.ntiles * sizeof(uint32_t));
+        L.tcursor = off;
+        off = align_up(off + L.ntiles * sizeof(uint32_t));
+        L.jobs = off;
+        off = align_up(off + L.max_jobs * sizeof(uint4));
+        L.qa = off;
+        off = align_up(off + L.cap_a * sizeof(PacketRec));
+        L.qb = off;
+        off = align_up(off + L.live * sizeof(PacketRec));
+    }
     L.total = off;
     return L;
 }
@@ -859,59 +1304,44 @@ mc_status launch_zero(void *p, size_t bytes, hipStream_t st) {
     return hipGetLastError() == hipSuccess ? MC_OK : MC_ERR_DEVICE;
 }
 
-mc_status run_mc(const mc_medium *m, const mc_source *src, int n_src, const mc_run *run, double *coeffs,
-                 mc_ledger *ledger, void *ws, size_t ws_bytes, void *stream, int adjoint) {
-    mc_status st = validate(m, src, n_src, run);
-    if (st != MC_OK) return st;
-    if (!coeffs) return MC_ERR_INVALID_ARG;
-    const Layout L = layout(m, src, run);
-    if (!ws || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255)) return MC_ERR_WORKSPACE;
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    char *base = static_cast<char *>(ws);
-    const int npix = m->nx * m->nz;
-    const int N = run->n_harm, K = 2 * N + 1;
-
-    double map_abs_sum = 0;
-    const bool is_map = src[0].kind == MC_SRC_MAP;
-    Params P;
-    fill_params(P, m, src, n_src, run, adjoint, 0.0);
-    P.med = reinterpret_cast<const float4 *>(base + L.med);
-    P.t64 = reinterpret_cast<double *>(base + L.t64);
-    P.t32 = L.lds_mode ? nullptr : reinterpret_cast<float *>(base + L.t32);
-    P.led = reinterpret_cast<double *>(base + L.led);
-    P.ledc = reinterpret_cast<unsigned long long *>(base + L.ledc);
-
-    // zero the tallies, ledger and packet counters
-    if ((st = launch_zero(base + L.t64, L.counters + L.n_chunks * 8 - L.t64, s)) != MC_OK) return st;
-    hipLaunchKernelGGL(k_setup_medium, dim3((npix + 255) / 256), dim3(256), 0, s, npix, m->dx, m->mua_d, m->mus_d,
-                       reinterpret_cast<float4 *>(base + L.med));
-    if (is_map) {
-        double *cdf = reinterpret_cast<double *>(base + L.cdf);
-        hipLaunchKernelGGL(k_map_cdf, dim3(1), dim3(1024), 0, s, npix, src[0].map_d, cdf);
-        // the normalisation needs sum |q|: read the last CDF entry
-        if (hipMemcpyAsync(&map_abs_sum, cdf + npix - 1, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess)
-            return MC_ERR_DEVICE;
-        if (!(map_abs_sum > 0)) return MC_ERR_INVALID_ARG;
-        fill_params(P, m, src, n_src, run, adjoint, map_abs_sum);
-        P.med = reinterpret_cast<const float4 *>(base + L.med);
-        P.t64 = reinterpret_cast<double *>(base + L.t64);
-        P.t32 = L.lds_mode ? nullptr : reinterpret_cast<float *>(base + L.t32);
-        P.led = reinterpret_cast<double *>(base + L.led);
-        P.ledc = reinterpret_cast<unsigned long long *>(base + L.ledc);
-        P.cdf = cdf;
+// Record HIP events around a transport launch when timing is on.
+struct LaunchTimer {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    bool on = false;
+    mc_status begin(hipStream_t s) {
+        Profile &pr = profile_state();
+        {
+            std::lock_guard<std::mutex> g(pr.mu);
+            on = pr.on;
+        }
+        if (!on) return MC_OK;
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return MC_ERR_DEVICE;
+        return hipEventRecord(e0, s) == hipSuccess ? MC_OK : MC_ERR_DEVICE;
     }
-    if (hipGetLastError() != hipSuccess) return MC_ERR_DEVICE;
+    mc_status end(hipStream_t s) {
+        if (!on) return MC_OK;
+        if (hipEventRecord(e1, s) != hipSuccess) return MC_ERR_DEVICE;
+        Profile &pr = profile_state();
+        std::lock_guard<std::mutex> g(pr.mu);
+        pr.pending.emplace_back(e0, e1);
+        return MC_OK;
+    }
+};
 
-    const Kernels &KT = kernels();
-    const TransportFn fn = L.lds_mode ? KT.lds[N] : KT.glb[N];
-    const size_t lds = L.lds_mode ? (size_t)npix * K * sizeof(float)
-                                  : (size_t)kWaves * 64 * K * sizeof(float) + kWaves * 64 * sizeof(int);
-    const int block = L.lds_mode ? kBlockLds : kBlock;
-    if (L.lds_mode && lds > 64 * 1024 &&
-        hipFuncSetAttribute(reinterpret_cast<const void *>(fn), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
-            hipSuccess)
-        return MC_ERR_DEVICE;
+mc_status set_lds_limit(const void *fn, size_t lds) {
+    if (lds <= 64 * 1024) return MC_OK;
+    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess ? MC_OK
+                                                                                                    : MC_ERR_DEVICE;
+}
+
+// Whole-grid mode: persistent launches over chunks of packets.
+mc_status run_grid(Params &P, const Layout &L, const mc_run *run, char *base, hipStream_t s) {
+    const int N = run->n_harm, K = 2 * N + 1;
+    const TransportFn fn = kernels().grid[N];
+    const size_t lds = (size_t)P.npix * K * sizeof(double);
+    mc_status st = set_lds_limit(reinterpret_cast<const void *>(fn), lds);
+    if (st != MC_OK) return st;
+    const int block = grid_block(N);
     const int occ = occupancy_blocks(fn, block, lds);
     const int cus = device_cus();
     for (uint64_t c = 0; c < L.n_chunks; ++c) {
@@ -922,30 +1352,111 @@ mc_status run_mc(const mc_medium *m, const mc_source *src, int n_src, const mc_r
         P.counter = reinterpret_cast<unsigned long long *>(base + L.counters) + c;
         const uint64_t want = (n + block - 1) / block;
         const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)cus * occ));
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        Profile &pr = profile_state();
-        bool timed = false;
-        {
-            std::lock_guard<std::mutex> g(pr.mu);
-            timed = pr.on;
-        }
-        if (timed) {
-            if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return MC_ERR_DEVICE;
-            if (hipEventRecord(e0, s) != hipSuccess) return MC_ERR_DEVICE;
-        }
+        LaunchTimer tm;
+        if ((st = tm.begin(s)) != MC_OK) return st;
         hipLaunchKernelGGL(fn, dim3(grid), dim3(block), lds, s, P);
-        if (timed) {
-            if (hipEventRecord(e1, s) != hipSuccess) return MC_ERR_DEVICE;
-            std::lock_guard<std::mutex> g(pr.mu);
-            pr.pending.emplace_back(e0, e1);
-        }
-        if (!L.lds_mode) {
-            const size_t tn = (size_t)npix * K;
-            hipLaunchKernelGGL(k_fold, dim3((unsigned)std::min<size_t>((tn + 255) / 256, 8192)), dim3(256), 0, s, tn,
-                               P.t32, P.t64);
-        }
+        if ((st = tm.end(s)) != MC_OK) return st;
         if (hipGetLastError() != hipSuccess) return MC_ERR_DEVICE;
     }
+    return MC_OK;
+}
+
+// Tiled mode: host-driven generations (launch, sort by tile, transport), one
+// stream synchronisation per generation to read the queue length.
+mc_status run_tiled(Params &P, const Layout &L, const mc_run *run, char *base, hipStream_t s) {
+    const int N = run->n_harm;
+    const TransportFn fn = kernels().tile[N];
+    mc_status st = set_lds_limit(reinterpret_cast<const void *>(fn), L.tile_lds);
+    if (st != MC_OK) return st;
+    const int occ = occupancy_blocks(fn, kBlockTile, L.tile_lds);
+    const int cus = device_cus();
+    const unsigned tgrid = (unsigned)std::max(1, std::min(cus * occ, kTileWavesMax / (kBlockTile / 64)));
+    P.tw = L.tw;
+    P.th = L.th;
+    P.ntx = L.ntx;
+    P.ntiles = L.ntiles;
+    P.qa = reinterpret_cast<PacketRec *>(base + L.qa);
+    P.qb = reinterpret_cast<PacketRec *>(base + L.qb);
+    P.qcnt = reinterpret_cast<uint32_t *>(base + L.qcnt);
+    P.tile_count = reinterpret_cast<uint32_t *>(base + L.tcount);
+    P.tile_cursor = reinterpret_cast<uint32_t *>(base + L.tcursor);
+    P.jobs = reinterpret_cast<uint4 *>(base + L.jobs);
+    P.cap_a = (uint32_t)L.cap_a;
+    P.cap_b = (uint32_t)L.live;
+    P.job_size = tile_tuning().job;
+    P.max_visits = tile_tuning().maxvis;
+    P.tail_visits = tile_tuning().tailvis;
+    const unsigned bgrid = (unsigned)std::min<uint64_t>((L.cap_a + 255) / 256, 4096);
+    static thread_local uint32_t *host_cnt = nullptr;
+    if (!host_cnt && hipHostMalloc(reinterpret_cast<void **>(&host_cnt), 8 * sizeof(uint32_t)) != hipSuccess)
+        return MC_ERR_DEVICE;
+    uint64_t launched = 0, carried = 0;
+    for (uint64_t gen = 0;; ++gen) {
+        if (gen > (1ull << 32)) return MC_ERR_DEVICE;
+        uint64_t n_new = 0;
+        if (carried < L.live) n_new = std::min<uint64_t>(L.live - carried, run->n_packets - launched);
+        if (carried == 0 && n_new == 0) break;
+        if (n_new) {
+            hipLaunchKernelGGL(k_tile_launch, dim3((unsigned)((n_new + 255) / 256)), dim3(256), 0, s, P,
+                               run->first_packet_id + launched, (uint32_t)n_new);
+            launched += n_new;
+        }
+        hipLaunchKernelGGL(k_bin_count, dim3(bgrid), dim3(256), 0, s, P);
+        hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, s, P);
+        hipLaunchKernelGGL(k_bin_scatter, dim3(bgrid), dim3(256), 0, s, P);
+        LaunchTimer tm;
+        if ((st = tm.begin(s)) != MC_OK) return st;
+        hipLaunchKernelGGL(fn, dim3(tgrid), dim3(kBlockTile), L.tile_lds, s, P);
+        if ((st = tm.end(s)) != MC_OK) return st;
+        if (hipGetLastError() != hipSuccess) return MC_ERR_DEVICE;
+        if (hipMemcpyAsync(host_cnt, P.qcnt, 8 * sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return MC_ERR_DEVICE;
+        if (host_cnt[4]) return MC_ERR_DEVICE;   // queue overflow (not expected by construction)
+        carried = host_cnt[0];
+    }
+    return MC_OK;
+}
+
+mc_status run_mc(const mc_medium *m, const mc_source *src, int n_src, const mc_run *run, double *coeffs,
+                 mc_ledger *ledger, void *ws, size_t ws_bytes, void *stream, int adjoint) {
+    mc_status st = validate(m, src, n_src, run);
+    if (st != MC_OK) return st;
+    if (!coeffs) return MC_ERR_INVALID_ARG;
+    const Layout L = layout(m, src, run);
+    if (!ws || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255)) return MC_ERR_WORKSPACE;
+    if (L.tiled && L.tile_lds > kLdsTileMax) return MC_ERR_UNSUPPORTED;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    char *base = static_cast<char *>(ws);
+    const int npix = m->nx * m->nz;
+    const int N = run->n_harm;
+
+    // zero the tally, ledger, counters and (tiled mode) queue counters and tile counts
+    const size_t zero_end = L.tiled ? L.jobs : L.counters + L.n_chunks * sizeof(unsigned long long);
+    if ((st = launch_zero(base + L.t64, zero_end - L.t64, s)) != MC_OK) return st;
+    hipLaunchKernelGGL(k_setup_medium, dim3((npix + 255) / 256), dim3(256), 0, s, npix, m->dx, m->mua_d, m->mus_d,
+                       reinterpret_cast<float4 *>(base + L.med));
+    double map_abs_sum = 0;
+    if (src[0].kind == MC_SRC_MAP) {
+        double *cdf = reinterpret_cast<double *>(base + L.cdf);
+        hipLaunchKernelGGL(k_map_cdf, dim3(1), dim3(1024), 0, s, npix, src[0].map_d, cdf);
+        // the normalisation needs sum |q|: read the last CDF entry
+        if (hipMemcpyAsync(&map_abs_sum, cdf + npix - 1, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return MC_ERR_DEVICE;
+        if (!(map_abs_sum > 0)) return MC_ERR_INVALID_ARG;
+    }
+    if (hipGetLastError() != hipSuccess) return MC_ERR_DEVICE;
+    Params P;
+    fill_params(P, m, src, n_src, run, adjoint, map_abs_sum);
+    P.med = reinterpret_cast<const float4 *>(base + L.med);
+    P.t64 = reinterpret_cast<double *>(base + L.t64);
+    P.led = reinterpret_cast<double *>(base + L.led);
+    P.ledc = reinterpret_cast<unsigned long long *>(base + L.ledc);
+    P.cdf = reinterpret_cast<const double *>(base + L.cdf);
+
+    st = L.tiled ? run_tiled(P, L, run, base, s) : run_grid(P, L, run, base, s);
+    if (st != MC_OK) return st;
     const double scale = P.total / ((double)run->n_packets);
     hipLaunchKernelGGL(k_normalise, dim3((npix + 255) / 256), dim3(256), 0, s, npix, N, adjoint,
                        scale / (double)m->dx, P.t64, coeffs);
@@ -1108,7 +1619,8 @@ mc_status mc_profile_read(double *transport_ms, uint64_t *launches, int reset) {
 }
 
 const char *mc_build_info(void) {
-    return "librmc gfx950: FP32 transport, LDS tally <= 64 KiB else FP32 HBM tally folded to FP64 per 2^22 packets";
+    return "librmc gfx950: FP32 transport; FP64 tally in LDS (whole grid when it fits, else square tiles with "
+           "packet migration between tiles), flushed to an FP64 HBM tally";
 }
 
 }  // extern "C"
