@@ -80,7 +80,8 @@ struct Params {
     struct PacketRec *qa;       // unsorted records (appended by launches and leavers)
     struct PacketRec *qb;       // records sorted by tile
     uint32_t *qcnt;             // [0] raw records in qa, [1] records to scatter, [2] jobs, [3] job cursor,
-                                // [4] overflow flag
+                                // [4] overflow flag, [5] finisher record cursor, [6] valid records
+                                // written by the last transport launch
     uint32_t *tile_count, *tile_cursor;
     uint4 *jobs;                // (tile, first record in qb, count, 0)
     uint32_t cap_a, cap_b, job_size, max_visits, tail_visits;
@@ -101,9 +102,10 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
             k0 += 0x9E3779B9u;
             k1 += 0xBB67AE85u;
         }
-        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
-        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
-        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        // one 32x32->64 product each (v_mad_u64_u32) rather than separate low and high multiplies
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+        c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
     }
     return c;
 }
@@ -284,6 +286,22 @@ __device__ bool launch(const Params &P, uint64_t pid, Packet &p, float *h, Ledge
     return true;
 }
 
+// expm1(-x) for x >= 0.  Below 1/4 a Taylor polynomial in Horner form
+// (truncation below x^9/9! ~ 1e-11 relative there); above, the library call.
+__device__ __forceinline__ float expm1_neg(float x) {
+    if (x < 0.25f) {
+        float t = fmaf(-x, 1.f / 8.f, 1.f);
+        t = fmaf(-x * (1.f / 7.f), t, 1.f);
+        t = fmaf(-x * (1.f / 6.f), t, 1.f);
+        t = fmaf(-x * (1.f / 5.f), t, 1.f);
+        t = fmaf(-x * 0.25f, t, 1.f);
+        t = fmaf(-x * (1.f / 3.f), t, 1.f);
+        t = fmaf(-x * 0.5f, t, 1.f);
+        return -x * t;
+    }
+    return expm1f(-x);
+}
+
 // One segment: run to the next pixel face or to the end of the free path,
 // depositing the track length weighted by the decaying weight (Sec. 3).
 // Returns EV_CROSS, EV_ESCAPE or EV_SCATTER; T (pixel units) and the pixel
@@ -294,7 +312,7 @@ __device__ __forceinline__ int step(const Params &P, Packet &p, const float4 m, 
     const float od = m.y * d;
     const bool scat = od > p.tau;
     const float l = scat ? p.tau * m.w : d;
-    dw = -p.w * expm1f(-m.x * l);     // weight absorbed on the segment
+    dw = -p.w * expm1_neg(m.x * l);   // weight absorbed on the segment
     T = m.x > 0.f ? dw * m.z : p.w * l;
     p.w -= dw;
     if (scat) {
@@ -541,7 +559,7 @@ __device__ __forceinline__ uint32_t rec_load(const PacketRec *r, Packet &p) {
 // with one atomic on the queue counter (shared by every wave of the device,
 // so it is touched rarely) and fills them; unused slots are marked invalid.
 struct QueueSlice {
-    uint32_t base = 0, used = kSlice;
+    uint32_t base = 0, used = kSlice, nput = 0;
     bool valid = false;
 };
 
@@ -573,6 +591,13 @@ __device__ __forceinline__ void slice_put(const Params &P, QueueSlice &q, bool p
         else atomicOr(P.qcnt + 4, 1u);   // overflow: reported to the host, never written
     }
     q.used += n;
+    q.nput += n;
+}
+
+// End of a wave's appends: pad its last slice and count its records.
+__device__ __forceinline__ void slice_finish(const Params &P, QueueSlice &q) {
+    slice_close(P, q);
+    if (q.nput && __lane_id() == 0) atomicAdd(P.qcnt + 6, q.nput);
 }
 
 // Launch n_new packets (ids pid_base..) and append those inside the grid.
@@ -658,6 +683,7 @@ __global__ void __launch_bounds__(1024) k_bin_scan(Params P) {
         P.qcnt[0] = 0;
         P.qcnt[2] = fits ? s_job[1023] : 0u;
         P.qcnt[3] = 0;
+        P.qcnt[6] = 0;
         if (!fits) P.qcnt[4] = 1u;
     }
 }
@@ -846,7 +872,108 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
         }
         __syncthreads();
     }
-    slice_close(P, q);
+    slice_finish(P, q);
+    ledger_flush(P, L);
+}
+
+// ------------------------------------------------------------------ tail finisher
+// When few packets remain after the last launch, the generations would be
+// dominated by the longest-lived packets.  The finisher moves each remaining
+// packet to its end without migration; a wave stages the K-vectors of the
+// visits it completes in LDS and adds them to the HBM FP64 tally as
+// contiguous runs of atomics.
+constexpr int kBlockFinish = 256;
+
+template <int NH>
+__global__ void __launch_bounds__(kBlockFinish) k_finish(Params P, uint32_t n_rec) {
+    constexpr int K = 2 * NH + 1;
+    extern __shared__ float stage_all[];
+    const int lane = __lane_id();
+    const int wave = threadIdx.x >> 6;
+    float *stage = stage_all + wave * 64 * K;
+    int *stage_pix = reinterpret_cast<int *>(stage_all + (kBlockFinish / 64) * 64 * K) + wave * 64;
+    const unsigned long long lt_mask = (1ull << lane) - 1ull;
+    LedgerRegs L;
+    Packet p;
+    p.alive = false;
+    float h[K], acc[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        h[j] = 0.f;
+        acc[j] = 0.f;
+    }
+    bool more = true, dirty = false;
+    for (;;) {
+        if (more) {
+            const unsigned long long dead = __ballot(!p.alive);
+            if (dead) {
+                const int ndead = __popcll(dead);
+                const int leader = __ffsll((long long)dead) - 1;
+                uint32_t base = 0;
+                if (lane == leader) base = atomicAdd(P.qcnt + 5, (uint32_t)ndead);
+                base = __shfl(base, leader);
+                if (base + ndead >= n_rec) more = false;
+                if (!p.alive) {
+                    const uint32_t my = base + __popcll(dead & lt_mask);
+                    if (my < n_rec && P.qa[my].tile != kInvalidTile) {
+                        rec_load(P.qa + my, p);
+                        dirty = true;
+                    }
+                }
+            }
+        }
+        if (!__ballot(p.alive)) {
+            if (!more) break;
+        }
+        refresh_harmonics<NH>(dirty, p, h);
+        dirty = false;
+        int ev = EV_NONE, pix = 0;
+        float T = 0.f, dw = 0.f;
+        if (p.alive) {
+            pix = p.iz * P.nx + p.ix;
+            ev = step(P, p, P.med[pix], T, dw);
+            L.absorbed += (double)dw;
+            L.segments += 1;
+        }
+#pragma unroll
+        for (int j = 0; j < K; ++j) acc[j] = fmaf(T, h[j], acc[j]);
+        bool flush = false;
+        if (ev == EV_SCATTER) {
+            if (scatter_dir(P, p, P.g[pix], L)) dirty = true;
+            else flush = true;
+        } else if (ev != EV_NONE) {
+            flush = true;
+            if (ev == EV_ESCAPE) {
+                L.escaped += p.w;
+                p.alive = false;
+            }
+        }
+        const unsigned long long fm = __ballot(flush);
+        if (fm) {
+            if (flush) {
+                L.visits += 1;
+                const int slot = __popcll(fm & lt_mask);
+                float *st = stage + slot * K;
+#pragma unroll
+                for (int j = 0; j < K; ++j) st[j] = acc[j];
+                stage_pix[slot] = pix;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int total = __popcll(fm) * K;
+            for (int e = lane; e < total; e += 64) {
+                const int v = e / K;
+                const float val = stage[e];
+                if (val != 0.f) unsafeAtomicAdd(P.t64 + (size_t)stage_pix[v] * K + (e - v * K), (double)val);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+#pragma unroll
+        for (int j = 0; j < K; ++j) acc[j] = flush ? 0.f : acc[j];
+    }
     ledger_flush(P, L);
 }
 
@@ -1052,21 +1179,24 @@ __global__ void k_philox_fill(uint64_t seed, uint32_t tag, uint64_t pid0, uint64
 // ------------------------------------------------------------------ dispatch tables
 using TransportFn = void (*)(Params);
 using TraceFn = void (*)(Params, const uint64_t *, int, mc_event *, size_t, unsigned long long *);
+using FinishFn = void (*)(Params, uint32_t);
 
 template <int NH>
 struct Table {
-    static void fill(TransportFn *grid, TransportFn *tile, TraceFn *tr) {
+    static void fill(TransportFn *grid, TransportFn *tile, TraceFn *tr, FinishFn *fin) {
         grid[NH] = k_transport_grid<NH>;
         tile[NH] = k_transport_tile<NH>;
         tr[NH] = k_trace<NH>;
-        if constexpr (NH > 0) Table<NH - 1>::fill(grid, tile, tr);
+        fin[NH] = k_finish<NH>;
+        if constexpr (NH > 0) Table<NH - 1>::fill(grid, tile, tr, fin);
     }
 };
 
 struct Kernels {
     TransportFn grid[MC_NHARM_MAX + 1], tile[MC_NHARM_MAX + 1];
     TraceFn tr[MC_NHARM_MAX + 1];
-    Kernels() { Table<MC_NHARM_MAX>::fill(grid, tile, tr); }
+    FinishFn fin[MC_NHARM_MAX + 1];
+    Kernels() { Table<MC_NHARM_MAX>::fill(grid, tile, tr, fin); }
 };
 
 const Kernels &kernels() {
@@ -1099,10 +1229,11 @@ constexpr uint32_t kMaxVisitsPerStay = 256;   // a packet pauses after this many
 constexpr int kTileWavesMax = 256 * 16;       // bound on resident waves of the tiled kernel
 
 // Tuning knobs of the tiled mode, overridable through the environment
-// (RMC_LIVE, RMC_JOB, RMC_MAXVIS, RMC_TAILVIS, RMC_TILE) for measurement sweeps.
+// (RMC_LIVE, RMC_JOB, RMC_MAXVIS, RMC_TAILVIS, RMC_TILE, RMC_FINISH) for measurement sweeps.
 struct TileTuning {
     uint64_t live = kLiveMax;
     uint32_t job = kJobSize, maxvis = kMaxVisitsPerStay, tailvis = 1u << 30;
+    uint64_t finish = 0;   // 0: live / 32
     int tile = 0;   // 0: largest square tile for two workgroups per CU
 };
 const TileTuning &tile_tuning() {
@@ -1119,6 +1250,7 @@ const TileTuning &tile_tuning() {
         v.maxvis = (uint32_t)get("RMC_MAXVIS", 1, 1u << 30, v.maxvis);
         v.tailvis = (uint32_t)get("RMC_TAILVIS", 1, 1u << 30, v.tailvis);
         v.tile = (int)get("RMC_TILE", 1, 256, 0);
+        v.finish = get("RMC_FINISH", 1, 1ull << 26, 0);
         return v;
     }();
     return t;
@@ -1281,9 +1413,9 @@ void fill_params(Params &P, const mc_medium *m, const mc_source *src, int n_src,
     if (n_src == 1 && src[0].kind == MC_SRC_MAP) P.map = src[0].map_d;
 }
 
-int occupancy_blocks(TransportFn fn, int block, size_t lds) {
+int occupancy_blocks(const void *fn, int block, size_t lds) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(fn), block, lds) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, block, lds) != hipSuccess ||
         nb < 1)
         nb = 1;
     return nb;
@@ -1342,7 +1474,7 @@ mc_status run_grid(Params &P, const Layout &L, const mc_run *run, char *base, hi
     mc_status st = set_lds_limit(reinterpret_cast<const void *>(fn), lds);
     if (st != MC_OK) return st;
     const int block = grid_block(N);
-    const int occ = occupancy_blocks(fn, block, lds);
+    const int occ = occupancy_blocks(reinterpret_cast<const void *>(fn), block, lds);
     const int cus = device_cus();
     for (uint64_t c = 0; c < L.n_chunks; ++c) {
         const uint64_t a = c * kChunk;
@@ -1368,7 +1500,7 @@ mc_status run_tiled(Params &P, const Layout &L, const mc_run *run, char *base, h
     const TransportFn fn = kernels().tile[N];
     mc_status st = set_lds_limit(reinterpret_cast<const void *>(fn), L.tile_lds);
     if (st != MC_OK) return st;
-    const int occ = occupancy_blocks(fn, kBlockTile, L.tile_lds);
+    const int occ = occupancy_blocks(reinterpret_cast<const void *>(fn), kBlockTile, L.tile_lds);
     const int cus = device_cus();
     const unsigned tgrid = (unsigned)std::max(1, std::min(cus * occ, kTileWavesMax / (kBlockTile / 64)));
     P.tw = L.tw;
@@ -1390,6 +1522,7 @@ mc_status run_tiled(Params &P, const Layout &L, const mc_run *run, char *base, h
     static thread_local uint32_t *host_cnt = nullptr;
     if (!host_cnt && hipHostMalloc(reinterpret_cast<void **>(&host_cnt), 8 * sizeof(uint32_t)) != hipSuccess)
         return MC_ERR_DEVICE;
+    const uint64_t finish_at = tile_tuning().finish ? tile_tuning().finish : L.live / 32;
     uint64_t launched = 0, carried = 0;
     for (uint64_t gen = 0;; ++gen) {
         if (gen > (1ull << 32)) return MC_ERR_DEVICE;
@@ -1413,7 +1546,24 @@ mc_status run_tiled(Params &P, const Layout &L, const mc_run *run, char *base, h
             hipStreamSynchronize(s) != hipSuccess)
             return MC_ERR_DEVICE;
         if (host_cnt[4]) return MC_ERR_DEVICE;   // queue overflow (not expected by construction)
-        carried = host_cnt[0];
+        carried = host_cnt[6];   // valid records; qa also holds the padding of partly used slices
+        if (launched == run->n_packets && carried > 0 && carried <= finish_at) {
+            const uint32_t n_rec = (uint32_t)std::min<uint64_t>(host_cnt[0], L.cap_a);
+            // finish the remaining packets without migration (qcnt[5]: record cursor)
+            const FinishFn ff = kernels().fin[N];
+            const size_t flds = (size_t)(kBlockFinish / 64) * 64 * (2 * N + 1) * sizeof(float) +
+                                (kBlockFinish / 64) * 64 * sizeof(int);
+            if ((st = set_lds_limit(reinterpret_cast<const void *>(ff), flds)) != MC_OK) return st;
+            const int focc = occupancy_blocks(reinterpret_cast<const void *>(ff), kBlockFinish, flds);
+            const unsigned fgrid = (unsigned)std::max<uint64_t>(
+                1, std::min<uint64_t>((carried + kBlockFinish - 1) / kBlockFinish, (uint64_t)cus * focc));
+            LaunchTimer tf;
+            if ((st = tf.begin(s)) != MC_OK) return st;
+            hipLaunchKernelGGL(ff, dim3(fgrid), dim3(kBlockFinish), flds, s, P, n_rec);
+            if ((st = tf.end(s)) != MC_OK) return st;
+            if (hipGetLastError() != hipSuccess) return MC_ERR_DEVICE;
+            break;
+        }
     }
     return MC_OK;
 }
