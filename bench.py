@@ -22,6 +22,27 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
 
+# HBM traffic of the transport launches from two rocprofv3 counter passes
+# (FETCH_SIZE, then WRITE_SIZE, KiB summed over the launches of one benchmark
+# step and divided by their number), each scaled by what the same counter
+# reads for a plain 1 GiB device copy.  Valid only for the kernel source it
+# was measured on: reported as null once that source changes.
+TRAFFIC = {
+    "source_sha256": "be3a874322ad380bc393911db10eb582ef30bb8530e371ed6fa0e5099b50d567",
+    "fetch_kib_per_launch": 1.19375e5, "fetch_factor": 1.990,
+    "write_kib_per_launch": 3.82504e5, "write_factor": 1.000,
+}
+
+
+def traffic_bytes_per_launch():
+    import hashlib
+    src = os.path.join(ROOT, "paper_1608_05238_amd", "csrc", "mcrad.hip")
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != TRAFFIC["source_sha256"]:
+            return None
+    t = TRAFFIC
+    return 1024.0 * (t["fetch_kib_per_launch"] * t["fetch_factor"] + t["write_kib_per_launch"] * t["write_factor"])
+
 
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -159,8 +180,10 @@ def main() -> int:
                                "forward + adjoint + gradient",
                    "packets_forward": Np, "packets_adjoint": Np, "n_harm": N, "tally": "fp64 LDS tiles, packet migration"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_transport", "avg_launch_ms": avg_launch_ms, "launches": tr_launches,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_bytes_per_launch(),
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
+                     "kernel": "k_transport_tile<16> + k_finish<16>", "avg_launch_ms": avg_launch_ms,
+                     "launches": tr_launches, "algorithmic_bytes_per_launch": visits * bytes_per_visit / max(tr_launches, 1),
                      "bytes_per_visit": bytes_per_visit,
                      "visits_per_packet": visits / (2 * Np * args.steps),
                      "segments_per_packet": segments / (2 * Np * args.steps),
