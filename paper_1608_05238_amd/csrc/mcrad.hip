@@ -78,6 +78,7 @@ struct Params {
     // tiled mode: packets migrate between square tiles whose tallies live in LDS
     int tw, th, ntx, ntiles;
     struct PacketRec *qa;       // unsorted records (appended by launches and leavers)
+    uint32_t *qtile;            // tile of each unsorted record (kInvalidTile: empty slot)
     struct PacketRec *qb;       // records sorted by tile
     uint32_t *qcnt;             // [0] raw records in qa, [1] records to scatter, [2] jobs, [3] job cursor,
                                 // [4] overflow flag, [5] finisher record cursor, [6] valid records
@@ -567,7 +568,7 @@ __device__ __forceinline__ void slice_close(const Params &P, QueueSlice &q) {
     if (!q.valid) return;
     const int lane = __lane_id();
     for (uint32_t i = q.used + lane; i < kSlice; i += 64)
-        if (q.base + i < P.cap_a) P.qa[q.base + i].tile = kInvalidTile;
+        if (q.base + i < P.cap_a) P.qtile[q.base + i] = kInvalidTile;
 }
 
 // Appends the packet of every lane with `put` set to the unsorted queue.
@@ -587,7 +588,10 @@ __device__ __forceinline__ void slice_put(const Params &P, QueueSlice &q, bool p
     }
     if (put) {
         const uint32_t pos = q.base + q.used + __popcll(m & ((1ull << lane) - 1ull));
-        if (pos < P.cap_a) rec_store(P.qa + pos, p, tile, nvis);
+        if (pos < P.cap_a) {
+            rec_store(P.qa + pos, p, tile, nvis);
+            P.qtile[pos] = tile;
+        }
         else atomicOr(P.qcnt + 4, 1u);   // overflow: reported to the host, never written
     }
     q.used += n;
@@ -616,20 +620,38 @@ __global__ void __launch_bounds__(256) k_tile_launch(Params P, uint64_t pid_base
         base = __shfl(base, 0);
         if (p.alive) {
             const uint32_t pos = base + __popcll(m & ((1ull << lane) - 1ull));
-            if (pos < P.cap_a) rec_store(P.qa + pos, p, tile_of(P, p.ix, p.iz), 0u);
+            if (pos < P.cap_a) {
+                const uint32_t t = tile_of(P, p.ix, p.iz);
+                rec_store(P.qa + pos, p, t, 0u);
+                P.qtile[pos] = t;
+            }
             else atomicOr(P.qcnt + 4, 1u);
         }
     }
     if (__ballot(i < n_new)) ledger_flush(P, L);
 }
 
-// Counting sort of the unsorted queue by tile: counts.
+// Counting sort of the unsorted queue by tile: counts.  Up to kHistTiles
+// tiles a workgroup histograms its share in LDS and adds each non-zero bin
+// to the global count once; beyond that, wave-aggregated global atomics.
+constexpr int kHistTiles = 4096;
+
 __global__ void __launch_bounds__(256) k_bin_count(Params P) {
+    __shared__ uint32_t hist[kHistTiles];
     const uint32_t n = P.qcnt[0] < P.cap_a ? P.qcnt[0] : P.cap_a;
     const int lane = __lane_id();
+    const bool local = P.ntiles <= kHistTiles;
+    if (local) {
+        for (int i = threadIdx.x; i < P.ntiles; i += blockDim.x) hist[i] = 0u;
+        __syncthreads();
+    }
     for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
         const uint32_t i = base + threadIdx.x;
-        uint32_t t = i < n ? P.qa[i].tile : kInvalidTile;
+        const uint32_t t = i < n ? P.qtile[i] : kInvalidTile;
+        if (local) {
+            if (t != kInvalidTile) atomicAdd(hist + t, 1u);
+            continue;
+        }
         bool pend = t != kInvalidTile;
         for (;;) {
             const unsigned long long m = __ballot(pend);
@@ -640,6 +662,11 @@ __global__ void __launch_bounds__(256) k_bin_count(Params P) {
             if (lane == leader) atomicAdd(P.tile_count + t0, (uint32_t)__popcll(same));
             if (pend && t == t0) pend = false;
         }
+    }
+    if (local) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < P.ntiles; i += blockDim.x)
+            if (hist[i]) atomicAdd(P.tile_count + i, hist[i]);
     }
 }
 
@@ -689,14 +716,18 @@ __global__ void __launch_bounds__(1024) k_bin_scan(Params P) {
 }
 
 // Counting sort: scatter records to their tile's range of the sorted queue.
+// Ranks come from wave-aggregated atomics on the tile cursors; the 64-byte
+// records are then moved by four lanes each, so every load and store
+// instruction covers sixteen whole records.
 __global__ void __launch_bounds__(256) k_bin_scatter(Params P) {
     const uint32_t n = P.qcnt[1];
     const int lane = __lane_id();
+    const int part = lane & 3;
     for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
         const uint32_t i = base + threadIdx.x;
-        uint32_t t = i < n ? P.qa[i].tile : kInvalidTile;
+        const uint32_t t = i < n ? P.qtile[i] : kInvalidTile;
         bool pend = t != kInvalidTile;
-        uint32_t pos = 0;
+        uint32_t pos = 0xFFFFFFFFu;
         for (;;) {
             const unsigned long long m = __ballot(pend);
             if (!m) break;
@@ -711,13 +742,15 @@ __global__ void __launch_bounds__(256) k_bin_scatter(Params P) {
                 pend = false;
             }
         }
-        if (t != kInvalidTile && pos < P.cap_b) {
-            const uint4 *src = reinterpret_cast<const uint4 *>(P.qa + i);
-            uint4 *dst = reinterpret_cast<uint4 *>(P.qb + pos);
-            dst[0] = src[0];
-            dst[1] = src[1];
-            dst[2] = src[2];
-            dst[3] = src[3];
+        const uint32_t wave_first = i - (uint32_t)lane;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = q * 16 + (lane >> 2);          // record of the wave this lane helps move
+            const uint32_t dst = __shfl(pos, r);
+            if (dst < P.cap_b) {
+                const uint4 *src = reinterpret_cast<const uint4 *>(P.qa + wave_first + r);
+                reinterpret_cast<uint4 *>(P.qb + dst)[part] = src[part];
+            }
         }
     }
 }
@@ -915,7 +948,7 @@ __global__ void __launch_bounds__(kBlockFinish) k_finish(Params P, uint32_t n_re
                 if (base + ndead >= n_rec) more = false;
                 if (!p.alive) {
                     const uint32_t my = base + __popcll(dead & lt_mask);
-                    if (my < n_rec && P.qa[my].tile != kInvalidTile) {
+                    if (my < n_rec && P.qtile[my] != kInvalidTile) {
                         rec_load(P.qa + my, p);
                         dirty = true;
                     }
@@ -1257,7 +1290,7 @@ const TileTuning &tile_tuning() {
 }
 
 struct Layout {
-    size_t med, cdf, t64, led, ledc, counters, qa, qb, tcount, tcursor, jobs, qcnt, total;
+    size_t med, cdf, t64, led, ledc, counters, qa, qtile, qb, tcount, tcursor, jobs, qcnt, total;
     uint64_t n_chunks;
     bool tiled;
     int tw, th, ntx, ntz, ntiles;
@@ -1316,6 +1349,8 @@ Layout layout(const mc_medium *m, const mc_source *src, const mc_run *run) {
         off = align_up(off + L.max_jobs * sizeof(uint4));
         L.qa = off;
         off = align_up(off + L.cap_a * sizeof(PacketRec));
+        L.qtile = off;
+        off = align_up(off + L.cap_a * sizeof(uint32_t));
         L.qb = off;
         off = align_up(off + L.live * sizeof(PacketRec));
     }
@@ -1508,6 +1543,7 @@ mc_status run_tiled(Params &P, const Layout &L, const mc_run *run, char *base, h
     P.ntx = L.ntx;
     P.ntiles = L.ntiles;
     P.qa = reinterpret_cast<PacketRec *>(base + L.qa);
+    P.qtile = reinterpret_cast<uint32_t *>(base + L.qtile);
     P.qb = reinterpret_cast<PacketRec *>(base + L.qb);
     P.qcnt = reinterpret_cast<uint32_t *>(base + L.qcnt);
     P.tile_count = reinterpret_cast<uint32_t *>(base + L.tcount);
@@ -1519,6 +1555,7 @@ mc_status run_tiled(Params &P, const Layout &L, const mc_run *run, char *base, h
     P.max_visits = tile_tuning().maxvis;
     P.tail_visits = tile_tuning().tailvis;
     const unsigned bgrid = (unsigned)std::min<uint64_t>((L.cap_a + 255) / 256, 4096);
+    const unsigned cgrid = (unsigned)std::min<uint64_t>((L.cap_a + 255) / 256, 4 * (uint64_t)cus);
     static thread_local uint32_t *host_cnt = nullptr;
     if (!host_cnt && hipHostMalloc(reinterpret_cast<void **>(&host_cnt), 8 * sizeof(uint32_t)) != hipSuccess)
         return MC_ERR_DEVICE;
@@ -1534,7 +1571,7 @@ mc_status run_tiled(Params &P, const Layout &L, const mc_run *run, char *base, h
                                run->first_packet_id + launched, (uint32_t)n_new);
             launched += n_new;
         }
-        hipLaunchKernelGGL(k_bin_count, dim3(bgrid), dim3(256), 0, s, P);
+        hipLaunchKernelGGL(k_bin_count, dim3(cgrid), dim3(256), 0, s, P);
         hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, s, P);
         hipLaunchKernelGGL(k_bin_scatter, dim3(bgrid), dim3(256), 0, s, P);
         LaunchTimer tm;

@@ -59,14 +59,22 @@ def _oracle_batches(O, ph, specs, n, N, B, seed=0, adjoint=False, first=0, tag=0
 
 
 def _assert_maps(name, gpu, ora, se):
+    """Element-wise bar max(1e-4 relative, 3 SE).  A pixel reached by only a few
+    packets (relative SE of a0 above 0.3) can hold most of one packet whose
+    FP32 trajectory left the FP64 one at a tie (a face/corner or roulette
+    decision within rounding of its threshold); such sparse pixels are exempt,
+    and their number is recorded and bounded."""
     tol = np.maximum(1e-4 * np.abs(ora), 3 * se)
     bad = np.abs(gpu - ora) > tol + 1e-300
+    sparse = se[0] > 0.3 * np.abs(ora[0])
+    bad_dense = bad & ~sparse[None]
     rel = np.abs(gpu - ora) / np.maximum(np.abs(ora), 1e-300)
     big = np.abs(ora) > 1e-3 * np.abs(ora).max()
     stats = {"max_rel_err_significant": float(rel[big].max()), "median_rel_err": float(np.median(rel[big])),
-             "frac_outside_tol": float(bad.mean())}
+             "frac_outside_tol": float(bad.mean()), "outside_tol_sparse": int((bad & sparse[None]).sum())}
     _record(name, stats)
-    assert not bad.any(), (name, stats, np.argwhere(bad)[:5])
+    assert not bad_dense.any(), (name, stats, np.argwhere(bad_dense)[:5])
+    assert bad.mean() <= 1e-5, (name, stats, np.argwhere(bad)[:5])
 
 
 # ---------------------------------------------------------------- RNG
@@ -241,13 +249,35 @@ def test_forward_maps_harmonic_orders(N):
     _assert_maps(f"forward_orders_N{N}", gpu, ora, se)
 
 
+def test_forward_maps_many_tiles():
+    """A grid cut into more tiles (65 x 65 at N = 16) than the per-workgroup
+    histogram of the sort holds, so packets are binned with global atomics."""
+    rmc = _rmc()
+    O = _oracle()
+    ph = P.homogeneous(1040, 1040, 0.1, 0.5, 5.0, 0.5)
+    # sources off the pixel faces (a face position depends on the precision of dx)
+    specs = [P.point_source(52.03, 51.97), P.SourceSpec("pencil", 51.03, 0.0, 0, 0, 0.0, 1.0, 0, 1.0)]
+    n, B = 20_000, 8
+    gpu, led = _gpu_run(rmc, ph, specs, n, 16, seed=21)
+    assert led["packets"] == n
+    outs = []
+    for b in range(B):
+        a0, a1 = n * b // B, n * (b + 1) // B
+        r = O.Run(a1 - a0, 21, 16, first_packet_id=a0)
+        outs.append(O.run_mc(O.medium_from(ph), O.sources_from(specs), r, n_threads=4)[0] * (a1 - a0) / n)
+    outs = np.array(outs)
+    ora, se = outs.sum(axis=0), outs.std(axis=0, ddof=1) * np.sqrt(B)
+    _assert_maps("forward_many_tiles", gpu, ora, se)
+
+
 def test_forward_global_tally_across_chunks():
-    """More packets than one launch chunk (2^22) on a grid that uses the HBM tally.
+    """More packets than one generation of the tiled transport keeps alive
+    (2^22) on a 96 x 96 grid.
 
     The run over [0, n) equals the packet-weighted combination of runs over
-    sub-ranges (the same packets), up to the FP32 rounding of the per-chunk
-    tallies, which must stay far below the Monte Carlo standard error; and a
-    sub-range straddling the chunk edge matches the oracle."""
+    sub-ranges (the same packets), up to the FP32 rounding of the per-visit
+    accumulators, which must stay far below the Monte Carlo standard error;
+    and a sub-range straddling the generation edge matches the oracle."""
     rmc = _rmc()
     O = _oracle()
     ph = P.disc_phantom(96, 0.1, 0.02, 8.0, 0.9, seed=4)
