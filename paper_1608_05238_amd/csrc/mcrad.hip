@@ -151,19 +151,28 @@ struct LedgerRegs {
     uint32_t packets = 0, segments = 0, visits = 0, scatters = 0;
 };
 
+// h = [1, cos t .. cos Nt, sin t .. sin Nt] for the direction (sin t, cos t)
+// by the three-term recurrences cos (n+1)t = 2 cos t cos nt - cos (n-1)t and
+// sin (n+1)t = 2 cos t sin nt - sin (n-1)t: one FMA per value.  A rounding
+// error made at order k reaches order n multiplied by a Chebyshev polynomial
+// of the second kind, bounded by n - k + 1, so the error stays below
+// n^2/2 ulp (8e-6 at n = 16).
 template <int NH>
 __device__ __forceinline__ void harmonics(float sx, float sz, float *h) {
-    // h = [1, cos t .. cos Nt, sin t .. sin Nt] from z = cos t + i sin t
     h[0] = 1.f;
-    float re = sz, im = sx;
+    if constexpr (NH >= 1) {
+        h[1] = sz;
+        h[NH + 1] = sx;
+    }
+    const float c2 = 2.f * sz;
+    if constexpr (NH >= 2) {
+        h[2] = fmaf(c2, sz, -1.f);
+        h[NH + 2] = c2 * sx;
+    }
 #pragma unroll
-    for (int n = 1; n <= NH; ++n) {
-        h[n] = re;
-        h[NH + n] = im;
-        const float nre = re * sz - im * sx;
-        const float nim = re * sx + im * sz;
-        re = nre;
-        im = nim;
+    for (int n = 3; n <= NH; ++n) {
+        h[n] = fmaf(c2, h[n - 1], -h[n - 2]);
+        h[NH + n] = fmaf(c2, h[NH + n - 1], -h[NH + n - 2]);
     }
 }
 
@@ -191,9 +200,11 @@ __device__ __forceinline__ void set_dir(Packet &p, float sx, float sz) {
 }
 
 // Draw block k: free path (optical depth) and the uniforms used at its end.
+// -ln u from the hardware log2 (u >= 2^-24 is never denormal; 1.2e-7
+// relative error measured on the generator's grid of u).
 __device__ __forceinline__ void new_leg(const Params &P, Packet &p) {
     const uint4 r = rng_block(P, p.pid, p.k);
-    p.tau = -logf(u01(r.x));
+    p.tau = __builtin_amdgcn_logf(u01(r.x)) * -0.693147180559945309f;
     p.uh = u01(r.y);
     p.ur = u01(r.z);
 }
@@ -307,8 +318,11 @@ __device__ __forceinline__ float expm1_neg(float x) {
 // depositing the track length weighted by the decaying weight (Sec. 3).
 // Returns EV_CROSS, EV_ESCAPE or EV_SCATTER; T (pixel units) and the pixel
 // of the segment are returned through the references.
-__device__ __forceinline__ int step(const Params &P, Packet &p, const float4 m, float &T, float &dw) {    const float dfx = p.sx > 0.f ? (1.f - p.fx) * p.isx : (p.sx < 0.f ? -p.fx * p.isx : INFINITY);
-    const float dfz = p.sz > 0.f ? (1.f - p.fz) * p.isz : (p.sz < 0.f ? -p.fz * p.isz : INFINITY);
+// Written with selects only: every lane of a wave runs the same instructions.
+__device__ __forceinline__ int step(const Params &P, Packet &p, const float4 m, float &T, float &dw) {
+    const bool px = p.sx > 0.f, pz = p.sz > 0.f;
+    const float dfx = p.sx != 0.f ? (px ? 1.f - p.fx : p.fx) * fabsf(p.isx) : INFINITY;
+    const float dfz = p.sz != 0.f ? (pz ? 1.f - p.fz : p.fz) * fabsf(p.isz) : INFINITY;
     const float d = fminf(dfx, dfz);
     const float od = m.y * d;
     const bool scat = od > p.tau;
@@ -316,45 +330,40 @@ __device__ __forceinline__ int step(const Params &P, Packet &p, const float4 m, 
     dw = -p.w * expm1_neg(m.x * l);   // weight absorbed on the segment
     T = m.x > 0.f ? dw * m.z : p.w * l;
     p.w -= dw;
-    if (scat) {
-        p.fx = fminf(fmaxf(p.fx + l * p.sx, 0.f), 1.f);
-        p.fz = fminf(fmaxf(p.fz + l * p.sz, 0.f), 1.f);
-        return EV_SCATTER;
-    }
-    p.tau -= od;
-    if (dfx <= dfz) {
-        if (p.sx > 0.f) { p.ix += 1; p.fx = 0.f; } else { p.ix -= 1; p.fx = 1.f; }
-    } else {
-        p.fx = fminf(fmaxf(p.fx + l * p.sx, 0.f), 1.f);
-    }
-    if (dfz <= dfx) {
-        if (p.sz > 0.f) { p.iz += 1; p.fz = 0.f; } else { p.iz -= 1; p.fz = 1.f; }
-    } else {
-        p.fz = fminf(fmaxf(p.fz + l * p.sz, 0.f), 1.f);
-    }
-    if (p.ix < 0 || p.ix >= P.nx || p.iz < 0 || p.iz >= P.nz) return EV_ESCAPE;
-    return EV_CROSS;
+    const float nfx = fminf(fmaxf(p.fx + l * p.sx, 0.f), 1.f);
+    const float nfz = fminf(fmaxf(p.fz + l * p.sz, 0.f), 1.f);
+    const bool cx = !scat && dfx <= dfz, cz = !scat && dfz <= dfx;   // faces crossed (both at a corner)
+    p.tau = scat ? p.tau : p.tau - od;
+    p.ix += cx ? (px ? 1 : -1) : 0;
+    p.iz += cz ? (pz ? 1 : -1) : 0;
+    p.fx = cx ? (px ? 0.f : 1.f) : nfx;
+    p.fz = cz ? (pz ? 0.f : 1.f) : nfz;
+    const bool out = (unsigned)p.ix >= (unsigned)P.nx || (unsigned)p.iz >= (unsigned)P.nz;
+    return scat ? EV_SCATTER : (out ? EV_ESCAPE : EV_CROSS);
 }
 
 // Scatter site: termination test on |W| (Sec. 3, Sec. 6), then the 2D HG
 // deflection (eq. scattering_angle) written without atan/tan: with
 // a = (1+g) cos(pi(u-1/2)), b = (1-g) sin(pi(u-1/2)), tan(dt/2) = b/a, so
-// cos dt = (a^2-b^2)/(a^2+b^2), sin dt = 2ab/(a^2+b^2).  Returns false if
-// the packet was killed.
-__device__ __forceinline__ bool scatter_dir(const Params &P, Packet &p, const float g, LedgerRegs &L) {
-    if (p.k >= kMaxInteractions) {
-        L.loss += p.w;
-        p.alive = false;
-        return false;
-    }
-    if (fabsf(p.w) < P.wth * p.w0abs) {
-        if ((P.flags & MC_FLAG_LITERAL_TRUNCATION) || !(p.ur < P.inv_rm)) {
-            L.loss += p.w;
-            p.alive = false;
-            return false;
+// cos dt = (a^2-b^2)/(a^2+b^2), sin dt = 2ab/(a^2+b^2); then the next block
+// of random numbers.  `at` marks the lanes that scatter; every lane runs the
+// same instructions and only those lanes commit (selects, so the Philox
+// rounds and the deflection form one basic block the scheduler can
+// interleave).  Returns true for the lanes whose packet was terminated.
+__device__ __forceinline__ bool scatter_masked(const Params &P, Packet &p, const bool at, const float g,
+                                               LedgerRegs &L) {
+    bool kill = false;
+    const bool low = at && (p.k >= kMaxInteractions || fabsf(p.w) < P.wth * p.w0abs);
+    if (__ballot(low)) {   // rare: roulette or the hard cap on interactions
+        if (low) {
+            if (p.k >= kMaxInteractions || (P.flags & MC_FLAG_LITERAL_TRUNCATION) || !(p.ur < P.inv_rm)) {
+                kill = true;
+                L.loss += p.w;
+            } else {
+                L.gain += (double)((P.rm - 1.f) * p.w);
+                p.w *= P.rm;
+            }
         }
-        L.gain += (double)((P.rm - 1.f) * p.w);
-        p.w *= P.rm;
     }
     float sp, cp;
     sincospif(p.uh - 0.5f, &sp, &cp);
@@ -363,14 +372,29 @@ __device__ __forceinline__ bool scatter_dir(const Params &P, Packet &p, const fl
     const float cd = (a * a - b * b) * inv, sd = 2.f * a * b * inv;
     float nx_ = p.sx * cd + p.sz * sd;
     float nz_ = p.sz * cd - p.sx * sd;
-    const float rn = rsqrtf(nx_ * nx_ + nz_ * nz_);
+    const float rn = __builtin_amdgcn_rsqf(nx_ * nx_ + nz_ * nz_);   // argument ~1
     nx_ *= rn;
     nz_ *= rn;
-    set_dir(p, nx_, nz_);
-    L.scatters += 1;
-    p.k += 1;
-    new_leg(P, p);
-    return true;
+    const uint4 r = rng_block(P, p.pid, p.k + 1);
+    const float tau = __builtin_amdgcn_logf(u01(r.x)) * -0.693147180559945309f;   // see new_leg
+    const bool go = at && !kill;
+    const float isx = nx_ != 0.f ? __builtin_amdgcn_rcpf(nx_) : INFINITY;
+    const float isz = nz_ != 0.f ? __builtin_amdgcn_rcpf(nz_) : INFINITY;
+    p.sx = go ? nx_ : p.sx;
+    p.sz = go ? nz_ : p.sz;
+    p.isx = go ? isx : p.isx;
+    p.isz = go ? isz : p.isz;
+    p.k = go ? p.k + 1 : p.k;
+    p.tau = go ? tau : p.tau;
+    p.uh = go ? u01(r.y) : p.uh;
+    p.ur = go ? u01(r.z) : p.ur;
+    p.alive = p.alive && !kill;
+    L.scatters += go ? 1u : 0u;
+    return kill;
+}
+
+__device__ __forceinline__ bool scatter_dir(const Params &P, Packet &p, const float g, LedgerRegs &L) {
+    return !scatter_masked(P, p, true, g, L);
 }
 
 template <int NH>
@@ -380,23 +404,14 @@ __device__ __forceinline__ bool scatter(const Params &P, Packet &p, const float 
     return true;
 }
 
-// Recompute the harmonic vector of the lanes whose direction changed.  One
-// call site per loop keeps h in place (a select per channel instead of
-// register copies at control-flow joins).
+// Recompute the harmonic vector when any lane of the wave changed direction.
+// Every lane recomputes: h is a pure function of the direction, so lanes
+// whose direction did not change get the same values back, and no select
+// per channel is needed.  One call site per loop keeps h in place.
 template <int NH>
 __device__ __forceinline__ void refresh_harmonics(bool dirty, const Packet &p, float *h) {
     if (!__ballot(dirty)) return;
-    h[0] = 1.f;
-    float re = p.sz, im = p.sx;
-#pragma unroll
-    for (int n = 1; n <= NH; ++n) {
-        h[n] = dirty ? re : h[n];
-        h[NH + n] = dirty ? im : h[NH + n];
-        const float nre = re * p.sz - im * p.sx;
-        const float nim = re * p.sx + im * p.sz;
-        re = nre;
-        im = nim;
-    }
+    harmonics<NH>(p.sx, p.sz, h);
 }
 
 __device__ __forceinline__ void ledger_flush(const Params &P, LedgerRegs &L) {
@@ -808,15 +823,17 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
         uint32_t tail_nvis = 0;   // visits of the current stay when the job ran out of packets
         uint4 nr0 = make_uint4(0u, 0u, 0u, 0u), nr1 = nr0, nr2 = nr0, nr3 = nr0;
         for (;;) {
-            if (more || __ballot(has_next)) {
-                if (!p.alive && has_next) {
-                    rec_decode(nr0, nr1, nr2, nr3, p);
-                    has_next = false;
-                    nvis = 0;
-                    tail_nvis = 0;
-                    dirty = true;
-                }
-                const unsigned long long want = more ? __ballot(!has_next) : 0ull;
+            // a free lane takes its prefetched record (the only decode site)
+            if (!p.alive && has_next) {
+                rec_decode(nr0, nr1, nr2, nr3, p);
+                has_next = false;
+                nvis = 0;
+                tail_nvis = 0;
+                dirty = true;
+            }
+            // lanes without a prefetched record claim the next ones of the job
+            if (more) {
+                const unsigned long long want = __ballot(!has_next);
                 if (want) {
                     const int nw = __popcll(want);
                     const int leader = __ffsll((long long)want) - 1;
@@ -839,41 +856,34 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
                         }
                     }
                 }
-                if (!p.alive && has_next) {   // no packet at all yet: take the one just loaded
-                    rec_decode(nr0, nr1, nr2, nr3, p);
-                    has_next = false;
-                    nvis = 0;
-                    tail_nvis = 0;
-                    dirty = true;
-                }
             }
             if (!__ballot(p.alive)) {
                 if (!more && !__ballot(has_next)) break;
             }
             refresh_harmonics<NH>(dirty, p, h);
             dirty = false;
-            int ev = EV_NONE, lp = 0;
+            // every lane steps (no branch); a free lane's result is discarded
+            const bool live = p.alive;
+            const int lp = live ? (p.iz - tz0) * P.tw + (p.ix - tx0) : 0;
             float T = 0.f, dw = 0.f;
-            if (p.alive) {
-                lp = (p.iz - tz0) * P.tw + (p.ix - tx0);
-                ev = step(P, p, smed[lp], T, dw);
-                L.absorbed += (double)dw;
-                L.segments += 1;
-            }
+            int ev = step(P, p, smed[lp], T, dw);
+            ev = live ? ev : EV_NONE;
+            T = live ? T : 0.f;
+            dw = live ? dw : 0.f;
+            L.absorbed += (double)dw;
+            L.segments += live ? 1u : 0u;
 #pragma unroll
             for (int j = 0; j < K; ++j) acc[j] = fmaf(T, h[j], acc[j]);
-            bool flush = false;
-            if (ev == EV_SCATTER) {
-                if (scatter_dir(P, p, sg[lp], L)) dirty = true;
-                else flush = true;
-            } else if (ev != EV_NONE) {
-                flush = true;
-                if (ev == EV_ESCAPE) {
-                    L.escaped += p.w;
-                    p.alive = false;
-                }
+            const bool at = ev == EV_SCATTER;
+            const bool killed = scatter_masked(P, p, at, sg[lp], L);
+            dirty = at && !killed;
+            const bool flush = killed || (ev != EV_NONE && !at);
+            if (ev == EV_ESCAPE) {
+                L.escaped += p.w;
+                p.alive = false;
             }
             bool leave = false;
+            uint32_t dest = tile;
             if (flush) {
                 L.visits += 1;
                 nvis += 1;
@@ -881,7 +891,10 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
 #pragma unroll
                 for (int j = 0; j < K; ++j) atomicAdd(t + j, (double)acc[j]);
                 if (ev == EV_CROSS) {
-                    const bool out = p.ix < tx0 || p.ix >= tx0 + P.tw || p.iz < tz0 || p.iz >= tz0 + P.th;
+                    const int ox = p.ix < tx0 ? -1 : (p.ix >= tx0 + P.tw ? 1 : 0);
+                    const int oz = p.iz < tz0 ? -1 : (p.iz >= tz0 + P.th ? 1 : 0);
+                    const bool out = (ox | oz) != 0;
+                    dest = (uint32_t)((int)tile + oz * P.ntx + ox);   // a crossing moves one pixel: a neighbour tile
                     // once the job has no packets left to hand out, a packet pauses
                     // after tail_visits more visits so the workgroup is not held by
                     // its longest stay (it resumes next generation)
@@ -890,7 +903,7 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
             }
 #pragma unroll
             for (int j = 0; j < K; ++j) acc[j] = flush ? 0.f : acc[j];
-            slice_put(P, q, leave, p, leave ? tile_of(P, p.ix, p.iz) : 0u, 0u);
+            slice_put(P, q, leave, p, dest, 0u);
             if (leave) {
                 p.alive = false;
                 nvis = 0;
@@ -1256,9 +1269,9 @@ Profile &profile_state() {
 
 // Tiled-mode sizing.  Tiles are square, as large as lets two workgroups of a
 // CU hold their tile's FP64 tally and medium in LDS.
-constexpr uint64_t kLiveMax = 1ull << 22;     // live packets per generation
-constexpr uint32_t kJobSize = 2048;           // packets per job
-constexpr uint32_t kMaxVisitsPerStay = 256;   // a packet pauses after this many visits in one job
+constexpr uint64_t kLiveMax = 1ull << 24;     // live packets per generation
+constexpr uint32_t kJobSize = 4096;           // packets per job
+constexpr uint32_t kMaxVisitsPerStay = 32;    // a packet pauses after this many visits in one job
 constexpr int kTileWavesMax = 256 * 16;       // bound on resident waves of the tiled kernel
 
 // Tuning knobs of the tiled mode, overridable through the environment

@@ -272,7 +272,7 @@ def test_forward_maps_many_tiles():
 
 def test_forward_global_tally_across_chunks():
     """More packets than one generation of the tiled transport keeps alive
-    (2^22) on a 96 x 96 grid.
+    (2^24) on a 96 x 96 grid.
 
     The run over [0, n) equals the packet-weighted combination of runs over
     sub-ranges (the same packets), up to the FP32 rounding of the per-visit
@@ -282,7 +282,7 @@ def test_forward_global_tally_across_chunks():
     O = _oracle()
     ph = P.disc_phantom(96, 0.1, 0.02, 8.0, 0.9, seed=4)
     specs = P.four_side_lines(ph)
-    n = (1 << 22) + 5000
+    n = (1 << 24) + 5000
     full, _ = _gpu_run(rmc, ph, specs, n, 16, seed=9)
     B = 8
     parts = []
@@ -297,7 +297,7 @@ def test_forward_global_tally_across_chunks():
                                  "median_gap_over_se": float(np.median(gap / np.maximum(se, 1e-300)))})
     assert np.all(gap <= 0.05 * se + 1e-12 * np.abs(full).max())
     m = 8000
-    first = (1 << 22) - 4000
+    first = (1 << 24) - 4000
     gpu, _ = _gpu_run(rmc, ph, specs, m, 16, seed=9, first=first)
     ora, se = _oracle_batches(O, ph, specs, m, 16, B=8, seed=9, first=first)
     _assert_maps("forward_chunk_edge", gpu, ora, se)
