@@ -51,17 +51,21 @@ def counters(root: str) -> str:
     if not files:
         raise SystemExit(f"no *counter_collection.csv under {root}")
     tot = defaultdict(float)
+    per = defaultdict(lambda: defaultdict(float))
     disp = defaultdict(set)
     for f in files:
         with open(f, newline="") as fh:
             for r in csv.DictReader(fh):
                 k = _short(r["Kernel_Name"])
-                tot[(k, r["Counter_Name"])] += float(r["Counter_Value"])
-                disp[k].add((r.get("Agent_Id", ""), r["Dispatch_Id"]))
-    out = ["| kernel | counter | dispatches | sum | per dispatch |", "|---|---|---|---|---|"]
+                d = (r.get("Agent_Id", ""), r["Dispatch_Id"])
+                v = float(r["Counter_Value"])
+                tot[(k, r["Counter_Name"])] += v
+                per[(k, r["Counter_Name"])][d] += v
+                disp[k].add(d)
+    out = ["| kernel | counter | dispatches | sum | per dispatch | largest dispatch |", "|---|---|---|---|---|---|"]
     for (k, c), v in sorted(tot.items(), key=lambda x: -x[1]):
         n = len(disp[k])
-        out.append(f"| {k} | {c} | {n} | {v:.6e} | {v / max(n, 1):.6e} |")
+        out.append(f"| {k} | {c} | {n} | {v:.6e} | {v / max(n, 1):.6e} | {max(per[(k, c)].values()):.6e} |")
     return "\n".join(out)
 
 
