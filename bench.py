@@ -72,6 +72,61 @@ def cpu_baseline(n_packets: int, threads: int) -> dict:
                       f"{dt:.1f} s"}
 
 
+def time_to_error(args) -> dict:
+    """Second half of the headline metric: wall time of one gradient evaluation
+    (forward + residual + adjoint + gradient, N = 16) at the smallest packet
+    count, doubling from 1e6, whose gradients are within 5% (d eps/d mua) and
+    20% (d eps/d mus) relative L2 error of a reference gradient from
+    args.ref_packets + args.ref_packets packets, over pixels at least 10
+    pixels from the boundary."""
+    import torch
+    import phantoms as P
+    from paper_1608_05238_amd import rmc
+    dev = torch.device("cuda", 0)
+    c = P.config2()
+    N = c.n_harm
+    med = rmc.Medium.from_phantom(c.phantom, dev)
+    tmed = rmc.Medium.from_phantom(c.extra["true"], dev)
+    ht, _ = rmc.mc_forward(tmed, c.sources, rmc.make_run(int(args.hmeas_packets), N, seed=1), ledger=False)
+    hmeas = rmc.mc_absorbed(tmed, ht)
+
+    def gradient(n, seed):
+        f, _ = rmc.mc_forward(med, c.sources, rmc.make_run(n, N, seed=seed), ledger=False)
+        q, _ = rmc.mc_residual(med, f, hmeas)
+        a, _ = rmc.mc_adjoint(med, [rmc.Source("map", map=q)], rmc.make_run(n, N, seed=seed, stream_tag=1),
+                              ledger=False)
+        return rmc.mc_gradient(med, N, f, a, hmeas)
+
+    log(f"reference gradient: {args.ref_packets:.0e} + {args.ref_packets:.0e} packets")
+    ra, rs = gradient(int(args.ref_packets), 100)
+    m = 10
+    ra, rs = ra[m:-m, m:-m], rs[m:-m, m:-m]
+    rows = []
+    n = 1_000_000
+    while True:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ga, gs = gradient(n, 7)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ea = float((ga[m:-m, m:-m] - ra).norm() / ra.norm())
+        es = float((gs[m:-m, m:-m] - rs).norm() / rs.norm())
+        rows.append({"packets": n, "wall_ms": wall * 1e3, "err_dmua": ea, "err_dmus": es})
+        log(f"{n:.2e} packets: {wall * 1e3:.1f} ms, error dmua {ea:.4f}, dmus {es:.4f}")
+        if (ea <= 0.05 and es <= 0.20) or n >= args.ref_packets // 4:
+            break
+        n *= 2
+    hit = rows[-1]
+    ok = hit["err_dmua"] <= 0.05 and hit["err_dmus"] <= 0.20
+    return {"metric": "wall time to gradient at fixed rel. error (5% d eps/d mua, 20% d eps/d mus)",
+            "value": hit["wall_ms"] if ok else None, "unit": "ms", "higher_is_better": False, "n_gpus": 1,
+            "packets_forward": hit["packets"], "packets_adjoint": hit["packets"], "reached": ok,
+            "reference_packets": int(args.ref_packets), "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "disc256: forward + residual + adjoint + gradient, N = 16, interior pixels "
+                                   "(10-pixel margin)"},
+            "sweep": rows}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +137,9 @@ def main() -> int:
     ap.add_argument("--hmeas-packets", type=float, default=2e7)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this size first (calibrates HBM counters)")
+    ap.add_argument("--time-to-error", action="store_true",
+                    help="instead of the throughput line, measure the wall time to a gradient of fixed error")
+    ap.add_argument("--ref-packets", type=float, default=1e9, help="packets of the reference gradient (each run)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -95,6 +153,9 @@ def main() -> int:
     from paper_1608_05238_amd import rmc
 
     torch.cuda.set_device(0)
+    if args.time_to_error:
+        print(json.dumps(time_to_error(args)), flush=True)
+        return 0
     dev = torch.device("cuda", 0)
     if args.copy_probe_mib > 0:
         a = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device=dev)

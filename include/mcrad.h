@@ -73,7 +73,8 @@ typedef enum {
  *    angle; a MAP source emits map(x) * 2pi p(t).  Packets of these two kinds
  *    are launched at a uniform angle with weight 2pi p(t) (times the sign of
  *    the map value), so p may be signed.
- *  map_d: device FP64 [nz][nx] (MAP only), may be signed (adjoint source). */
+ *  map_d: device FP64 [nz][nx] (MAP only), may be signed (adjoint source);
+ *    an all-zero map is a source of zero power: the output is zero. */
 typedef struct {
     int32_t kind;            /* mc_source_kind */
     float x0, z0, x1, z1;
@@ -155,6 +156,26 @@ mc_status mc_residual(const mc_medium *medium, const double *coeffs_d, const dou
  * dmua_d, dmus_d: FP64 [nz][nx] out (either may be NULL). */
 mc_status mc_gradient(const mc_medium *medium, int n_harm, const double *fwd_d, const double *adj_d,
                       const double *hmeas_d, double *dmua_d, double *dmus_d, void *stream);
+
+/* Absorbed energy density H = mua a0 (Sec. 2, Grueneisen parameter 1).
+ * coeffs_d: forward FP64 [>=1][nz][nx] (only a0 is read); h_d: FP64 [nz][nx]
+ * out.  Only the medium's mua_d, nx and nz are read. */
+mc_status mc_absorbed(const mc_medium *medium, const double *coeffs_d, double *h_d, void *stream);
+
+/* Adjoint source for any loss L(H) (Sec. 5 and 6 by the chain rule): given
+ * the upstream gradient grad_h = dL/dH per pixel, q* = -mua grad_h / A per
+ * unit angle (A = dx^2).  For L = eps, grad_h = -A (hmeas - H) and q* is the
+ * q* = mua (hmeas - H) of mc_residual.  grad_h_d, q_star_d: FP64 [nz][nx]. */
+mc_status mc_adjoint_source(const mc_medium *medium, const double *grad_h_d, double *q_star_d, void *stream);
+
+/* Gradients of L(H) with respect to mua and mus (Sec. 5 with the direct term
+ * of the chain rule through H = mua Phi), per pixel:
+ *   dL/dmua = grad_h a0 + dx^2 [a0 a0'/2pi + (1/pi) sum_n (a_n a_n' + b_n b_n')]
+ *   dL/dmus = dx^2 (1/pi) sum_{n>=1} (a_n a_n' + b_n b_n') (1 - g^n)
+ * where adj_d is the mc_adjoint field of the source from mc_adjoint_source.
+ * With grad_h = -A (hmeas - H) this equals mc_gradient. */
+mc_status mc_gradient_h(const mc_medium *medium, int n_harm, const double *fwd_d, const double *adj_d,
+                        const double *grad_h_d, double *dmua_d, double *dmus_d, void *stream);
 
 /* Detector readout <phi, b> (Sec. 4.1, eq. adj_definition): the integral over
  * the domain and angle of a radiance times a detector weight function b, both

@@ -17,9 +17,9 @@ MC_FLAG_LITERAL_TRUNCATION = 1
 MC_NHARM_MAX = 32
 
 # exported symbols declared in include/mcrad.h
-SYMBOLS = ("mc_workspace_bytes", "mc_forward", "mc_adjoint", "mc_residual", "mc_gradient", "mc_detect",
-           "mc_trace", "mc_philox_fill", "mc_profile_enable", "mc_profile_read", "mc_status_string",
-           "mc_build_info")
+SYMBOLS = ("mc_workspace_bytes", "mc_forward", "mc_adjoint", "mc_residual", "mc_gradient", "mc_absorbed",
+           "mc_adjoint_source", "mc_gradient_h", "mc_detect", "mc_trace", "mc_philox_fill", "mc_profile_enable",
+           "mc_profile_read", "mc_status_string", "mc_build_info")
 
 
 class mc_medium(C.Structure):
@@ -75,6 +75,12 @@ def load() -> C.CDLL:
     lib.mc_residual.restype = St
     lib.mc_gradient.argtypes = [P(mc_medium), C.c_int, V, V, V, V, V, V]
     lib.mc_gradient.restype = St
+    lib.mc_absorbed.argtypes = [P(mc_medium), V, V, V]
+    lib.mc_absorbed.restype = St
+    lib.mc_adjoint_source.argtypes = [P(mc_medium), V, V, V]
+    lib.mc_adjoint_source.restype = St
+    lib.mc_gradient_h.argtypes = [P(mc_medium), C.c_int, V, V, V, V, V, V]
+    lib.mc_gradient_h.restype = St
     lib.mc_detect.argtypes = [P(mc_medium), C.c_int, V, V, V, V]
     lib.mc_detect.restype = St
     lib.mc_trace.argtypes = [P(mc_medium), P(mc_source), C.c_int, P(mc_run), C.c_int, P(C.c_uint64), C.c_int,

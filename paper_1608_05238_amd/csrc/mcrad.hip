@@ -731,13 +731,59 @@ __global__ void __launch_bounds__(1024) k_bin_scan(Params P) {
 }
 
 // Counting sort: scatter records to their tile's range of the sorted queue.
-// Ranks come from wave-aggregated atomics on the tile cursors; the 64-byte
-// records are then moved by four lanes each, so every load and store
-// instruction covers sixteen whole records.
-__global__ void __launch_bounds__(256) k_bin_scatter(Params P) {
-    const uint32_t n = P.qcnt[1];
+// A workgroup takes chunks of kScatterChunk records.  Up to kHistTiles tiles,
+// each record gets its rank among the chunk's records of its tile from an LDS
+// atomic, the workgroup reserves one range per tile it holds with a single
+// global atomic, and every record lands at range start + rank; beyond that,
+// ranks come from wave-aggregated global atomics.  The 64-byte records are
+// moved by four lanes each, so every load and store instruction covers
+// sixteen whole records.
+constexpr int kScatterPer = 8;                              // records per thread and chunk
+constexpr uint32_t kScatterChunk = 256u * kScatterPer;
+
+__device__ __forceinline__ void move_records(const Params &P, uint32_t wave_first, uint32_t pos) {
     const int lane = __lane_id();
     const int part = lane & 3;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int r = q * 16 + (lane >> 2);   // record of the wave this lane helps move
+        const uint32_t dst = __shfl(pos, r);
+        if (dst < P.cap_b) {
+            const uint4 *src = reinterpret_cast<const uint4 *>(P.qa + wave_first + r);
+            reinterpret_cast<uint4 *>(P.qb + dst)[part] = src[part];
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_bin_scatter(Params P) {
+    __shared__ uint32_t cnt[kHistTiles];
+    __shared__ uint32_t start[kHistTiles];
+    const uint32_t n = P.qcnt[1];
+    const int lane = __lane_id();
+    if (P.ntiles <= kHistTiles) {
+        for (uint32_t c0 = blockIdx.x * kScatterChunk; c0 < n; c0 += gridDim.x * kScatterChunk) {
+            for (int i = threadIdx.x; i < P.ntiles; i += blockDim.x) cnt[i] = 0u;
+            __syncthreads();
+            uint32_t t[kScatterPer], rank[kScatterPer];
+#pragma unroll
+            for (int r = 0; r < kScatterPer; ++r) {
+                const uint32_t i = c0 + r * 256u + threadIdx.x;
+                t[r] = i < n ? P.qtile[i] : kInvalidTile;
+                rank[r] = t[r] != kInvalidTile ? atomicAdd(cnt + t[r], 1u) : 0u;
+            }
+            __syncthreads();
+            for (int i = threadIdx.x; i < P.ntiles; i += blockDim.x)
+                start[i] = cnt[i] ? atomicAdd(P.tile_cursor + i, cnt[i]) : 0u;
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < kScatterPer; ++r) {
+                const uint32_t pos = t[r] != kInvalidTile ? start[t[r]] + rank[r] : 0xFFFFFFFFu;
+                move_records(P, c0 + r * 256u + threadIdx.x - (uint32_t)lane, pos);
+            }
+            __syncthreads();
+        }
+        return;
+    }
     for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
         const uint32_t i = base + threadIdx.x;
         const uint32_t t = i < n ? P.qtile[i] : kInvalidTile;
@@ -757,16 +803,7 @@ __global__ void __launch_bounds__(256) k_bin_scatter(Params P) {
                 pend = false;
             }
         }
-        const uint32_t wave_first = i - (uint32_t)lane;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int r = q * 16 + (lane >> 2);          // record of the wave this lane helps move
-            const uint32_t dst = __shfl(pos, r);
-            if (dst < P.cap_b) {
-                const uint4 *src = reinterpret_cast<const uint4 *>(P.qa + wave_first + r);
-                reinterpret_cast<uint4 *>(P.qb + dst)[part] = src[part];
-            }
-        }
+        move_records(P, i - (uint32_t)lane, pos);
     }
 }
 
@@ -1169,12 +1206,15 @@ __global__ void __launch_bounds__(1024) k_residual(int npix, double area, const 
 }
 
 // Gradients (Sec. 5: eqs. grad_2D_abs_integral3, scattering_gradient3).
+// With hmeas the direct term is that of eps, -A a0 (hmeas - mua a0); with an
+// upstream gradient gh = dL/dH instead (hmeas == nullptr) it is gh a0, the
+// chain rule through H = mua Phi for any loss L(H).
 __global__ void k_gradient(int npix, int N, double area, const float *mua, const float *g, const double *fwd,
-                           const double *adj, const double *hmeas, double *dmua, double *dmus) {
+                           const double *adj, const double *hmeas, const double *gh, double *dmua, double *dmus) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= npix) return;
     const double a0 = fwd[i], a0s = adj[i];
-    const double r = hmeas[i] - (double)mua[i] * a0;
+    const double direct = hmeas ? -area * a0 * (hmeas[i] - (double)mua[i] * a0) : gh[i] * a0;
     const double gi = g[i];
     double all = 0, wg = 0, gn = 1;
     for (int n = 1; n <= N; ++n) {
@@ -1185,8 +1225,21 @@ __global__ void k_gradient(int npix, int N, double area, const float *mua, const
         wg += pr * (1.0 - gn);
     }
     const double ip = 0.31830988618379067154;   // 1/pi
-    if (dmua) dmua[i] = area * (-a0 * r + a0 * a0s * (0.5 * ip) + all * ip);
+    if (dmua) dmua[i] = direct + area * (a0 * a0s * (0.5 * ip) + all * ip);
     if (dmus) dmus[i] = area * (wg * ip);
+}
+
+// H = mua a0 (Sec. 2, Grueneisen parameter 1).
+__global__ void k_absorbed(int npix, const float *mua, const double *a0, double *h) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < npix) h[i] = (double)mua[i] * a0[i];
+}
+
+// Adjoint source for an upstream gradient gh = dL/dH: q* = -mua gh / A per
+// unit angle (for L = eps, gh = -A (hmeas - H) and q* = mua (hmeas - H)).
+__global__ void k_adjoint_source(int npix, double inv_area, const float *mua, const double *gh, double *qs) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < npix) qs[i] = -(double)mua[i] * gh[i] * inv_area;
 }
 
 __global__ void __launch_bounds__(1024) k_detect(int npix, int N, double area, const double *c, const double *d,
@@ -1279,7 +1332,7 @@ constexpr int kTileWavesMax = 256 * 16;       // bound on resident waves of the 
 struct TileTuning {
     uint64_t live = kLiveMax;
     uint32_t job = kJobSize, maxvis = kMaxVisitsPerStay, tailvis = 1u << 30;
-    uint64_t finish = 0;   // 0: live / 32
+    uint64_t finish = 0;   // 0: live / 128
     int tile = 0;   // 0: largest square tile for two workgroups per CU
 };
 const TileTuning &tile_tuning() {
@@ -1572,7 +1625,7 @@ mc_status run_tiled(Params &P, const Layout &L, const mc_run *run, char *base, h
     static thread_local uint32_t *host_cnt = nullptr;
     if (!host_cnt && hipHostMalloc(reinterpret_cast<void **>(&host_cnt), 8 * sizeof(uint32_t)) != hipSuccess)
         return MC_ERR_DEVICE;
-    const uint64_t finish_at = tile_tuning().finish ? tile_tuning().finish : L.live / 32;
+    const uint64_t finish_at = tile_tuning().finish ? tile_tuning().finish : L.live / 128;
     uint64_t launched = 0, carried = 0;
     for (uint64_t gen = 0;; ++gen) {
         if (gen > (1ull << 32)) return MC_ERR_DEVICE;
@@ -1644,7 +1697,12 @@ mc_status run_mc(const mc_medium *m, const mc_source *src, int n_src, const mc_r
         if (hipMemcpyAsync(&map_abs_sum, cdf + npix - 1, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
             return MC_ERR_DEVICE;
-        if (!(map_abs_sum > 0)) return MC_ERR_INVALID_ARG;
+        if (map_abs_sum == 0.0) {   // an all-zero source: the field is zero
+            st = launch_zero(coeffs, (size_t)npix * (2 * N + 1) * sizeof(double), s);
+            if (st == MC_OK && ledger) st = launch_zero(ledger, sizeof(mc_ledger), s);
+            return st;
+        }
+        if (!(map_abs_sum > 0)) return MC_ERR_INVALID_ARG;   // NaN in the map
     }
     if (hipGetLastError() != hipSuccess) return MC_ERR_DEVICE;
     Params P;
@@ -1701,7 +1759,37 @@ mc_status mc_gradient(const mc_medium *m, int n_harm, const double *fwd_d, const
     if (n_harm < 0 || n_harm > MC_NHARM_MAX) return MC_ERR_INVALID_ARG;
     const int npix = m->nx * m->nz;
     hipLaunchKernelGGL(k_gradient, dim3((npix + 255) / 256), dim3(256), 0, reinterpret_cast<hipStream_t>(stream), npix,
-                       n_harm, (double)m->dx * m->dx, m->mua_d, m->g_d, fwd_d, adj_d, hmeas_d, dmua_d, dmus_d);
+                       n_harm, (double)m->dx * m->dx, m->mua_d, m->g_d, fwd_d, adj_d, hmeas_d, nullptr, dmua_d, dmus_d);
+    return hipGetLastError() == hipSuccess ? MC_OK : MC_ERR_DEVICE;
+}
+
+mc_status mc_gradient_h(const mc_medium *m, int n_harm, const double *fwd_d, const double *adj_d,
+                        const double *grad_h_d, double *dmua_d, double *dmus_d, void *stream) {
+    if (!m || m->nx <= 0 || m->nz <= 0 || !(m->dx > 0.f) || !m->mua_d || !m->g_d || !fwd_d || !adj_d || !grad_h_d)
+        return MC_ERR_INVALID_ARG;
+    if (n_harm < 0 || n_harm > MC_NHARM_MAX) return MC_ERR_INVALID_ARG;
+    const int npix = m->nx * m->nz;
+    hipLaunchKernelGGL(k_gradient, dim3((npix + 255) / 256), dim3(256), 0, reinterpret_cast<hipStream_t>(stream), npix,
+                       n_harm, (double)m->dx * m->dx, m->mua_d, m->g_d, fwd_d, adj_d, nullptr, grad_h_d, dmua_d,
+                       dmus_d);
+    return hipGetLastError() == hipSuccess ? MC_OK : MC_ERR_DEVICE;
+}
+
+mc_status mc_absorbed(const mc_medium *m, const double *coeffs_d, double *h_d, void *stream) {
+    if (!m || m->nx <= 0 || m->nz <= 0 || !m->mua_d || !coeffs_d || !h_d) return MC_ERR_INVALID_ARG;
+    const int npix = m->nx * m->nz;
+    hipLaunchKernelGGL(k_absorbed, dim3((npix + 255) / 256), dim3(256), 0, reinterpret_cast<hipStream_t>(stream), npix,
+                       m->mua_d, coeffs_d, h_d);
+    return hipGetLastError() == hipSuccess ? MC_OK : MC_ERR_DEVICE;
+}
+
+mc_status mc_adjoint_source(const mc_medium *m, const double *grad_h_d, double *q_star_d, void *stream) {
+    if (!m || m->nx <= 0 || m->nz <= 0 || !(m->dx > 0.f) || !m->mua_d || !grad_h_d || !q_star_d)
+        return MC_ERR_INVALID_ARG;
+    const int npix = m->nx * m->nz;
+    hipLaunchKernelGGL(k_adjoint_source, dim3((npix + 255) / 256), dim3(256), 0,
+                       reinterpret_cast<hipStream_t>(stream), npix, 1.0 / ((double)m->dx * m->dx), m->mua_d, grad_h_d,
+                       q_star_d);
     return hipGetLastError() == hipSuccess ? MC_OK : MC_ERR_DEVICE;
 }
 

@@ -62,6 +62,24 @@ class Medium:
                            self.g.data_ptr())
 
 
+@dataclass
+class Source:
+    """A source as the C ABI's mc_source: kind is "pencil", "line", "point" or
+    "map"; positions in mm; map: FP64 [nz][nx] array or device tensor (MAP);
+    prof: angular profile coefficients c0, c1..cn, s1..sn (POINT/MAP)."""
+    kind: str
+    x0: float = 0.0
+    z0: float = 0.0
+    x1: float = 0.0
+    z1: float = 0.0
+    dir_x: float = 0.0
+    dir_z: float = 1.0
+    lambertian: int = 0
+    power: float = 1.0
+    map: Optional[object] = None
+    prof: Optional[object] = None
+
+
 class _Sources:
     """Holds the ctypes source array and every buffer it points to."""
 
@@ -169,6 +187,36 @@ def mc_gradient(medium: Medium, n_harm: int, fwd: torch.Tensor, adj: torch.Tenso
     hm = hmeas.to(torch.float64).contiguous()
     L.check("mc_gradient", lib.mc_gradient(C.byref(medium.c()), int(n_harm), fwd.data_ptr(), adj.data_ptr(),
                                            hm.data_ptr(), dmua.data_ptr(), dmus.data_ptr(), _stream(stream)))
+    return dmua, dmus
+
+
+def mc_absorbed(medium: Medium, coeffs: torch.Tensor, stream=None) -> torch.Tensor:
+    """H = mua a0, float64 [nz][nx]."""
+    lib = L.load()
+    h = torch.empty((medium.nz, medium.nx), dtype=torch.float64, device=coeffs.device)
+    L.check("mc_absorbed", lib.mc_absorbed(C.byref(medium.c()), coeffs.data_ptr(), h.data_ptr(), _stream(stream)))
+    return h
+
+
+def mc_adjoint_source(medium: Medium, grad_h: torch.Tensor, stream=None) -> torch.Tensor:
+    """q* = -mua grad_h / dx^2 for an upstream gradient grad_h = dL/dH."""
+    lib = L.load()
+    g = grad_h.to(torch.float64).contiguous()
+    q = torch.empty((medium.nz, medium.nx), dtype=torch.float64, device=g.device)
+    L.check("mc_adjoint_source", lib.mc_adjoint_source(C.byref(medium.c()), g.data_ptr(), q.data_ptr(),
+                                                       _stream(stream)))
+    return q
+
+
+def mc_gradient_h(medium: Medium, n_harm: int, fwd: torch.Tensor, adj: torch.Tensor, grad_h: torch.Tensor,
+                  stream=None):
+    """(dL/dmua, dL/dmus) per pixel for an upstream gradient grad_h = dL/dH."""
+    lib = L.load()
+    g = grad_h.to(torch.float64).contiguous()
+    dmua = torch.empty((medium.nz, medium.nx), dtype=torch.float64, device=fwd.device)
+    dmus = torch.empty_like(dmua)
+    L.check("mc_gradient_h", lib.mc_gradient_h(C.byref(medium.c()), int(n_harm), fwd.data_ptr(), adj.data_ptr(),
+                                               g.data_ptr(), dmua.data_ptr(), dmus.data_ptr(), _stream(stream)))
     return dmua, dmus
 
 
