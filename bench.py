@@ -28,9 +28,9 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
 # reads for a plain 1 GiB device copy.  Valid only for the kernel source it
 # was measured on: reported as null once that source changes.
 TRAFFIC = {
-    "source_sha256": "be3a874322ad380bc393911db10eb582ef30bb8530e371ed6fa0e5099b50d567",
-    "fetch_kib_per_launch": 1.19375e5, "fetch_factor": 1.990,
-    "write_kib_per_launch": 3.82504e5, "write_factor": 1.000,
+    "source_sha256": "e171396203168ebb3f0d35fee326d7731441e888d9df691b3c4219efe01719dc",
+    "fetch_kib_per_launch": 213458.45, "fetch_factor": 2.000,
+    "write_kib_per_launch": 601734.04, "write_factor": 1.000,
 }
 
 
