@@ -430,6 +430,38 @@ __device__ __forceinline__ void ledger_flush(const Params &P, LedgerRegs &L) {
     }
 }
 
+// Ledger of a whole workgroup (every thread calls it): wave sums, then one
+// set of device atomics per workgroup.
+__device__ __forceinline__ void ledger_flush_block(const Params &P, LedgerRegs &L) {
+    __shared__ double s_v[16][5];
+    __shared__ unsigned long long s_c[16][4];
+    double v[5] = {L.launched, L.absorbed, L.escaped, L.gain, L.loss};
+    unsigned long long c[4] = {L.packets, L.segments, L.visits, L.scatters};
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+        for (int i = 0; i < 5; ++i) v[i] += __shfl_xor(v[i], off);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) c[i] += __shfl_xor(c[i], off);
+    }
+    const int wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    if (__lane_id() == 0) {
+        for (int i = 0; i < 5; ++i) s_v[wave][i] = v[i];
+        for (int i = 0; i < 4; ++i) s_c[wave][i] = c[i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < nw; ++w) {
+            for (int i = 0; i < 5; ++i) v[i] += s_v[w][i];
+            for (int i = 0; i < 4; ++i) c[i] += s_c[w][i];
+        }
+        for (int i = 0; i < 5; ++i)
+            if (v[i] != 0.0) atomicAdd(P.led + i, v[i]);
+        for (int i = 0; i < 4; ++i)
+            if (c[i]) atomicAdd(P.ledc + i, c[i]);
+    }
+}
+
 // ------------------------------------------------------------------ whole-grid transport
 // Small grids: the whole FP64 tally [npix][K] lives in LDS for the
 // workgroup's life (LDS FP64 atomics), flushed to the HBM FP64 tally with
@@ -506,7 +538,7 @@ __global__ void __launch_bounds__(grid_block(NH)) k_transport_grid(Params P) {
 #pragma unroll
         for (int j = 0; j < K; ++j) acc[j] = flush ? 0.f : acc[j];
     }
-    ledger_flush(P, L);
+    ledger_flush_block(P, L);
     __syncthreads();
     for (int i = threadIdx.x; i < P.npix * K; i += blockDim.x) {
         const double v = tally[i];
@@ -620,30 +652,42 @@ __device__ __forceinline__ void slice_finish(const Params &P, QueueSlice &q) {
 }
 
 // Launch n_new packets (ids pid_base..) and append those inside the grid.
+// A grid-stride loop over few workgroups: each iteration reserves queue slots
+// with one atomic per workgroup, and the energy ledger is reduced over the
+// workgroup before its single set of atomics (the ledger and queue counters
+// are single addresses shared by the whole device).
 __global__ void __launch_bounds__(256) k_tile_launch(Params P, uint64_t pid_base, uint32_t n_new) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ uint32_t s_cnt[4];
+    __shared__ uint32_t s_base;
+    const int lane = __lane_id(), wave = threadIdx.x >> 6;
     LedgerRegs L;
-    Packet p;
-    p.alive = false;
-    if (i < n_new) launch_state(P, pid_base + i, p, L);
-    // exact reservation per wave (one atomic per wave of new packets)
-    const unsigned long long m = __ballot(p.alive);
-    if (m) {
-        const int lane = __lane_id();
-        uint32_t base = 0;
-        if (lane == 0) base = atomicAdd(P.qcnt, (uint32_t)__popcll(m));
-        base = __shfl(base, 0);
+    for (uint32_t b0 = blockIdx.x * blockDim.x; b0 < n_new; b0 += gridDim.x * blockDim.x) {
+        const uint32_t i = b0 + threadIdx.x;
+        Packet p;
+        p.alive = false;
+        if (i < n_new) launch_state(P, pid_base + i, p, L);
+        const unsigned long long m = __ballot(p.alive);
+        if (lane == 0) s_cnt[wave] = (uint32_t)__popcll(m);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const uint32_t tot = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+            s_base = tot ? atomicAdd(P.qcnt, tot) : 0u;
+        }
+        __syncthreads();
         if (p.alive) {
-            const uint32_t pos = base + __popcll(m & ((1ull << lane) - 1ull));
+            uint32_t pos = s_base + __popcll(m & ((1ull << lane) - 1ull));
+            for (int w = 0; w < wave; ++w) pos += s_cnt[w];
             if (pos < P.cap_a) {
                 const uint32_t t = tile_of(P, p.ix, p.iz);
                 rec_store(P.qa + pos, p, t, 0u);
                 P.qtile[pos] = t;
+            } else {
+                atomicOr(P.qcnt + 4, 1u);
             }
-            else atomicOr(P.qcnt + 4, 1u);
         }
+        __syncthreads();
     }
-    if (__ballot(i < n_new)) ledger_flush(P, L);
+    ledger_flush_block(P, L);
 }
 
 // Counting sort of the unsorted queue by tile: counts.  Up to kHistTiles
@@ -956,7 +1000,7 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
         __syncthreads();
     }
     slice_finish(P, q);
-    ledger_flush(P, L);
+    ledger_flush_block(P, L);
 }
 
 // ------------------------------------------------------------------ tail finisher
@@ -1057,7 +1101,7 @@ __global__ void __launch_bounds__(kBlockFinish) k_finish(Params P, uint32_t n_re
 #pragma unroll
         for (int j = 0; j < K; ++j) acc[j] = flush ? 0.f : acc[j];
     }
-    ledger_flush(P, L);
+    ledger_flush_block(P, L);
 }
 
 // ------------------------------------------------------------------ trace kernel
@@ -1633,8 +1677,9 @@ mc_status run_tiled(Params &P, const Layout &L, const mc_run *run, char *base, h
         if (carried < L.live) n_new = std::min<uint64_t>(L.live - carried, run->n_packets - launched);
         if (carried == 0 && n_new == 0) break;
         if (n_new) {
-            hipLaunchKernelGGL(k_tile_launch, dim3((unsigned)((n_new + 255) / 256)), dim3(256), 0, s, P,
-                               run->first_packet_id + launched, (uint32_t)n_new);
+            const unsigned lgrid = (unsigned)std::min<uint64_t>((n_new + 255) / 256, 8 * (uint64_t)cus);
+            hipLaunchKernelGGL(k_tile_launch, dim3(lgrid), dim3(256), 0, s, P, run->first_packet_id + launched,
+                               (uint32_t)n_new);
             launched += n_new;
         }
         hipLaunchKernelGGL(k_bin_count, dim3(cgrid), dim3(256), 0, s, P);
