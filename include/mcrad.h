@@ -87,6 +87,10 @@ typedef struct {
 } mc_source;
 
 #define MC_FLAG_LITERAL_TRUNCATION 1u  /* stop below the threshold (Sec. 3) instead of roulette */
+#define MC_FLAG_EQUAL_COUNT 2u         /* MAP source (Sec. 6 read literally): every pixel equally likely and
+                                          the packet weight scaled by q_i / mean |q| (default: pixels drawn
+                                          in proportion to |q_i|, weight sign(q_i)); same normalisation.
+                                          Packets drawn in a pixel with q = 0 carry nothing and end at once */
 
 /* One Monte Carlo run.  Packet p (first_packet_id <= p < first_packet_id +
  * n_packets) draws its random numbers from Philox4x32-10 with key = seed and

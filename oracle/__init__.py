@@ -7,4 +7,5 @@ from .oracle import (  # noqa: F401
     Medium, Source, Run, Ledger, run_mc, trace, residual, gradient, detect,
     philox, philox_fill, u01, hg_dtheta, free_path, build, EV_LAUNCH, EV_CROSS,
     EV_SCATTER, EV_ESCAPE, EV_KILL, PENCIL, LINE, POINT, MAP, medium_from, sources_from,
+    FLAG_LITERAL_TRUNCATION, FLAG_EQUAL_COUNT,
 )

@@ -19,6 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 PENCIL, LINE, POINT, MAP = 0, 1, 2, 3
+FLAG_LITERAL_TRUNCATION, FLAG_EQUAL_COUNT = 1, 2
 EV_LAUNCH, EV_CROSS, EV_SCATTER, EV_ESCAPE, EV_KILL = 0, 1, 2, 3, 4
 
 

@@ -236,20 +236,32 @@ static void run_packet(const or_ctx *c, uint64_t pid, or_sink *k)
         th = OR_PI * (2.0 * u[2] - 1.0);
         sx = sin(th); sz = cos(th);
         W0 = 2.0 * OR_PI * profile_eval(c->prof[s], c->n_prof[s], th);
-    } else {  /* MAP: pixel with probability |q_i| / sum |q|, uniform inside it */
-        double t = u[0] * c->map_cdf[npix - 1];
-        int lo = 0, hi = npix - 1;
-        while (lo < hi) {            /* first i with cdf[i] > t */
-            int mid = (lo + hi) / 2;
-            if (c->map_cdf[mid] > t) hi = mid; else lo = mid + 1;
+    } else {  /* MAP source, uniform position inside the chosen pixel */
+        int lo;
+        double wq;
+        if (run->flags & OR_FLAG_EQUAL_COUNT) {
+            /* Sec. 6 read literally: pixels drawn with equal probability, the
+             * launch weight scaled by the source value (relative to the mean
+             * of |q|, so that the normalisation is the same as below) */
+            lo = (int)floor(u[0] * npix);
+            if (lo > npix - 1) lo = npix - 1;
+            wq = q->map[lo] / (c->map_cdf[npix - 1] / npix);
+        } else {   /* pixel with probability |q_i| / sum |q|, weight sign(q_i) */
+            double t = u[0] * c->map_cdf[npix - 1];
+            int hi = npix - 1;
+            lo = 0;
+            while (lo < hi) {            /* first i with cdf[i] > t */
+                int mid = (lo + hi) / 2;
+                if (c->map_cdf[mid] > t) hi = mid; else lo = mid + 1;
+            }
+            wq = q->map[lo] < 0 ? -1.0 : 1.0;
         }
         int ixs = lo % nx, izs = lo / nx;
         x = (ixs + u[1]) * dx;
         z = (izs + u[2]) * dx;
         th = OR_PI * (2.0 * u[3] - 1.0);
         sx = sin(th); sz = cos(th);
-        double sgn = q->map[lo] < 0 ? -1.0 : 1.0;
-        W0 = sgn * 2.0 * OR_PI * profile_eval(c->prof[0], c->n_prof[0], th);
+        W0 = wq * 2.0 * OR_PI * profile_eval(c->prof[0], c->n_prof[0], th);
     }
     double W = W0, W0abs = fabs(W0);
     k->led.launched += W0;
@@ -258,7 +270,9 @@ static void run_packet(const or_ctx *c, uint64_t pid, or_sink *k)
     int ix, iz;
     locate(m, x, z, sx, sz, &ix, &iz);
     record(k, pid, 0, OR_EV_LAUNCH, ix, iz, x, z, sx, sz, W, 0.0);
-    if (ix < 0 || ix >= nx || iz < 0 || iz >= nz) {
+    /* a packet of zero weight (equal-count launch in a pixel where q = 0)
+     * carries nothing and leaves at once, like one launched outside */
+    if (ix < 0 || ix >= nx || iz < 0 || iz >= nz || ((run->flags & OR_FLAG_EQUAL_COUNT) && W0 == 0.0)) {
         k->led.escaped += W;
         record(k, pid, 0, OR_EV_ESCAPE, ix, iz, x, z, sx, sz, W, 0.0);
         return;
@@ -330,7 +344,7 @@ static void run_packet(const or_ctx *c, uint64_t pid, or_sink *k)
         }
         /* scatter site: termination test first (Sec. 3, Sec. 6: on |W|) */
         if (fabs(W) < run->w_threshold * W0abs) {
-            if ((run->flags & 1u) || !(u[2] < 1.0 / run->roulette_m)) {
+            if ((run->flags & OR_FLAG_LITERAL_TRUNCATION) || !(u[2] < 1.0 / run->roulette_m)) {
                 k->led.roulette_loss += W;
                 k->led.visits += 1;
                 record(k, pid, (int)kk, OR_EV_KILL, ix, iz, x, z, sx, sz, W, T);

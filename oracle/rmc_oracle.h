@@ -30,6 +30,10 @@
  *    counter = (j, stream_tag, pid_lo, pid_hi); block j = 0 launches the packet,
  *    block j = k >= 1 serves the k-th free path (u0), the HG angle at its end
  *    (u1) and the roulette draw there (u2).  u = ((x >> 9) + 1/2) 2^-23.
+ *  - MAP sources (Sec. 6): a pixel is drawn with probability |q_i|/sum|q| and
+ *    the packet carries the sign of q_i; with OR_FLAG_EQUAL_COUNT every pixel
+ *    is equally likely and the packet carries q_i / mean|q| (the literal
+ *    reading); both are normalised by 2 pi sum|q| A.
  *  - Adjoint (Sec. 4, eq. adjoint_RTE1): the adjoint field is the forward
  *    field of the direction-mirrored source, read at the mirrored direction,
  *    so source profiles are mirrored on input and orders n >= 1 of the output
@@ -40,6 +44,8 @@
 #include <stdint.h>
 
 #define OR_MAX_HARM 32
+#define OR_FLAG_LITERAL_TRUNCATION 1u   /* stop below the threshold instead of roulette (Sec. 3) */
+#define OR_FLAG_EQUAL_COUNT 2u          /* MAP source: equal packets per pixel, weight ~ q (Sec. 6 literally) */
 
 typedef struct {
     int nx, nz;
@@ -66,7 +72,7 @@ typedef struct {
     int n_harm;                      /* N: orders 1..N, K = 2N+1 channels */
     double w_threshold;              /* roulette threshold relative to |W0| */
     double roulette_m;               /* survival 1/m, weight times m */
-    uint32_t flags;                  /* bit 0: literal truncation instead of roulette */
+    uint32_t flags;                  /* OR_FLAG_* */
     int adjoint;                     /* 1: adjoint run (mirror source, flip output orders) */
 } or_run;
 

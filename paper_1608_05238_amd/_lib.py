@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(_HERE, "librmc.so")
 MC_OK, MC_ERR_INVALID_ARG, MC_ERR_UNSUPPORTED, MC_ERR_DEVICE, MC_ERR_WORKSPACE = range(5)
 MC_SRC_PENCIL, MC_SRC_LINE, MC_SRC_POINT, MC_SRC_MAP = range(4)
 MC_FLAG_LITERAL_TRUNCATION = 1
+MC_FLAG_EQUAL_COUNT = 2
 MC_NHARM_MAX = 32
 
 # exported symbols declared in include/mcrad.h

@@ -44,7 +44,7 @@ constexpr int kMaxProf = 2 * (2 * MC_NHARM_MAX + 1);  // profile coefficients ov
 // whole-grid mode: 12 waves share one LDS tally (8 for high orders, whose
 // harmonic vectors need more registers)
 constexpr int grid_block(int nh) { return nh <= 16 ? 768 : 512; }
-constexpr int kBlockTile = 384;                        // tiled mode: 6 waves per workgroup, 2 workgroups per CU
+constexpr int kBlockTile = 512;                        // tiled mode: 8 waves per workgroup, 2 workgroups per CU
 constexpr uint64_t kChunk = 1ull << 22;                // whole-grid mode: packets per launch
 constexpr size_t kLdsGridMax = 144 * 1024;             // whole-grid mode: FP64 tally bytes in LDS
 constexpr size_t kLdsTileMax = 72 * 1024;              // tiled mode: tile tally + medium bytes (2 WGs/CU)
@@ -70,6 +70,7 @@ struct Params {
     uint64_t seed, pid0, npk;   // packet range of this launch
     float wth, rm, inv_rm;
     double total;
+    double inv_qbar;            // MAP: npix / sum |q| (equal-count launch)
     const float4 *med;          // {mua dx, mus dx, 1/(mua dx), 1/(mus dx)}
     const float *g;
     const double *map;          // MAP source values (sign)
@@ -145,6 +146,23 @@ struct alignas(16) PacketRec {
     uint32_t spare;
 };
 static_assert(sizeof(PacketRec) == 64, "packet record layout");
+
+// State of a lane without a packet.  Free lanes run the same instructions as
+// busy ones (their results are discarded), so the state must be harmless: a
+// pixel of the grid (or tile) and a finite direction, whose deposits are 0.
+__device__ __forceinline__ void idle_packet(Packet &p, int ix, int iz) {
+    p.ix = ix;
+    p.iz = iz;
+    p.fx = p.fz = 0.5f;
+    p.sx = 0.f;
+    p.sz = 1.f;
+    p.isx = INFINITY;
+    p.isz = 1.f;
+    p.w = p.w0abs = p.tau = p.uh = p.ur = 0.f;
+    p.k = 0;
+    p.pid = 0;
+    p.alive = false;
+}
 
 struct LedgerRegs {
     double launched = 0, absorbed = 0, escaped = 0, gain = 0, loss = 0;
@@ -259,18 +277,27 @@ __device__ bool launch_state(const Params &P, uint64_t pid, Packet &p, LedgerReg
         az = S.z0 / (double)P.dx;
         sincospif(2.f * u2 - 1.f, &sx, &sz);
         w0 = 2.f * kPi * profile(P, S, sx, sz);
-    } else {   // MAP: pixel with probability |q_i| / sum |q|, uniform inside it
-        const double t = (double)u0 * P.cdf[P.npix - 1];
-        int lo = 0, hi = P.npix - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (P.cdf[mid] > t) hi = mid; else lo = mid + 1;
+    } else {   // MAP source, uniform position inside the chosen pixel (Sec. 6)
+        int lo;
+        float wq;
+        if (P.flags & MC_FLAG_EQUAL_COUNT) {   // every pixel equally likely, weight q_i / mean |q|
+            lo = min((int)((double)u0 * P.npix), P.npix - 1);
+            wq = (float)(P.map[lo] * P.inv_qbar);
+        } else {   // pixel with probability |q_i| / sum |q|, weight sign(q_i)
+            const double t = (double)u0 * P.cdf[P.npix - 1];
+            int hi = P.npix - 1;
+            lo = 0;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (P.cdf[mid] > t) hi = mid; else lo = mid + 1;
+            }
+            wq = P.map[lo] < 0.0 ? -1.f : 1.f;
         }
         const int ixs = lo % P.nx, izs = lo / P.nx;
         ax = ixs + (double)u1;
         az = izs + (double)u2;
         sincospif(2.f * u3 - 1.f, &sx, &sz);
-        w0 = (P.map[lo] < 0.0 ? -2.f : 2.f) * kPi * profile(P, S, sx, sz);
+        w0 = wq * 2.f * kPi * profile(P, S, sx, sz);
     }
     p.pid = pid;
     p.k = 1;
@@ -281,7 +308,9 @@ __device__ bool launch_state(const Params &P, uint64_t pid, Packet &p, LedgerReg
     L.packets += 1;
     locate1(ax, P.nx, sx, p.ix, p.fx);
     locate1(az, P.nz, sz, p.iz, p.fz);
-    if (p.ix < 0 || p.ix >= P.nx || p.iz < 0 || p.iz >= P.nz) {
+    // a packet of zero weight (equal-count launch where q = 0) carries nothing
+    // and leaves at once, like one launched outside the grid
+    if (p.ix < 0 || p.ix >= P.nx || p.iz < 0 || p.iz >= P.nz || ((P.flags & MC_FLAG_EQUAL_COUNT) && w0 == 0.f)) {
         L.escaped += w0;
         p.alive = false;
         return false;
@@ -404,6 +433,32 @@ __device__ __forceinline__ bool scatter(const Params &P, Packet &p, const float 
     return true;
 }
 
+// acc += T [1, cos t .. cos Nt, sin t .. sin Nt] with the harmonic values
+// generated on the fly by the same recurrence as harmonics(): the transport
+// loop would recompute the vector for nearly every iteration anyway (some lane
+// of the wave scatters), so not storing it saves 2N+1 registers per lane.
+template <int NH>
+__device__ __forceinline__ void deposit_harmonics(float T, float sx, float sz, float *acc) {
+    acc[0] += T;
+    if constexpr (NH >= 1) {
+        acc[1] = fmaf(T, sz, acc[1]);
+        acc[NH + 1] = fmaf(T, sx, acc[NH + 1]);
+    }
+    const float c2 = 2.f * sz;
+    float cm = 1.f, sm = 0.f, cn = sz, sn = sx;
+#pragma unroll
+    for (int n = 2; n <= NH; ++n) {
+        const float c = n == 2 ? fmaf(c2, sz, -1.f) : fmaf(c2, cn, -cm);
+        const float s_ = n == 2 ? c2 * sx : fmaf(c2, sn, -sm);
+        cm = cn;
+        sm = sn;
+        cn = c;
+        sn = s_;
+        acc[n] = fmaf(T, c, acc[n]);
+        acc[NH + n] = fmaf(T, s_, acc[NH + n]);
+    }
+}
+
 // Recompute the harmonic vector when any lane of the wave changed direction.
 // Every lane recomputes: h is a pure function of the direction, so lanes
 // whose direction did not change get the same values back, and no select
@@ -476,7 +531,7 @@ __global__ void __launch_bounds__(grid_block(NH)) k_transport_grid(Params P) {
     __syncthreads();
 
     Packet p;
-    p.alive = false;
+    idle_packet(p, 0, 0);
     float h[K], acc[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) {
@@ -852,7 +907,7 @@ __global__ void __launch_bounds__(256) k_bin_scatter(Params P) {
 }
 
 template <int NH>
-__global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu(NH <= 16 ? 3 : 2))) k_transport_tile(Params P) {
+__global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu(NH <= 16 ? 4 : 2))) k_transport_tile(Params P) {
     constexpr int K = 2 * NH + 1;
     extern __shared__ double tally[];                  // [tw*th][K]
     float4 *smed = reinterpret_cast<float4 *>(tally + (((size_t)P.tw * P.th * K + 1) & ~size_t(1)));
@@ -890,17 +945,14 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
         __syncthreads();
 
         Packet p;
-        p.alive = false;
+        idle_packet(p, tx0, tz0);
         uint32_t nvis = 0;
-        float h[K], acc[K];
+        float acc[K];
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
-            h[j] = 0.f;
-            acc[j] = 0.f;
-        }
+        for (int j = 0; j < K; ++j) acc[j] = 0.f;
         // Each lane holds the record of its next packet in registers, loaded
         // one whole stay ahead, so a refill never waits for memory.
-        bool more = true, dirty = false, has_next = false;
+        bool more = true, has_next = false;
         uint32_t tail_nvis = 0;   // visits of the current stay when the job ran out of packets
         uint4 nr0 = make_uint4(0u, 0u, 0u, 0u), nr1 = nr0, nr2 = nr0, nr3 = nr0;
         for (;;) {
@@ -910,7 +962,6 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
                 has_next = false;
                 nvis = 0;
                 tail_nvis = 0;
-                dirty = true;
             }
             // lanes without a prefetched record claim the next ones of the job
             if (more) {
@@ -941,8 +992,6 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
             if (!__ballot(p.alive)) {
                 if (!more && !__ballot(has_next)) break;
             }
-            refresh_harmonics<NH>(dirty, p, h);
-            dirty = false;
             // every lane steps (no branch); a free lane's result is discarded
             const bool live = p.alive;
             const int lp = live ? (p.iz - tz0) * P.tw + (p.ix - tx0) : 0;
@@ -953,11 +1002,9 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
             dw = live ? dw : 0.f;
             L.absorbed += (double)dw;
             L.segments += live ? 1u : 0u;
-#pragma unroll
-            for (int j = 0; j < K; ++j) acc[j] = fmaf(T, h[j], acc[j]);
+            deposit_harmonics<NH>(T, p.sx, p.sz, acc);   // direction of the segment, before any scatter
             const bool at = ev == EV_SCATTER;
             const bool killed = scatter_masked(P, p, at, sg[lp], L);
-            dirty = at && !killed;
             const bool flush = killed || (ev != EV_NONE && !at);
             if (ev == EV_ESCAPE) {
                 L.escaped += p.w;
@@ -1022,7 +1069,7 @@ __global__ void __launch_bounds__(kBlockFinish) k_finish(Params P, uint32_t n_re
     const unsigned long long lt_mask = (1ull << lane) - 1ull;
     LedgerRegs L;
     Packet p;
-    p.alive = false;
+    idle_packet(p, 0, 0);
     float h[K], acc[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) {
@@ -1474,6 +1521,7 @@ mc_status validate(const mc_medium *m, const mc_source *src, int n_src, const mc
     if ((int64_t)m->nx * m->nz > (1 << 26)) return MC_ERR_UNSUPPORTED;
     if (run->n_harm < 0 || run->n_harm > MC_NHARM_MAX || run->n_packets == 0) return MC_ERR_INVALID_ARG;
     if (!(run->roulette_m > 1.f) || !(run->w_threshold >= 0.f)) return MC_ERR_INVALID_ARG;
+    if (run->flags & ~(MC_FLAG_LITERAL_TRUNCATION | MC_FLAG_EQUAL_COUNT)) return MC_ERR_INVALID_ARG;
     if (n_src < 1 || n_src > kMaxSrc) return MC_ERR_INVALID_ARG;
     const double W = (double)m->nx * m->dx, H = (double)m->nz * m->dx;
     const double tx = boundary_snap(m->nx) * m->dx, tz = boundary_snap(m->nz) * m->dx;
@@ -1555,7 +1603,10 @@ void fill_params(Params &P, const mc_medium *m, const mc_source *src, int n_src,
         d.cum = total;
     }
     P.total = total;
-    if (n_src == 1 && src[0].kind == MC_SRC_MAP) P.map = src[0].map_d;
+    if (n_src == 1 && src[0].kind == MC_SRC_MAP) {
+        P.map = src[0].map_d;
+        P.inv_qbar = map_abs_sum > 0 ? (double)P.npix / map_abs_sum : 0.0;
+    }
 }
 
 int occupancy_blocks(const void *fn, int block, size_t lds) {

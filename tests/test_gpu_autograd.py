@@ -42,7 +42,8 @@ def test_eps_gradient_equals_the_residual_adjoint_chain():
     mua = med.mua.double().clone().requires_grad_(True)
     mus = med.mus.double().clone().requires_grad_(True)
     h = A.absorbed_energy(mua, mus, med.g, med.dx, src, A.MCConfig(n, N, seed=seed))
-    np.testing.assert_allclose(h.detach().cpu().numpy(), (med.mua.double() * f[0]).cpu().numpy(), rtol=1e-15)
+    # two runs of the same packets: equal up to the order of the FP64 tally additions
+    np.testing.assert_allclose(h.detach().cpu().numpy(), (med.mua.double() * f[0]).cpu().numpy(), rtol=1e-12)
     A.error_functional(h, hm, med.dx).backward()
     for got, ref in ((mua.grad, ga), (mus.grad, gs)):
         rel = float((got - ref).norm() / ref.norm())

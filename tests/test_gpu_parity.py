@@ -338,6 +338,39 @@ def test_literal_truncation_flag():
     assert led["roulette_gain"] == 0 and led["roulette_loss"] > 0
 
 
+def test_equal_count_map_launch():
+    """Adjoint run with the literal Sec. 6 launch (equal packets per pixel,
+    weight ~ q_i), including pixels where q = 0, against the oracle."""
+    rmc = _rmc()
+    O = _oracle()
+    ph = P.disc_phantom(40, 0.25, 0.03, 6.0, 0.85, seed=6, radius=(1.0, 2.0))
+    q = P.residual_like_map(ph, seed=2)
+    q[:8, :] = 0.0
+    specs = [P.map_source(q)]
+    n = 40_000
+    gpu, led = _gpu_run(rmc, ph, specs, n, 8, seed=13, adjoint=True, tag=1, flags=2)
+    ora, se = _oracle_batches(O, ph, specs, n, 8, B=8, seed=13, adjoint=True, tag=1, flags=2)
+    _assert_maps("equal_count_adjoint", gpu, ora, se)
+    bal = led["launched"] + led["roulette_gain"] - led["roulette_loss"] - led["absorbed"] - led["escaped"]
+    assert abs(bal) < 1e-5 * abs(led["launched"]) + 1e-6 * n
+
+
+def test_anisotropic_point_source_sin2_2theta():
+    """The anisotropic source of the adjoint validation (Sec. 4.1):
+    p(t) = sin^2(2t)/pi = 1/2pi - cos(4t)/2pi, i.e. c0 = 1, c4 = -1/2."""
+    rmc = _rmc()
+    O = _oracle()
+    ph = P.homogeneous(32, 32, 0.25, 0.05, 8.0, 0.8)
+    prof = np.zeros(2 * 4 + 1)
+    prof[0], prof[4] = 1.0, -0.5
+    specs = [P.point_source(4.03, 3.97, prof=prof)]
+    n = 40_000
+    for adj, tag in ((False, 0), (True, 1)):
+        gpu, _ = _gpu_run(rmc, ph, specs, n, 8, seed=17, adjoint=adj, tag=tag)
+        ora, se = _oracle_batches(O, ph, specs, n, 8, B=8, seed=17, adjoint=adj, tag=tag)
+        _assert_maps(f"sin2_2theta_{'adj' if adj else 'fwd'}", gpu, ora, se)
+
+
 # ---------------------------------------------------------------- FP64 post-processing
 def test_residual_gradient_detect_fp64():
     import torch

@@ -58,7 +58,7 @@ def _pencil(L):
     return s
 
 
-@pytest.mark.parametrize("bad", ["nx", "harm", "packets", "power", "outside", "dir", "roulette", "nsrc"])
+@pytest.mark.parametrize("bad", ["nx", "harm", "packets", "power", "outside", "dir", "roulette", "nsrc", "flags"])
 def test_invalid_arguments_rejected_on_host(bad):
     """Every check runs before any HIP call, so these need no GPU."""
     L, lib = _lib()
@@ -82,6 +82,8 @@ def test_invalid_arguments_rejected_on_host(bad):
         run.roulette_m = 1.0
     elif bad == "nsrc":
         n_src = 9
+    elif bad == "flags":
+        run.flags = 4
     assert lib.mc_workspace_bytes(C.byref(m), src, n_src, C.byref(run)) == 0
     rc = lib.mc_forward(C.byref(m), src, n_src, C.byref(run), 0x2000, None, 0x3000, 1 << 30, None)
     assert rc == L.MC_ERR_INVALID_ARG

@@ -492,3 +492,33 @@ def test_side_sources_deliver_equal_power(oracle_lib):
     vals = np.array(vals)
     assert np.all(vals > 0.05)
     assert vals.max() - vals.min() < 0.1 * vals.mean(), vals
+
+
+def test_equal_count_map_launch_is_unbiased(oracle_lib):
+    """Sec. 6 read literally (every pixel equally likely, launch weight ~ q_i)
+    and the importance-sampled launch (pixels ~ |q_i|, weight sign q_i) are two
+    unbiased estimators of the same field: their maps agree within the
+    combined standard error, and both ledgers balance.  A wrong weight scale
+    in the equal-count branch (e.g. a missing 1/mean|q|) fails this."""
+    O = oracle_lib
+    ph = P.disc_phantom(16, 0.5, 0.05, 4.0, 0.7, seed=8, radius=(1.0, 2.0))
+    q = P.residual_like_map(ph, seed=5)
+    q[:4, :] = 0.0                                   # pixels with no source at all
+    med, src = O.medium_from(ph), O.sources_from([P.map_source(q)])
+    outs = {0: [], O.FLAG_EQUAL_COUNT: []}
+    for flag in outs:
+        for b in range(8):
+            r = O.Run(20_000, 40 + b, 3, stream_tag=1, adjoint=1, flags=flag)
+            m, led = O.run_mc(med, src, r, n_threads=8)
+            bal = led.launched + led.roulette_gain - led.roulette_loss - led.absorbed - led.escaped
+            assert abs(bal) < 1e-9 * max(abs(led.launched), 1.0)
+            outs[flag].append(m)
+    a, b = np.array(outs[0]), np.array(outs[O.FLAG_EQUAL_COUNT])
+    ma, mb = a.mean(0), b.mean(0)
+    se = np.sqrt(a.var(0, ddof=1) / len(a) + b.var(0, ddof=1) / len(b))
+    big = np.abs(ma[0]) > 0.05 * np.abs(ma[0]).max()
+    z = np.abs(ma - mb)[:, big] / np.maximum(se[:, big], 1e-300)
+    assert np.mean(z < 3) > 0.98 and np.max(z) < 6, (np.mean(z < 3), np.max(z))
+    # the summed absorbed power agrees too (a global check of the normalisation)
+    pa, pb = (ph.mua * a[:, 0]).sum((1, 2)), (ph.mua * b[:, 0]).sum((1, 2))
+    assert abs(pa.mean() - pb.mean()) < 3 * np.sqrt(pa.var(ddof=1) / 8 + pb.var(ddof=1) / 8)
