@@ -215,6 +215,32 @@ mc_status mc_trace(const mc_medium *medium, const mc_source *src, int n_src, con
 mc_status mc_philox_fill(uint64_t seed, uint32_t tag, uint64_t pid0, uint64_t n, uint32_t j,
                          uint32_t *out_d, void *stream);
 
+/* Tuning of the tiled transport (grids whose FP64 tally exceeds one
+ * workgroup's LDS).  Process-wide; a run uses the values current when its
+ * layout is computed (mc_workspace_bytes, mc_forward, mc_adjoint), so call
+ * mc_workspace_bytes again after a change (live_packets sizes the queues).
+ * Results do not depend on these values beyond the order of FP64 additions.
+ *  live_packets   packets kept alive per generation, 1024 .. 2^26
+ *  job_packets    packets of one tile handed to one workgroup, 64 .. 2^20
+ *  max_visits     visits in one tile before a packet pauses until the next
+ *                 generation, >= 1
+ *  tile           tile side in pixels, 0 .. 256 (0, or a tile whose tally does
+ *                 not fit: the largest square tile that fits two workgroups
+ *                 per CU)
+ *  finish_packets once every packet is launched and at most this many remain
+ *                 they finish without migration (0: live_packets / 128)
+ * mc_set_tuning(NULL) restores the built-in defaults. */
+typedef struct {
+    uint64_t live_packets;
+    uint32_t job_packets;
+    uint32_t max_visits;
+    uint32_t tile;
+    uint32_t reserved;
+    uint64_t finish_packets;
+} mc_tuning;
+mc_status mc_set_tuning(const mc_tuning *tuning_h);
+mc_status mc_get_tuning(mc_tuning *tuning_h);
+
 /* Timing of the transport kernel launches: when enabled, every transport
  * launch made by mc_forward / mc_adjoint is bracketed by two HIP events
  * recorded on the caller's stream.  mc_profile_read waits for the pending

@@ -20,7 +20,7 @@ MC_NHARM_MAX = 32
 # exported symbols declared in include/mcrad.h
 SYMBOLS = ("mc_workspace_bytes", "mc_forward", "mc_adjoint", "mc_residual", "mc_gradient", "mc_absorbed",
            "mc_adjoint_source", "mc_gradient_h", "mc_detect", "mc_trace", "mc_philox_fill", "mc_profile_enable",
-           "mc_profile_read", "mc_status_string", "mc_build_info")
+           "mc_profile_read", "mc_set_tuning", "mc_get_tuning", "mc_status_string", "mc_build_info")
 
 
 class mc_medium(C.Structure):
@@ -52,6 +52,11 @@ class mc_event(C.Structure):
     _fields_ = [("pid", C.c_uint64), ("k", C.c_int32), ("type", C.c_int32), ("ix", C.c_int32),
                 ("iz", C.c_int32), ("x", C.c_float), ("z", C.c_float), ("sx", C.c_float),
                 ("sz", C.c_float), ("w", C.c_float), ("t", C.c_float)]
+
+
+class mc_tuning(C.Structure):
+    _fields_ = [("live_packets", C.c_uint64), ("job_packets", C.c_uint32), ("max_visits", C.c_uint32),
+                ("tile", C.c_uint32), ("reserved", C.c_uint32), ("finish_packets", C.c_uint64)]
 
 
 _lib = None
@@ -93,6 +98,10 @@ def load() -> C.CDLL:
     lib.mc_profile_enable.restype = None
     lib.mc_profile_read.argtypes = [P(C.c_double), P(C.c_uint64), C.c_int]
     lib.mc_profile_read.restype = St
+    lib.mc_set_tuning.argtypes = [P(mc_tuning)]
+    lib.mc_set_tuning.restype = St
+    lib.mc_get_tuning.argtypes = [P(mc_tuning)]
+    lib.mc_get_tuning.restype = St
     lib.mc_status_string.argtypes = [C.c_int]
     lib.mc_status_string.restype = C.c_char_p
     lib.mc_build_info.argtypes = []

@@ -1,0 +1,131 @@
+"""Autotuner of the tiled transport: live packets, job size, visits per stay
+and tile side.
+
+`tune()` times short forward (or adjoint) runs of the caller's problem over a
+set of candidate tunings, keeps the fastest, applies it with mc_set_tuning
+and records it in an optional JSON cache keyed by grid size, harmonic order
+and run kind.  The tuning changes only the schedule (which packets move
+together, how often they are sorted); the result of a run is the same up to
+the order of the FP64 tally additions.
+
+    python -m paper_1608_05238_amd.autotune      # tune the 256x256 disc workload
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import os
+import sys
+from typing import Iterable, Optional, Sequence
+
+import torch
+
+from . import rmc
+
+DEFAULT_CANDIDATES = {
+    "live_packets": (1 << 23, 1 << 24),
+    "job_packets": (2048, 4096, 8192),
+    "max_visits": (16, 32, 64),
+    "tile": (0, 12),
+}
+
+
+def candidates(space: Optional[dict] = None) -> Iterable[dict]:
+    space = space or DEFAULT_CANDIDATES
+    keys = list(space)
+    for vals in itertools.product(*(space[k] for k in keys)):
+        yield dict(zip(keys, vals))
+
+
+def _key(medium: rmc.Medium, n_harm: int, adjoint: bool) -> str:
+    return f"{medium.nx}x{medium.nz}_N{n_harm}_{'adjoint' if adjoint else 'forward'}"
+
+
+def time_run(medium: rmc.Medium, sources: Sequence, n_harm: int, n_packets: int, adjoint: bool = False,
+             seed: int = 0) -> float:
+    """Seconds of one run (HIP events on the current stream); the workspace is
+    sized for the tuning in force."""
+    fn = rmc.mc_adjoint if adjoint else rmc.mc_forward
+    run = rmc.make_run(n_packets, n_harm, seed=seed, stream_tag=1 if adjoint else 0)
+    ws = torch.empty(rmc.mc_workspace_bytes(medium, sources, run) + 256, dtype=torch.uint8,
+                     device=medium.mua.device)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    fn(medium, sources, run, workspace=ws, ledger=False)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) * 1e-3
+
+
+def tune(medium: rmc.Medium, sources: Sequence, n_harm: int, trial_packets: int = 10_000_000,
+         adjoint: bool = False, space: Optional[dict] = None, cache_path: Optional[str] = None, log=None) -> dict:
+    """Pick the fastest tuning for this problem, apply it and return
+    {"tuning": ..., "packets_per_s": ..., "trials": [...]}."""
+    key = _key(medium, n_harm, adjoint)
+    cache = {}
+    if cache_path and os.path.exists(cache_path):
+        with open(cache_path) as f:
+            cache = json.load(f)
+        if key in cache:
+            rmc.mc_set_tuning(cache[key]["tuning"])
+            return cache[key]
+    base = rmc.mc_get_tuning()
+    trials = []
+    time_run(medium, sources, n_harm, min(trial_packets, 1_000_000), adjoint)   # warm-up (code, caches)
+    for cand in candidates(space):
+        rmc.mc_set_tuning({**base, **cand})
+        t = time_run(medium, sources, n_harm, trial_packets, adjoint, seed=1)
+        trials.append({"tuning": {**base, **cand}, "packets_per_s": trial_packets / t})
+        if log:
+            log(f"{cand}: {trial_packets / t:.4e} packets/s")
+    best = max(trials, key=lambda r: r["packets_per_s"])
+    rmc.mc_set_tuning(best["tuning"])
+    out = {"tuning": best["tuning"], "packets_per_s": best["packets_per_s"], "trials": trials}
+    if cache_path:
+        cache[key] = {"tuning": best["tuning"], "packets_per_s": best["packets_per_s"]}
+        with open(cache_path, "w") as f:
+            json.dump(cache, f, indent=1)
+    return out
+
+
+def main(argv=None) -> int:
+    import argparse
+    import numpy as np
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--dx", type=float, default=0.1)
+    ap.add_argument("--trial-packets", type=float, default=1e7)
+    ap.add_argument("--adjoint", action="store_true")
+    ap.add_argument("--cache", default=None)
+    args = ap.parse_args(argv)
+    dev = torch.device("cuda", 0)
+    n, dx = args.n, args.dx
+    L = n * dx
+    rng = np.random.default_rng(0)
+    mua = np.full((n, n), 0.01, np.float32)
+    mus = np.full((n, n), 10.0, np.float32)
+    c = (np.arange(n) + 0.5) * dx
+    X, Z = np.meshgrid(c, c)
+    for _ in range(4):
+        r = rng.uniform(1, 4)
+        cx, cz = rng.uniform(r, L - r, 2)
+        inside = (X - cx) ** 2 + (Z - cz) ** 2 <= r * r
+        mua[inside] *= rng.uniform(2, 10)
+        mus[inside] *= rng.uniform(0.5, 2)
+    med = rmc.Medium(torch.as_tensor(mua, device=dev), torch.as_tensor(mus, device=dev),
+                     torch.full((n, n), 0.9, dtype=torch.float32, device=dev), dx)
+    if args.adjoint:
+        q = torch.as_tensor(np.sin(X / 3.0) * np.cos(Z / 5.0) * 1e-3, device=dev)
+        src = [rmc.Source("map", map=q)]
+    else:
+        src = [rmc.Source("line", 0.0, 0.0, L, 0.0, 0.0, 1.0, 0, 0.25), rmc.Source("line", 0.0, L, L, L, 0.0, -1.0, 0, 0.25),
+               rmc.Source("line", 0.0, 0.0, 0.0, L, 1.0, 0.0, 0, 0.25), rmc.Source("line", L, 0.0, L, L, -1.0, 0.0, 0, 0.25)]
+    res = tune(med, src, 16, int(args.trial_packets), args.adjoint, cache_path=args.cache,
+               log=lambda m: print(m, file=sys.stderr, flush=True))
+    print(json.dumps({"best": res["tuning"], "packets_per_s": res["packets_per_s"],
+                      "trials": len(res.get("trials", []))}), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

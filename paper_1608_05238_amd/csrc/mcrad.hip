@@ -1418,32 +1418,44 @@ constexpr uint32_t kJobSize = 4096;           // packets per job
 constexpr uint32_t kMaxVisitsPerStay = 32;    // a packet pauses after this many visits in one job
 constexpr int kTileWavesMax = 256 * 16;       // bound on resident waves of the tiled kernel
 
-// Tuning knobs of the tiled mode, overridable through the environment
-// (RMC_LIVE, RMC_JOB, RMC_MAXVIS, RMC_TAILVIS, RMC_TILE, RMC_FINISH) for measurement sweeps.
+// Tuning knobs of the tiled mode.  Process-wide; set through mc_set_tuning()
+// (the autotuner) and initialised from the environment (RMC_LIVE, RMC_JOB,
+// RMC_MAXVIS, RMC_TAILVIS, RMC_TILE, RMC_FINISH) for measurement sweeps.  A
+// run takes one snapshot when its layout is computed.
 struct TileTuning {
     uint64_t live = kLiveMax;
     uint32_t job = kJobSize, maxvis = kMaxVisitsPerStay, tailvis = 1u << 30;
     uint64_t finish = 0;   // 0: live / 128
     int tile = 0;   // 0: largest square tile for two workgroups per CU
 };
-const TileTuning &tile_tuning() {
-    static TileTuning t = [] {
-        TileTuning v;
-        auto get = [](const char *n, uint64_t lo, uint64_t hi, uint64_t def) {
-            const char *e = std::getenv(n);
-            if (!e) return def;
-            const unsigned long long x = std::strtoull(e, nullptr, 10);
-            return (x >= lo && x <= hi) ? (uint64_t)x : def;
-        };
-        v.live = get("RMC_LIVE", 1024, 1ull << 26, v.live);
-        v.job = (uint32_t)get("RMC_JOB", 64, 1u << 20, v.job);
-        v.maxvis = (uint32_t)get("RMC_MAXVIS", 1, 1u << 30, v.maxvis);
-        v.tailvis = (uint32_t)get("RMC_TAILVIS", 1, 1u << 30, v.tailvis);
-        v.tile = (int)get("RMC_TILE", 1, 256, 0);
-        v.finish = get("RMC_FINISH", 1, 1ull << 26, 0);
-        return v;
-    }();
-    return t;
+TileTuning tuning_from_env() {
+    TileTuning v;
+    auto get = [](const char *n, uint64_t lo, uint64_t hi, uint64_t def) {
+        const char *e = std::getenv(n);
+        if (!e) return def;
+        const unsigned long long x = std::strtoull(e, nullptr, 10);
+        return (x >= lo && x <= hi) ? (uint64_t)x : def;
+    };
+    v.live = get("RMC_LIVE", 1024, 1ull << 26, v.live);
+    v.job = (uint32_t)get("RMC_JOB", 64, 1u << 20, v.job);
+    v.maxvis = (uint32_t)get("RMC_MAXVIS", 1, 1u << 30, v.maxvis);
+    v.tailvis = (uint32_t)get("RMC_TAILVIS", 1, 1u << 30, v.tailvis);
+    v.tile = (int)get("RMC_TILE", 1, 256, 0);
+    v.finish = get("RMC_FINISH", 1, 1ull << 26, 0);
+    return v;
+}
+struct TuningState {
+    std::mutex mu;
+    TileTuning t = tuning_from_env();
+};
+TuningState &tuning_state() {
+    static TuningState s;
+    return s;
+}
+TileTuning tuning_snapshot() {
+    TuningState &s = tuning_state();
+    std::lock_guard<std::mutex> g(s.mu);
+    return s.t;
 }
 
 struct Layout {
@@ -1453,6 +1465,7 @@ struct Layout {
     int tw, th, ntx, ntz, ntiles;
     uint64_t live, cap_a, max_jobs;
     size_t tile_lds;
+    TileTuning tt;   // the tuning this layout was computed with
 };
 
 size_t tile_lds_bytes(int tw, int th, int K) {
@@ -1462,6 +1475,7 @@ size_t tile_lds_bytes(int tw, int th, int K) {
 
 Layout layout(const mc_medium *m, const mc_source *src, const mc_run *run) {
     Layout L{};
+    L.tt = tuning_snapshot();
     const size_t npix = (size_t)m->nx * m->nz;
     const int K = 2 * run->n_harm + 1;
     L.tiled = npix * K * sizeof(double) > kLdsGridMax;
@@ -1483,17 +1497,16 @@ Layout layout(const mc_medium *m, const mc_source *src, const mc_run *run) {
     } else {
         int t = 1;
         while (tile_lds_bytes(t + 1, t + 1, K) <= kLdsTileMax) ++t;
-        if (tile_tuning().tile && tile_lds_bytes(tile_tuning().tile, tile_tuning().tile, K) <= kLdsTileMax)
-            t = tile_tuning().tile;
+        if (L.tt.tile && tile_lds_bytes(L.tt.tile, L.tt.tile, K) <= kLdsTileMax) t = L.tt.tile;
         L.tw = std::min(t, m->nx);
         L.th = std::min(t, m->nz);
         L.ntx = (m->nx + L.tw - 1) / L.tw;
         L.ntz = (m->nz + L.th - 1) / L.th;
         L.ntiles = L.ntx * L.ntz;
         L.tile_lds = tile_lds_bytes(L.tw, L.th, K);
-        L.live = std::min<uint64_t>(run->n_packets, tile_tuning().live);
+        L.live = std::min<uint64_t>(run->n_packets, L.tt.live);
         L.cap_a = 2 * L.live + (uint64_t)kSlice * kTileWavesMax + 64ull * 64;
-        L.max_jobs = L.ntiles + L.live / tile_tuning().job + 2;
+        L.max_jobs = L.ntiles + L.live / L.tt.job + 2;
         L.counters = off;
         off = align_up(off + 8 * sizeof(unsigned long long));
         L.qcnt = off;
@@ -1712,15 +1725,15 @@ mc_status run_tiled(Params &P, const Layout &L, const mc_run *run, char *base, h
     P.jobs = reinterpret_cast<uint4 *>(base + L.jobs);
     P.cap_a = (uint32_t)L.cap_a;
     P.cap_b = (uint32_t)L.live;
-    P.job_size = tile_tuning().job;
-    P.max_visits = tile_tuning().maxvis;
-    P.tail_visits = tile_tuning().tailvis;
+    P.job_size = L.tt.job;
+    P.max_visits = L.tt.maxvis;
+    P.tail_visits = L.tt.tailvis;
     const unsigned bgrid = (unsigned)std::min<uint64_t>((L.cap_a + 255) / 256, 4096);
     const unsigned cgrid = (unsigned)std::min<uint64_t>((L.cap_a + 255) / 256, 4 * (uint64_t)cus);
     static thread_local uint32_t *host_cnt = nullptr;
     if (!host_cnt && hipHostMalloc(reinterpret_cast<void **>(&host_cnt), 8 * sizeof(uint32_t)) != hipSuccess)
         return MC_ERR_DEVICE;
-    const uint64_t finish_at = tile_tuning().finish ? tile_tuning().finish : L.live / 128;
+    const uint64_t finish_at = L.tt.finish ? L.tt.finish : L.live / 128;
     uint64_t launched = 0, carried = 0;
     for (uint64_t gen = 0;; ++gen) {
         if (gen > (1ull << 32)) return MC_ERR_DEVICE;
@@ -1977,6 +1990,35 @@ void mc_profile_enable(int on) {
     Profile &pr = profile_state();
     std::lock_guard<std::mutex> g(pr.mu);
     pr.on = on != 0;
+}
+
+mc_status mc_set_tuning(const mc_tuning *t) {
+    TileTuning v;   // defaults
+    if (t) {
+        if (t->live_packets < 1024 || t->live_packets > (1ull << 26) || t->job_packets < 64 ||
+            t->job_packets > (1u << 20) || t->max_visits < 1 || t->tile > 256 || t->finish_packets > (1ull << 26))
+            return MC_ERR_INVALID_ARG;
+        v.live = t->live_packets;
+        v.job = t->job_packets;
+        v.maxvis = t->max_visits;
+        v.tile = (int)t->tile;
+        v.finish = t->finish_packets;
+    }
+    TuningState &s = tuning_state();
+    std::lock_guard<std::mutex> g(s.mu);
+    s.t = v;
+    return MC_OK;
+}
+
+mc_status mc_get_tuning(mc_tuning *t) {
+    if (!t) return MC_ERR_INVALID_ARG;
+    const TileTuning v = tuning_snapshot();
+    t->live_packets = v.live;
+    t->job_packets = v.job;
+    t->max_visits = v.maxvis;
+    t->tile = (uint32_t)v.tile;
+    t->finish_packets = v.finish;
+    return MC_OK;
 }
 
 mc_status mc_profile_read(double *transport_ms, uint64_t *launches, int reset) {

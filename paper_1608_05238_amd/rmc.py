@@ -269,5 +269,28 @@ def mc_profile_read(reset: bool = True):
     return ms.value, n.value
 
 
+_TUNING_FIELDS = ("live_packets", "job_packets", "max_visits", "tile", "finish_packets")
+
+
+def mc_get_tuning() -> dict:
+    """Current tiled-transport tuning (see mc_tuning in include/mcrad.h)."""
+    t = L.mc_tuning()
+    L.check("mc_get_tuning", L.load().mc_get_tuning(C.byref(t)))
+    return {f: getattr(t, f) for f in _TUNING_FIELDS}
+
+
+def mc_set_tuning(tuning: Optional[dict] = None) -> None:
+    """Set the tiled-transport tuning; None restores the built-in defaults."""
+    lib = L.load()
+    if tuning is None:
+        L.check("mc_set_tuning", lib.mc_set_tuning(None))
+        return
+    t = L.mc_tuning()
+    cur = mc_get_tuning()
+    for f in _TUNING_FIELDS:
+        setattr(t, f, int(tuning.get(f, cur[f])))
+    L.check("mc_set_tuning", lib.mc_set_tuning(C.byref(t)))
+
+
 def build_info() -> str:
     return L.load().mc_build_info().decode()

@@ -371,6 +371,36 @@ def test_anisotropic_point_source_sin2_2theta():
         _assert_maps(f"sin2_2theta_{'adj' if adj else 'fwd'}", gpu, ora, se)
 
 
+def test_tuning_changes_schedule_not_results():
+    """Other tile sides, generation sizes, job sizes and pause lengths move the
+    same packets in another order: the maps agree to FP64 rounding (the
+    per-visit FP32 sums are the same; only the order of the FP64 additions
+    differs).  The autotuner picks one of its candidates and applies it."""
+    rmc = _rmc()
+    from paper_1608_05238_amd import autotune
+    base = rmc.mc_get_tuning()
+    ph = P.disc_phantom(64, 0.2, 0.02, 8.0, 0.9, seed=12, radius=(1.0, 2.5))
+    specs = P.four_side_lines(ph)
+    n = 300_000
+    try:
+        ref, lref = _gpu_run(rmc, ph, specs, n, 16, seed=31)
+        for t in ({"tile": 7}, {"live_packets": 4096, "job_packets": 256, "max_visits": 3},
+                  {"live_packets": 1 << 17, "finish_packets": 50_000}):
+            rmc.mc_set_tuning({**base, **t})
+            got, lgot = _gpu_run(rmc, ph, specs, n, 16, seed=31)
+            big = np.abs(ref) > 1e-6 * np.abs(ref).max()
+            rel = np.abs(got - ref)[big] / np.abs(ref)[big]
+            assert rel.max() < 1e-9, (t, rel.max())
+            assert lgot["visits"] == lref["visits"] and lgot["scatters"] == lref["scatters"], t
+        rmc.mc_set_tuning(base)
+        med = rmc.Medium.from_phantom(ph)
+        res = autotune.tune(med, specs, 16, trial_packets=200_000,
+                            space={"job_packets": (1024, 4096), "max_visits": (16, 32)})
+        assert rmc.mc_get_tuning() == res["tuning"] and len(res["trials"]) == 4
+    finally:
+        rmc.mc_set_tuning(base)
+
+
 # ---------------------------------------------------------------- FP64 post-processing
 def test_residual_gradient_detect_fp64():
     import torch

@@ -113,3 +113,30 @@ def test_workspace_grows_with_grid_and_harmonics():
     big = lib.mc_workspace_bytes(C.byref(_medium(L, 256, 256, 0.1)), one, 1,
                                  C.byref(L.mc_run(10, 0, 0, 0, 16, 1e-4, 10.0, 0)))
     assert big > 65536 * 33 * 8 > small > 0
+
+
+def test_tuning_set_get_and_workspace():
+    """mc_set_tuning / mc_get_tuning round-trip, range checks, and the queue
+    sizes follow live_packets (host only)."""
+    L, lib = _lib()
+    from paper_1608_05238_amd import rmc
+    base = rmc.mc_get_tuning()
+    try:
+        m = _medium(L)
+        m.nx = m.nz = 256
+        src = (L.mc_source * 1)(_pencil(L))
+        run = L.mc_run(1 << 26, 0, 0, 0, 16, 1e-4, 10.0, 0)
+        rmc.mc_set_tuning({"live_packets": 1 << 20})
+        small = lib.mc_workspace_bytes(C.byref(m), src, 1, C.byref(run))
+        rmc.mc_set_tuning({"live_packets": 1 << 22, "job_packets": 1024, "max_visits": 7, "tile": 9})
+        assert rmc.mc_get_tuning() == {"live_packets": 1 << 22, "job_packets": 1024, "max_visits": 7, "tile": 9,
+                                       "finish_packets": 0}
+        big = lib.mc_workspace_bytes(C.byref(m), src, 1, C.byref(run))
+        assert big > small + 3 * (1 << 20) * 64
+        for bad in ({"live_packets": 10}, {"job_packets": 1}, {"max_visits": 0}, {"tile": 1000}):
+            with pytest.raises(Exception):
+                rmc.mc_set_tuning(bad)
+        rmc.mc_set_tuning(None)
+        assert rmc.mc_get_tuning()["job_packets"] == 4096
+    finally:
+        rmc.mc_set_tuning(base)
