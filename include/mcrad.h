@@ -144,6 +144,36 @@ mc_status mc_adjoint(const mc_medium *medium, const mc_source *src, int n_src, c
                      double *coeffs_d, mc_ledger *ledger_d, void *workspace_d, size_t workspace_bytes,
                      void *stream);
 
+/* One problem of a batch: a forward (adjoint = 0, as mc_forward) or adjoint
+ * (adjoint = 1, as mc_adjoint) run with its own medium, sources, packet
+ * range, seed and stream tag.  coeffs_d: FP64 [2N+1][nz][nx] out;
+ * ledger_d: device mc_ledger or NULL.  Every problem of a batch has the
+ * same n_harm. */
+typedef struct {
+    mc_medium medium;
+    const mc_source *src;
+    int32_t n_src;
+    mc_run run;
+    int32_t adjoint;
+    double *coeffs_d;
+    mc_ledger *ledger_d;
+} mc_problem;
+
+#define MC_BATCH_MAX 4096
+
+/* Workspace bytes of mc_run_batch (0 on invalid arguments). */
+size_t mc_batch_workspace_bytes(const mc_problem *probs_h, int n_probs);
+
+/* Many problems (sources, wavelengths, grid sizes) in one packet pool: the
+ * tiled transport's generations launch packets of every problem, sort all of
+ * them by tile over one tile index space, and each workgroup job moves the
+ * packets of one tile of one problem with that problem's medium and tally in
+ * LDS.  Every problem's output equals what mc_forward / mc_adjoint gives for
+ * it alone (the same packets; only the order of FP64 tally additions
+ * differs).  probs_h: host array of n_probs (1 .. MC_BATCH_MAX) problems. */
+mc_status mc_run_batch(const mc_problem *probs_h, int n_probs, void *workspace_d, size_t workspace_bytes,
+                       void *stream);
+
 /* Residual (Sec. 2 eq. error_function3, Sec. 6): H = mua a0 (Grueneisen 1),
  * r = hmeas - H, q* = mua r (per unit angle), eps = (dx^2 / 2) sum r^2.
  * coeffs_d: forward FP64 [>=1][nz][nx] (only a0 is read); hmeas_d FP64

@@ -20,7 +20,8 @@ MC_NHARM_MAX = 32
 # exported symbols declared in include/mcrad.h
 SYMBOLS = ("mc_workspace_bytes", "mc_forward", "mc_adjoint", "mc_residual", "mc_gradient", "mc_absorbed",
            "mc_adjoint_source", "mc_gradient_h", "mc_detect", "mc_trace", "mc_philox_fill", "mc_profile_enable",
-           "mc_profile_read", "mc_set_tuning", "mc_get_tuning", "mc_status_string", "mc_build_info")
+           "mc_profile_read", "mc_set_tuning", "mc_get_tuning", "mc_batch_workspace_bytes", "mc_run_batch",
+           "mc_status_string", "mc_build_info")
 
 
 class mc_medium(C.Structure):
@@ -52,6 +53,11 @@ class mc_event(C.Structure):
     _fields_ = [("pid", C.c_uint64), ("k", C.c_int32), ("type", C.c_int32), ("ix", C.c_int32),
                 ("iz", C.c_int32), ("x", C.c_float), ("z", C.c_float), ("sx", C.c_float),
                 ("sz", C.c_float), ("w", C.c_float), ("t", C.c_float)]
+
+
+class mc_problem(C.Structure):
+    _fields_ = [("medium", mc_medium), ("src", C.POINTER(mc_source)), ("n_src", C.c_int32), ("run", mc_run),
+                ("adjoint", C.c_int32), ("coeffs_d", C.c_void_p), ("ledger_d", C.c_void_p)]
 
 
 class mc_tuning(C.Structure):
@@ -98,6 +104,10 @@ def load() -> C.CDLL:
     lib.mc_profile_enable.restype = None
     lib.mc_profile_read.argtypes = [P(C.c_double), P(C.c_uint64), C.c_int]
     lib.mc_profile_read.restype = St
+    lib.mc_batch_workspace_bytes.argtypes = [P(mc_problem), C.c_int]
+    lib.mc_batch_workspace_bytes.restype = C.c_size_t
+    lib.mc_run_batch.argtypes = [P(mc_problem), C.c_int, V, C.c_size_t, V]
+    lib.mc_run_batch.restype = St
     lib.mc_set_tuning.argtypes = [P(mc_tuning)]
     lib.mc_set_tuning.restype = St
     lib.mc_get_tuning.argtypes = [P(mc_tuning)]

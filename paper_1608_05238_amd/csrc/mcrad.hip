@@ -62,6 +62,28 @@ struct SrcDev {
     double cum;                 // inclusive prefix of the sampling measure
 };
 
+// Per-problem values the tiled transport needs for a job: one entry per
+// problem of a batch (a single run is a batch of one).
+struct ProbDev {
+    int nx, nz, ntx, tile_base;   // grid, tiles across, first global tile index
+    uint32_t tag, flags;
+    uint64_t seed;
+    float wth, rm, inv_rm, pad;
+    const float4 *med;
+    const float *g;
+    double *t64;
+    double *led;
+    unsigned long long *ledc;
+};
+
+// The values a step and a scatter read, uniform over a workgroup's job.
+struct Hot {
+    int nx, nz;
+    uint32_t tag, flags;
+    uint64_t seed;
+    float wth, rm, inv_rm;
+};
+
 struct Params {
     int nx, nz, npix, nsrc;
     float dx;
@@ -87,6 +109,10 @@ struct Params {
     uint32_t *tile_count, *tile_cursor;
     uint4 *jobs;                // (tile, first record in qb, count, 0)
     uint32_t cap_a, cap_b, job_size, max_visits, tail_visits;
+    const ProbDev *probs;       // batch: problem descriptors
+    const uint32_t *tile_prob;  // batch: problem of each global tile
+    int tile_base;              // this problem's first global tile
+    uint32_t prob;              // this problem's index in the batch
     unsigned long long *counter;
     double *led;                // 5 doubles
     unsigned long long *ledc;   // 4 counters
@@ -112,7 +138,8 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
     return c;
 }
 
-__device__ __forceinline__ uint4 rng_block(const Params &P, uint64_t pid, uint32_t j) {
+template <class PP>
+__device__ __forceinline__ uint4 rng_block(const PP &P, uint64_t pid, uint32_t j) {
     return philox4x32_10(make_uint4(j, P.tag, (uint32_t)pid, (uint32_t)(pid >> 32)),
                          (uint32_t)P.seed, (uint32_t)(P.seed >> 32));
 }
@@ -143,7 +170,7 @@ struct alignas(16) PacketRec {
     int32_t ix, iz;
     uint64_t pid;
     uint32_t tile;
-    uint32_t spare;
+    uint32_t prob;     // problem of the batch
 };
 static_assert(sizeof(PacketRec) == 64, "packet record layout");
 
@@ -220,7 +247,8 @@ __device__ __forceinline__ void set_dir(Packet &p, float sx, float sz) {
 // Draw block k: free path (optical depth) and the uniforms used at its end.
 // -ln u from the hardware log2 (u >= 2^-24 is never denormal; 1.2e-7
 // relative error measured on the generator's grid of u).
-__device__ __forceinline__ void new_leg(const Params &P, Packet &p) {
+template <class PP>
+__device__ __forceinline__ void new_leg(const PP &P, Packet &p) {
     const uint4 r = rng_block(P, p.pid, p.k);
     p.tau = __builtin_amdgcn_logf(u01(r.x)) * -0.693147180559945309f;
     p.uh = u01(r.y);
@@ -348,7 +376,8 @@ __device__ __forceinline__ float expm1_neg(float x) {
 // Returns EV_CROSS, EV_ESCAPE or EV_SCATTER; T (pixel units) and the pixel
 // of the segment are returned through the references.
 // Written with selects only: every lane of a wave runs the same instructions.
-__device__ __forceinline__ int step(const Params &P, Packet &p, const float4 m, float &T, float &dw) {
+template <class PP>
+__device__ __forceinline__ int step(const PP &P, Packet &p, const float4 m, float &T, float &dw) {
     const bool px = p.sx > 0.f, pz = p.sz > 0.f;
     const float dfx = p.sx != 0.f ? (px ? 1.f - p.fx : p.fx) * fabsf(p.isx) : INFINITY;
     const float dfz = p.sz != 0.f ? (pz ? 1.f - p.fz : p.fz) * fabsf(p.isz) : INFINITY;
@@ -379,7 +408,8 @@ __device__ __forceinline__ int step(const Params &P, Packet &p, const float4 m, 
 // same instructions and only those lanes commit (selects, so the Philox
 // rounds and the deflection form one basic block the scheduler can
 // interleave).  Returns true for the lanes whose packet was terminated.
-__device__ __forceinline__ bool scatter_masked(const Params &P, Packet &p, const bool at, const float g,
+template <class PP>
+__device__ __forceinline__ bool scatter_masked(const PP &P, Packet &p, const bool at, const float g,
                                                LedgerRegs &L) {
     bool kill = false;
     const bool low = at && (p.k >= kMaxInteractions || fabsf(p.w) < P.wth * p.w0abs);
@@ -422,7 +452,8 @@ __device__ __forceinline__ bool scatter_masked(const Params &P, Packet &p, const
     return kill;
 }
 
-__device__ __forceinline__ bool scatter_dir(const Params &P, Packet &p, const float g, LedgerRegs &L) {
+template <class PP>
+__device__ __forceinline__ bool scatter_dir(const PP &P, Packet &p, const float g, LedgerRegs &L) {
     return !scatter_masked(P, p, true, g, L);
 }
 
@@ -487,7 +518,7 @@ __device__ __forceinline__ void ledger_flush(const Params &P, LedgerRegs &L) {
 
 // Ledger of a whole workgroup (every thread calls it): wave sums, then one
 // set of device atomics per workgroup.
-__device__ __forceinline__ void ledger_flush_block(const Params &P, LedgerRegs &L) {
+__device__ __forceinline__ void ledger_flush_block(double *led, unsigned long long *ledc, LedgerRegs &L) {
     __shared__ double s_v[16][5];
     __shared__ unsigned long long s_c[16][4];
     double v[5] = {L.launched, L.absorbed, L.escaped, L.gain, L.loss};
@@ -511,10 +542,11 @@ __device__ __forceinline__ void ledger_flush_block(const Params &P, LedgerRegs &
             for (int i = 0; i < 4; ++i) c[i] += s_c[w][i];
         }
         for (int i = 0; i < 5; ++i)
-            if (v[i] != 0.0) atomicAdd(P.led + i, v[i]);
+            if (v[i] != 0.0) atomicAdd(led + i, v[i]);
         for (int i = 0; i < 4; ++i)
-            if (c[i]) atomicAdd(P.ledc + i, c[i]);
+            if (c[i]) atomicAdd(ledc + i, c[i]);
     }
+    __syncthreads();   // the staging arrays may be reused by a next call
 }
 
 // ------------------------------------------------------------------ whole-grid transport
@@ -593,7 +625,7 @@ __global__ void __launch_bounds__(grid_block(NH)) k_transport_grid(Params P) {
 #pragma unroll
         for (int j = 0; j < K; ++j) acc[j] = flush ? 0.f : acc[j];
     }
-    ledger_flush_block(P, L);
+    ledger_flush_block(P.led, P.ledc, L);
     __syncthreads();
     for (int i = threadIdx.x; i < P.npix * K; i += blockDim.x) {
         const double v = tally[i];
@@ -616,13 +648,13 @@ __device__ __forceinline__ uint32_t tile_of(const Params &P, int ix, int iz) {
     return (uint32_t)((iz / P.th) * P.ntx + ix / P.tw);
 }
 
-__device__ __forceinline__ void rec_store(PacketRec *r, const Packet &p, uint32_t tile, uint32_t nvis) {
+__device__ __forceinline__ void rec_store(PacketRec *r, const Packet &p, uint32_t tile, uint32_t prob) {
     float4 *q = reinterpret_cast<float4 *>(r);
     q[0] = make_float4(p.fx, p.fz, p.sx, p.sz);
     q[1] = make_float4(p.w, p.w0abs, p.tau, p.uh);
     uint4 *u = reinterpret_cast<uint4 *>(r);
     u[2] = make_uint4(__float_as_uint(p.ur), p.k, (uint32_t)p.ix, (uint32_t)p.iz);
-    u[3] = make_uint4((uint32_t)p.pid, (uint32_t)(p.pid >> 32), tile, nvis);
+    u[3] = make_uint4((uint32_t)p.pid, (uint32_t)(p.pid >> 32), tile, prob);
 }
 
 __device__ __forceinline__ void rec_decode(const uint4 a, const uint4 b, const uint4 c, const uint4 d, Packet &p) {
@@ -675,7 +707,7 @@ __device__ __forceinline__ void slice_close(const Params &P, QueueSlice &q) {
 
 // Appends the packet of every lane with `put` set to the unsorted queue.
 __device__ __forceinline__ void slice_put(const Params &P, QueueSlice &q, bool put, const Packet &p, uint32_t tile,
-                                          uint32_t nvis) {
+                                          uint32_t prob) {
     const unsigned long long m = __ballot(put);
     if (!m) return;
     const int n = __popcll(m);
@@ -691,7 +723,7 @@ __device__ __forceinline__ void slice_put(const Params &P, QueueSlice &q, bool p
     if (put) {
         const uint32_t pos = q.base + q.used + __popcll(m & ((1ull << lane) - 1ull));
         if (pos < P.cap_a) {
-            rec_store(P.qa + pos, p, tile, nvis);
+            rec_store(P.qa + pos, p, tile, prob);
             P.qtile[pos] = tile;
         }
         else atomicOr(P.qcnt + 4, 1u);   // overflow: reported to the host, never written
@@ -733,8 +765,8 @@ __global__ void __launch_bounds__(256) k_tile_launch(Params P, uint64_t pid_base
             uint32_t pos = s_base + __popcll(m & ((1ull << lane) - 1ull));
             for (int w = 0; w < wave; ++w) pos += s_cnt[w];
             if (pos < P.cap_a) {
-                const uint32_t t = tile_of(P, p.ix, p.iz);
-                rec_store(P.qa + pos, p, t, 0u);
+                const uint32_t t = (uint32_t)P.tile_base + tile_of(P, p.ix, p.iz);
+                rec_store(P.qa + pos, p, t, P.prob);
                 P.qtile[pos] = t;
             } else {
                 atomicOr(P.qcnt + 4, 1u);
@@ -742,7 +774,7 @@ __global__ void __launch_bounds__(256) k_tile_launch(Params P, uint64_t pid_base
         }
         __syncthreads();
     }
-    ledger_flush_block(P, L);
+    ledger_flush_block(P.led, P.ledc, L);
 }
 
 // Counting sort of the unsorted queue by tile: counts.  Up to kHistTiles
@@ -814,7 +846,7 @@ __global__ void __launch_bounds__(1024) k_bin_scan(Params P) {
         P.tile_cursor[i] = roff;
         if (fits)
             for (uint32_t s0 = 0; s0 < c; s0 += P.job_size)
-                P.jobs[joff++] = make_uint4((uint32_t)i, roff + s0, min(P.job_size, c - s0), 0u);
+                P.jobs[joff++] = make_uint4((uint32_t)i, roff + s0, min(P.job_size, c - s0), P.tile_prob[i]);
         roff += c;
         P.tile_count[i] = 0;
     }
@@ -912,13 +944,14 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
     extern __shared__ double tally[];                  // [tw*th][K]
     float4 *smed = reinterpret_cast<float4 *>(tally + (((size_t)P.tw * P.th * K + 1) & ~size_t(1)));
     float *sg = reinterpret_cast<float *>(smed + P.tw * P.th);
-    __shared__ uint32_t s_job[4];
+    __shared__ uint32_t s_job[5];
     __shared__ uint32_t s_next;
     const int lane = __lane_id();
     const int ntp = P.tw * P.th;
     const unsigned long long lt_mask = (1ull << lane) - 1ull;
     LedgerRegs L;
     QueueSlice q;
+    int cur = -1;   // problem whose ledger L holds
 
     for (;;) {
         if (threadIdx.x == 0) {
@@ -929,18 +962,32 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
             s_job[1] = jb.x;
             s_job[2] = jb.y;
             s_job[3] = jb.z;
+            s_job[4] = jb.w;
             s_next = 0;
         }
         __syncthreads();
         if (!s_job[0]) break;
-        const uint32_t tile = s_job[1], first = s_job[2], cnt = s_job[3];
-        const int tx0 = (int)(tile % P.ntx) * P.tw, tz0 = (int)(tile / P.ntx) * P.th;
+        const uint32_t tile = s_job[1], first = s_job[2], cnt = s_job[3], prob = s_job[4];
+        const ProbDev &pd = P.probs[prob];
+        if ((int)prob != cur) {   // the ledger follows the problem (uniform in the workgroup)
+            if (cur >= 0) {
+                ledger_flush_block(P.probs[cur].led, P.probs[cur].ledc, L);
+                L = LedgerRegs();
+            }
+            cur = (int)prob;
+        }
+        const Hot H{pd.nx, pd.nz, pd.tag, pd.flags, pd.seed, pd.wth, pd.rm, pd.inv_rm};
+        const int ntx = pd.ntx, local = (int)tile - pd.tile_base;
+        const float4 *gmed = pd.med;
+        const float *gg = pd.g;
+        double *t64 = pd.t64;
+        const int tx0 = (local % ntx) * P.tw, tz0 = (local / ntx) * P.th;
         for (int i = threadIdx.x; i < ntp * K; i += blockDim.x) tally[i] = 0.0;
         for (int i = threadIdx.x; i < ntp; i += blockDim.x) {
             const int gx = tx0 + i % P.tw, gz = tz0 + i / P.tw;
-            const bool in = gx < P.nx && gz < P.nz;
-            smed[i] = in ? P.med[gz * P.nx + gx] : make_float4(0.f, 0.f, 0.f, 0.f);
-            sg[i] = in ? P.g[gz * P.nx + gx] : 0.f;
+            const bool in = gx < H.nx && gz < H.nz;
+            smed[i] = in ? gmed[gz * H.nx + gx] : make_float4(0.f, 0.f, 0.f, 0.f);
+            sg[i] = in ? gg[gz * H.nx + gx] : 0.f;
         }
         __syncthreads();
 
@@ -996,7 +1043,7 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
             const bool live = p.alive;
             const int lp = live ? (p.iz - tz0) * P.tw + (p.ix - tx0) : 0;
             float T = 0.f, dw = 0.f;
-            int ev = step(P, p, smed[lp], T, dw);
+            int ev = step(H, p, smed[lp], T, dw);
             ev = live ? ev : EV_NONE;
             T = live ? T : 0.f;
             dw = live ? dw : 0.f;
@@ -1004,7 +1051,7 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
             L.segments += live ? 1u : 0u;
             deposit_harmonics<NH>(T, p.sx, p.sz, acc);   // direction of the segment, before any scatter
             const bool at = ev == EV_SCATTER;
-            const bool killed = scatter_masked(P, p, at, sg[lp], L);
+            const bool killed = scatter_masked(H, p, at, sg[lp], L);
             const bool flush = killed || (ev != EV_NONE && !at);
             if (ev == EV_ESCAPE) {
                 L.escaped += p.w;
@@ -1022,7 +1069,7 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
                     const int ox = p.ix < tx0 ? -1 : (p.ix >= tx0 + P.tw ? 1 : 0);
                     const int oz = p.iz < tz0 ? -1 : (p.iz >= tz0 + P.th ? 1 : 0);
                     const bool out = (ox | oz) != 0;
-                    dest = (uint32_t)((int)tile + oz * P.ntx + ox);   // a crossing moves one pixel: a neighbour tile
+                    dest = (uint32_t)((int)tile + oz * ntx + ox);   // a crossing moves one pixel: a neighbour tile
                     // once the job has no packets left to hand out, a packet pauses
                     // after tail_visits more visits so the workgroup is not held by
                     // its longest stay (it resumes next generation)
@@ -1031,7 +1078,7 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
             }
 #pragma unroll
             for (int j = 0; j < K; ++j) acc[j] = flush ? 0.f : acc[j];
-            slice_put(P, q, leave, p, dest, 0u);
+            slice_put(P, q, leave, p, dest, prob);
             if (leave) {
                 p.alive = false;
                 nvis = 0;
@@ -1042,12 +1089,12 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
             const double v = tally[i];
             const int lp = i / K, c = i - lp * K;
             const int gx = tx0 + lp % P.tw, gz = tz0 + lp / P.tw;
-            if (v != 0.0 && gx < P.nx && gz < P.nz) unsafeAtomicAdd(P.t64 + (size_t)(gz * P.nx + gx) * K + c, v);
+            if (v != 0.0 && gx < H.nx && gz < H.nz) unsafeAtomicAdd(t64 + (size_t)(gz * H.nx + gx) * K + c, v);
         }
         __syncthreads();
     }
     slice_finish(P, q);
-    ledger_flush_block(P, L);
+    if (cur >= 0) ledger_flush_block(P.probs[cur].led, P.probs[cur].ledc, L);   // cur is uniform
 }
 
 // ------------------------------------------------------------------ tail finisher
@@ -1089,7 +1136,7 @@ __global__ void __launch_bounds__(kBlockFinish) k_finish(Params P, uint32_t n_re
                 if (base + ndead >= n_rec) more = false;
                 if (!p.alive) {
                     const uint32_t my = base + __popcll(dead & lt_mask);
-                    if (my < n_rec && P.qtile[my] != kInvalidTile) {
+                    if (my < n_rec && P.qtile[my] != kInvalidTile && P.qa[my].prob == P.prob) {
                         rec_load(P.qa + my, p);
                         dirty = true;
                     }
@@ -1148,7 +1195,7 @@ __global__ void __launch_bounds__(kBlockFinish) k_finish(Params P, uint32_t n_re
 #pragma unroll
         for (int j = 0; j < K; ++j) acc[j] = flush ? 0.f : acc[j];
     }
-    ledger_flush_block(P, L);
+    ledger_flush_block(P.led, P.ledc, L);
 }
 
 // ------------------------------------------------------------------ trace kernel
@@ -1473,12 +1520,16 @@ size_t tile_lds_bytes(int tw, int th, int K) {
     return tal + (size_t)tw * th * (sizeof(float4) + sizeof(float));
 }
 
+bool is_tiled(const mc_medium *m, const mc_run *run) {
+    return (size_t)m->nx * m->nz * (2 * run->n_harm + 1) * sizeof(double) > kLdsGridMax;
+}
+
+// Whole-grid mode: medium, CDF, tally, ledger and per-chunk counters.
 Layout layout(const mc_medium *m, const mc_source *src, const mc_run *run) {
     Layout L{};
-    L.tt = tuning_snapshot();
     const size_t npix = (size_t)m->nx * m->nz;
     const int K = 2 * run->n_harm + 1;
-    L.tiled = npix * K * sizeof(double) > kLdsGridMax;
+    L.tiled = is_tiled(m, run);
     size_t off = 0;
     L.med = off;
     off = align_up(off + npix * sizeof(float4));
@@ -1490,42 +1541,91 @@ Layout layout(const mc_medium *m, const mc_source *src, const mc_run *run) {
     off = align_up(off + 8 * sizeof(double));
     L.ledc = off;
     off = align_up(off + 8 * sizeof(unsigned long long));
-    if (!L.tiled) {
-        L.n_chunks = (run->n_packets + kChunk - 1) / kChunk;
-        L.counters = off;
-        off = align_up(off + L.n_chunks * sizeof(unsigned long long));
-    } else {
-        int t = 1;
-        while (tile_lds_bytes(t + 1, t + 1, K) <= kLdsTileMax) ++t;
-        if (L.tt.tile && tile_lds_bytes(L.tt.tile, L.tt.tile, K) <= kLdsTileMax) t = L.tt.tile;
-        L.tw = std::min(t, m->nx);
-        L.th = std::min(t, m->nz);
-        L.ntx = (m->nx + L.tw - 1) / L.tw;
-        L.ntz = (m->nz + L.th - 1) / L.th;
-        L.ntiles = L.ntx * L.ntz;
-        L.tile_lds = tile_lds_bytes(L.tw, L.th, K);
-        L.live = std::min<uint64_t>(run->n_packets, L.tt.live);
-        L.cap_a = 2 * L.live + (uint64_t)kSlice * kTileWavesMax + 64ull * 64;
-        L.max_jobs = L.ntiles + L.live / L.tt.job + 2;
-        L.counters = off;
-        off = align_up(off + 8 * sizeof(unsigned long long));
-        L.qcnt = off;
-        off = align_up(off + 8 * sizeof(uint32_t));
-        L.tcount = off;
-        off = align_up(off + L.ntiles * sizeof(uint32_t));
-        L.tcursor = off;
-        off = align_up(off + L.ntiles * sizeof(uint32_t));
-        L.jobs = off;
-        off = align_up(off + L.max_jobs * sizeof(uint4));
-        L.qa = off;
-        off = align_up(off + L.cap_a * sizeof(PacketRec));
-        L.qtile = off;
-        off = align_up(off + L.cap_a * sizeof(uint32_t));
-        L.qb = off;
-        off = align_up(off + L.live * sizeof(PacketRec));
-    }
+    L.n_chunks = (run->n_packets + kChunk - 1) / kChunk;
+    L.counters = off;
+    off = align_up(off + L.n_chunks * sizeof(unsigned long long));
     L.total = off;
     return L;
+}
+
+// One problem of a batch, as the caller gave it.
+struct BatchProblem {
+    const mc_medium *m;
+    const mc_source *src;
+    int n_src;
+    const mc_run *run;
+    int adjoint;
+    double *coeffs;
+    mc_ledger *ledger;
+};
+
+// Tiled mode for a batch of problems sharing the harmonic order: per-problem
+// medium, CDF, tally and ledger; one packet pool, one set of queues and one
+// global tile index space (problem p owns tiles tile_base[p] ..).
+struct BatchLayout {
+    TileTuning tt;
+    int N = 0, K = 0, t = 0, ntiles = 0;
+    size_t tile_lds = 0;
+    uint64_t live = 0, cap_a = 0, max_jobs = 0, total_packets = 0;
+    std::vector<size_t> med, cdf, t64, led, ledc;
+    std::vector<int> ntx, ntz, tile_base;
+    size_t probs = 0, tile_prob = 0, qcnt = 0, tcount = 0, tcursor = 0, jobs = 0, qa = 0, qtile = 0, qb = 0, total = 0;
+};
+
+BatchLayout batch_layout(const BatchProblem *pb, int n) {
+    BatchLayout B;
+    B.tt = tuning_snapshot();
+    B.N = pb[0].run->n_harm;
+    B.K = 2 * B.N + 1;
+    int t = 1;
+    while (tile_lds_bytes(t + 1, t + 1, B.K) <= kLdsTileMax) ++t;
+    if (B.tt.tile && tile_lds_bytes(B.tt.tile, B.tt.tile, B.K) <= kLdsTileMax) t = B.tt.tile;
+    int maxn = 1;
+    for (int i = 0; i < n; ++i) maxn = std::max({maxn, pb[i].m->nx, pb[i].m->nz});
+    B.t = std::min(t, maxn);
+    B.tile_lds = tile_lds_bytes(B.t, B.t, B.K);
+    size_t off = 0;
+    for (int i = 0; i < n; ++i) {
+        const size_t npix = (size_t)pb[i].m->nx * pb[i].m->nz;
+        B.med.push_back(off);
+        off = align_up(off + npix * sizeof(float4));
+        B.cdf.push_back(off);
+        if (pb[i].src[0].kind == MC_SRC_MAP) off = align_up(off + npix * sizeof(double));
+        B.t64.push_back(off);
+        off = align_up(off + npix * B.K * sizeof(double));
+        B.led.push_back(off);
+        off = align_up(off + 8 * sizeof(double));
+        B.ledc.push_back(off);
+        off = align_up(off + 8 * sizeof(unsigned long long));
+        B.ntx.push_back((pb[i].m->nx + B.t - 1) / B.t);
+        B.ntz.push_back((pb[i].m->nz + B.t - 1) / B.t);
+        B.tile_base.push_back(B.ntiles);
+        B.ntiles += B.ntx.back() * B.ntz.back();
+        B.total_packets += pb[i].run->n_packets;
+    }
+    B.live = std::min<uint64_t>(B.total_packets, B.tt.live);
+    B.cap_a = 2 * B.live + (uint64_t)kSlice * kTileWavesMax + 64ull * 64;
+    B.max_jobs = (uint64_t)B.ntiles + B.live / B.tt.job + 2;
+    B.probs = off;
+    off = align_up(off + (size_t)n * sizeof(ProbDev));
+    B.tile_prob = off;
+    off = align_up(off + (size_t)B.ntiles * sizeof(uint32_t));
+    B.qcnt = off;
+    off = align_up(off + 8 * sizeof(uint32_t));
+    B.tcount = off;
+    off = align_up(off + (size_t)B.ntiles * sizeof(uint32_t));
+    B.tcursor = off;
+    off = align_up(off + (size_t)B.ntiles * sizeof(uint32_t));
+    B.jobs = off;
+    off = align_up(off + B.max_jobs * sizeof(uint4));
+    B.qa = off;
+    off = align_up(off + B.cap_a * sizeof(PacketRec));
+    B.qtile = off;
+    off = align_up(off + B.cap_a * sizeof(uint32_t));
+    B.qb = off;
+    off = align_up(off + B.live * sizeof(PacketRec));
+    B.total = off;
+    return B;
 }
 
 mc_status validate(const mc_medium *m, const mc_source *src, int n_src, const mc_run *run) {
@@ -1702,66 +1802,146 @@ mc_status run_grid(Params &P, const Layout &L, const mc_run *run, char *base, hi
     return MC_OK;
 }
 
-// Tiled mode: host-driven generations (launch, sort by tile, transport), one
-// stream synchronisation per generation to read the queue length.
-mc_status run_tiled(Params &P, const Layout &L, const mc_run *run, char *base, hipStream_t s) {
-    const int N = run->n_harm;
+// Tiled mode: host-driven generations over one packet pool shared by every
+// problem of the batch (launch, sort by tile, transport), one stream
+// synchronisation per generation to read the queue length.
+mc_status run_batch(const BatchProblem *pb, int n, void *ws, size_t ws_bytes, hipStream_t s) {
+    for (int i = 0; i < n; ++i) {
+        mc_status st = validate(pb[i].m, pb[i].src, pb[i].n_src, pb[i].run);
+        if (st != MC_OK) return st;
+        if (!pb[i].coeffs || pb[i].run->n_harm != pb[0].run->n_harm) return MC_ERR_INVALID_ARG;
+    }
+    const BatchLayout B = batch_layout(pb, n);
+    if (!ws || ws_bytes < B.total || (reinterpret_cast<uintptr_t>(ws) & 255)) return MC_ERR_WORKSPACE;
+    if (B.tile_lds > kLdsTileMax || B.live > 0xFFFFFFFFull / 4) return MC_ERR_UNSUPPORTED;
+    char *base = static_cast<char *>(ws);
+    const int N = B.N;
+    mc_status st;
+    // per problem: zero tally and ledger, medium table, CDF of a map source
+    std::vector<Params> PP(n);
+    std::vector<ProbDev> PD(n);
+    std::vector<uint32_t> tile_prob(B.ntiles);
+    std::vector<uint64_t> todo(n), launched(n, 0);
+    for (int i = 0; i < n; ++i) {
+        const mc_medium *m = pb[i].m;
+        const int npix = m->nx * m->nz;
+        if ((st = launch_zero(base + B.t64[i], (size_t)npix * B.K * sizeof(double), s)) != MC_OK) return st;
+        if ((st = launch_zero(base + B.led[i], B.ledc[i] + 8 * sizeof(unsigned long long) - B.led[i], s)) != MC_OK)
+            return st;
+        hipLaunchKernelGGL(k_setup_medium, dim3((npix + 255) / 256), dim3(256), 0, s, npix, m->dx, m->mua_d,
+                           m->mus_d, reinterpret_cast<float4 *>(base + B.med[i]));
+        double map_abs_sum = 0;
+        todo[i] = pb[i].run->n_packets;
+        if (pb[i].src[0].kind == MC_SRC_MAP) {
+            double *cdf = reinterpret_cast<double *>(base + B.cdf[i]);
+            hipLaunchKernelGGL(k_map_cdf, dim3(1), dim3(1024), 0, s, npix, pb[i].src[0].map_d, cdf);
+            // the normalisation needs sum |q|: read the last CDF entry
+            if (hipMemcpyAsync(&map_abs_sum, cdf + npix - 1, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess)
+                return MC_ERR_DEVICE;
+            if (map_abs_sum == 0.0) todo[i] = 0;   // an all-zero source: the field is zero
+            else if (!(map_abs_sum > 0)) return MC_ERR_INVALID_ARG;   // NaN in the map
+        }
+        Params &P = PP[i];
+        fill_params(P, m, pb[i].src, pb[i].n_src, pb[i].run, pb[i].adjoint, map_abs_sum);
+        P.med = reinterpret_cast<const float4 *>(base + B.med[i]);
+        P.t64 = reinterpret_cast<double *>(base + B.t64[i]);
+        P.led = reinterpret_cast<double *>(base + B.led[i]);
+        P.ledc = reinterpret_cast<unsigned long long *>(base + B.ledc[i]);
+        P.cdf = reinterpret_cast<const double *>(base + B.cdf[i]);
+        P.tw = P.th = B.t;
+        P.ntx = B.ntx[i];
+        P.ntiles = B.ntiles;
+        P.tile_base = B.tile_base[i];
+        P.prob = (uint32_t)i;
+        P.qa = reinterpret_cast<PacketRec *>(base + B.qa);
+        P.qtile = reinterpret_cast<uint32_t *>(base + B.qtile);
+        P.qb = reinterpret_cast<PacketRec *>(base + B.qb);
+        P.qcnt = reinterpret_cast<uint32_t *>(base + B.qcnt);
+        P.tile_count = reinterpret_cast<uint32_t *>(base + B.tcount);
+        P.tile_cursor = reinterpret_cast<uint32_t *>(base + B.tcursor);
+        P.jobs = reinterpret_cast<uint4 *>(base + B.jobs);
+        P.probs = reinterpret_cast<const ProbDev *>(base + B.probs);
+        P.tile_prob = reinterpret_cast<const uint32_t *>(base + B.tile_prob);
+        P.cap_a = (uint32_t)B.cap_a;
+        P.cap_b = (uint32_t)B.live;
+        P.job_size = B.tt.job;
+        P.max_visits = B.tt.maxvis;
+        P.tail_visits = B.tt.tailvis;
+        ProbDev &d = PD[i];
+        d.nx = m->nx;
+        d.nz = m->nz;
+        d.ntx = B.ntx[i];
+        d.tile_base = B.tile_base[i];
+        d.tag = P.tag;
+        d.flags = P.flags;
+        d.seed = P.seed;
+        d.wth = P.wth;
+        d.rm = P.rm;
+        d.inv_rm = P.inv_rm;
+        d.pad = 0.f;
+        d.med = P.med;
+        d.g = P.g;
+        d.t64 = P.t64;
+        d.led = P.led;
+        d.ledc = P.ledc;
+        for (int k = 0; k < B.ntx[i] * B.ntz[i]; ++k) tile_prob[B.tile_base[i] + k] = (uint32_t)i;
+    }
+    if ((st = launch_zero(base + B.qcnt, 8 * sizeof(uint32_t), s)) != MC_OK) return st;
+    if ((st = launch_zero(base + B.tcount, (size_t)B.ntiles * sizeof(uint32_t), s)) != MC_OK) return st;
+    if (hipMemcpyAsync(base + B.probs, PD.data(), (size_t)n * sizeof(ProbDev), hipMemcpyHostToDevice, s) !=
+            hipSuccess ||
+        hipMemcpyAsync(base + B.tile_prob, tile_prob.data(), (size_t)B.ntiles * sizeof(uint32_t),
+                       hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)   // the host arrays go out of scope below
+        return MC_ERR_DEVICE;
+    if (hipGetLastError() != hipSuccess) return MC_ERR_DEVICE;
+
     const TransportFn fn = kernels().tile[N];
-    mc_status st = set_lds_limit(reinterpret_cast<const void *>(fn), L.tile_lds);
-    if (st != MC_OK) return st;
-    const int occ = occupancy_blocks(reinterpret_cast<const void *>(fn), kBlockTile, L.tile_lds);
+    if ((st = set_lds_limit(reinterpret_cast<const void *>(fn), B.tile_lds)) != MC_OK) return st;
+    const int occ = occupancy_blocks(reinterpret_cast<const void *>(fn), kBlockTile, B.tile_lds);
     const int cus = device_cus();
     const unsigned tgrid = (unsigned)std::max(1, std::min(cus * occ, kTileWavesMax / (kBlockTile / 64)));
-    P.tw = L.tw;
-    P.th = L.th;
-    P.ntx = L.ntx;
-    P.ntiles = L.ntiles;
-    P.qa = reinterpret_cast<PacketRec *>(base + L.qa);
-    P.qtile = reinterpret_cast<uint32_t *>(base + L.qtile);
-    P.qb = reinterpret_cast<PacketRec *>(base + L.qb);
-    P.qcnt = reinterpret_cast<uint32_t *>(base + L.qcnt);
-    P.tile_count = reinterpret_cast<uint32_t *>(base + L.tcount);
-    P.tile_cursor = reinterpret_cast<uint32_t *>(base + L.tcursor);
-    P.jobs = reinterpret_cast<uint4 *>(base + L.jobs);
-    P.cap_a = (uint32_t)L.cap_a;
-    P.cap_b = (uint32_t)L.live;
-    P.job_size = L.tt.job;
-    P.max_visits = L.tt.maxvis;
-    P.tail_visits = L.tt.tailvis;
-    const unsigned bgrid = (unsigned)std::min<uint64_t>((L.cap_a + 255) / 256, 4096);
-    const unsigned cgrid = (unsigned)std::min<uint64_t>((L.cap_a + 255) / 256, 4 * (uint64_t)cus);
+    const unsigned bgrid = (unsigned)std::min<uint64_t>((B.cap_a + 255) / 256, 4096);
+    const unsigned cgrid = (unsigned)std::min<uint64_t>((B.cap_a + 255) / 256, 4 * (uint64_t)cus);
+    const Params &P0 = PP[0];   // the sort and transport kernels read only batch-wide fields
     static thread_local uint32_t *host_cnt = nullptr;
     if (!host_cnt && hipHostMalloc(reinterpret_cast<void **>(&host_cnt), 8 * sizeof(uint32_t)) != hipSuccess)
         return MC_ERR_DEVICE;
-    const uint64_t finish_at = L.tt.finish ? L.tt.finish : L.live / 128;
-    uint64_t launched = 0, carried = 0;
+    const uint64_t finish_at = B.tt.finish ? B.tt.finish : B.live / 128;
+    uint64_t total_todo = 0, total_launched = 0, carried = 0;
+    for (int i = 0; i < n; ++i) total_todo += todo[i];
     for (uint64_t gen = 0;; ++gen) {
         if (gen > (1ull << 32)) return MC_ERR_DEVICE;
-        uint64_t n_new = 0;
-        if (carried < L.live) n_new = std::min<uint64_t>(L.live - carried, run->n_packets - launched);
-        if (carried == 0 && n_new == 0) break;
-        if (n_new) {
+        uint64_t budget = carried < B.live ? B.live - carried : 0;
+        if (carried == 0 && total_launched == total_todo) break;
+        for (int i = 0; i < n && budget; ++i) {   // refill the pool, problems in order
+            const uint64_t n_new = std::min<uint64_t>(budget, todo[i] - launched[i]);
+            if (!n_new) continue;
             const unsigned lgrid = (unsigned)std::min<uint64_t>((n_new + 255) / 256, 8 * (uint64_t)cus);
-            hipLaunchKernelGGL(k_tile_launch, dim3(lgrid), dim3(256), 0, s, P, run->first_packet_id + launched,
-                               (uint32_t)n_new);
-            launched += n_new;
+            hipLaunchKernelGGL(k_tile_launch, dim3(lgrid), dim3(256), 0, s, PP[i],
+                               pb[i].run->first_packet_id + launched[i], (uint32_t)n_new);
+            launched[i] += n_new;
+            total_launched += n_new;
+            budget -= n_new;
         }
-        hipLaunchKernelGGL(k_bin_count, dim3(cgrid), dim3(256), 0, s, P);
-        hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, s, P);
-        hipLaunchKernelGGL(k_bin_scatter, dim3(bgrid), dim3(256), 0, s, P);
+        hipLaunchKernelGGL(k_bin_count, dim3(cgrid), dim3(256), 0, s, P0);
+        hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, s, P0);
+        hipLaunchKernelGGL(k_bin_scatter, dim3(bgrid), dim3(256), 0, s, P0);
         LaunchTimer tm;
         if ((st = tm.begin(s)) != MC_OK) return st;
-        hipLaunchKernelGGL(fn, dim3(tgrid), dim3(kBlockTile), L.tile_lds, s, P);
+        hipLaunchKernelGGL(fn, dim3(tgrid), dim3(kBlockTile), B.tile_lds, s, P0);
         if ((st = tm.end(s)) != MC_OK) return st;
         if (hipGetLastError() != hipSuccess) return MC_ERR_DEVICE;
-        if (hipMemcpyAsync(host_cnt, P.qcnt, 8 * sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        if (hipMemcpyAsync(host_cnt, P0.qcnt, 8 * sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
             return MC_ERR_DEVICE;
         if (host_cnt[4]) return MC_ERR_DEVICE;   // queue overflow (not expected by construction)
         carried = host_cnt[6];   // valid records; qa also holds the padding of partly used slices
-        if (launched == run->n_packets && carried > 0 && carried <= finish_at) {
-            const uint32_t n_rec = (uint32_t)std::min<uint64_t>(host_cnt[0], L.cap_a);
-            // finish the remaining packets without migration (qcnt[5]: record cursor)
+        if (total_launched == total_todo && carried > 0 && carried <= finish_at) {
+            // finish the remaining packets without migration, one launch per
+            // problem (each takes only its own records; qcnt[5]: record cursor)
+            const uint32_t n_rec = (uint32_t)std::min<uint64_t>(host_cnt[0], B.cap_a);
             const FinishFn ff = kernels().fin[N];
             const size_t flds = (size_t)(kBlockFinish / 64) * 64 * (2 * N + 1) * sizeof(float) +
                                 (kBlockFinish / 64) * 64 * sizeof(int);
@@ -1769,15 +1949,30 @@ mc_status run_tiled(Params &P, const Layout &L, const mc_run *run, char *base, h
             const int focc = occupancy_blocks(reinterpret_cast<const void *>(ff), kBlockFinish, flds);
             const unsigned fgrid = (unsigned)std::max<uint64_t>(
                 1, std::min<uint64_t>((carried + kBlockFinish - 1) / kBlockFinish, (uint64_t)cus * focc));
-            LaunchTimer tf;
-            if ((st = tf.begin(s)) != MC_OK) return st;
-            hipLaunchKernelGGL(ff, dim3(fgrid), dim3(kBlockFinish), flds, s, P, n_rec);
-            if ((st = tf.end(s)) != MC_OK) return st;
-            if (hipGetLastError() != hipSuccess) return MC_ERR_DEVICE;
+            for (int i = 0; i < n; ++i) {
+                if (!todo[i]) continue;
+                if ((st = launch_zero(PP[i].qcnt + 5, sizeof(uint32_t), s)) != MC_OK) return st;
+                LaunchTimer tf;
+                if ((st = tf.begin(s)) != MC_OK) return st;
+                hipLaunchKernelGGL(ff, dim3(fgrid), dim3(kBlockFinish), flds, s, PP[i], n_rec);
+                if ((st = tf.end(s)) != MC_OK) return st;
+                if (hipGetLastError() != hipSuccess) return MC_ERR_DEVICE;
+            }
             break;
         }
     }
-    return MC_OK;
+    // normalisation and ledgers
+    for (int i = 0; i < n; ++i) {
+        const mc_medium *m = pb[i].m;
+        const int npix = m->nx * m->nz;
+        const double scale = PP[i].total / ((double)pb[i].run->n_packets);
+        hipLaunchKernelGGL(k_normalise, dim3((npix + 255) / 256), dim3(256), 0, s, npix, N, pb[i].adjoint,
+                           todo[i] ? scale / (double)m->dx : 0.0, PP[i].t64, pb[i].coeffs);
+        if (pb[i].ledger)
+            hipLaunchKernelGGL(k_ledger_out, dim3(1), dim3(1), 0, s, PP[i].led, PP[i].ledc, todo[i] ? scale : 0.0,
+                               pb[i].ledger);
+    }
+    return hipGetLastError() == hipSuccess ? MC_OK : MC_ERR_DEVICE;
 }
 
 mc_status run_mc(const mc_medium *m, const mc_source *src, int n_src, const mc_run *run, double *coeffs,
@@ -1785,17 +1980,20 @@ mc_status run_mc(const mc_medium *m, const mc_source *src, int n_src, const mc_r
     mc_status st = validate(m, src, n_src, run);
     if (st != MC_OK) return st;
     if (!coeffs) return MC_ERR_INVALID_ARG;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (is_tiled(m, run)) {
+        const BatchProblem one{m, src, n_src, run, adjoint, coeffs, ledger};
+        return run_batch(&one, 1, ws, ws_bytes, s);
+    }
     const Layout L = layout(m, src, run);
     if (!ws || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255)) return MC_ERR_WORKSPACE;
-    if (L.tiled && L.tile_lds > kLdsTileMax) return MC_ERR_UNSUPPORTED;
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     char *base = static_cast<char *>(ws);
     const int npix = m->nx * m->nz;
     const int N = run->n_harm;
 
-    // zero the tally, ledger, counters and (tiled mode) queue counters and tile counts
-    const size_t zero_end = L.tiled ? L.jobs : L.counters + L.n_chunks * sizeof(unsigned long long);
-    if ((st = launch_zero(base + L.t64, zero_end - L.t64, s)) != MC_OK) return st;
+    // zero the tally, ledger and chunk counters
+    if ((st = launch_zero(base + L.t64, L.counters + L.n_chunks * sizeof(unsigned long long) - L.t64, s)) != MC_OK)
+        return st;
     hipLaunchKernelGGL(k_setup_medium, dim3((npix + 255) / 256), dim3(256), 0, s, npix, m->dx, m->mua_d, m->mus_d,
                        reinterpret_cast<float4 *>(base + L.med));
     double map_abs_sum = 0;
@@ -1822,7 +2020,7 @@ mc_status run_mc(const mc_medium *m, const mc_source *src, int n_src, const mc_r
     P.ledc = reinterpret_cast<unsigned long long *>(base + L.ledc);
     P.cdf = reinterpret_cast<const double *>(base + L.cdf);
 
-    st = L.tiled ? run_tiled(P, L, run, base, s) : run_grid(P, L, run, base, s);
+    st = run_grid(P, L, run, base, s);
     if (st != MC_OK) return st;
     const double scale = P.total / ((double)run->n_packets);
     hipLaunchKernelGGL(k_normalise, dim3((npix + 255) / 256), dim3(256), 0, s, npix, N, adjoint,
@@ -1838,7 +2036,33 @@ extern "C" {
 
 size_t mc_workspace_bytes(const mc_medium *medium, const mc_source *src, int n_src, const mc_run *run) {
     if (validate(medium, src, n_src, run) != MC_OK) return 0;
+    if (is_tiled(medium, run)) {
+        const BatchProblem one{medium, src, n_src, run, 0, nullptr, nullptr};
+        return batch_layout(&one, 1).total;
+    }
     return layout(medium, src, run).total;
+}
+
+size_t mc_batch_workspace_bytes(const mc_problem *probs, int n_probs) {
+    if (!probs || n_probs < 1 || n_probs > MC_BATCH_MAX) return 0;
+    std::vector<BatchProblem> pb(n_probs);
+    for (int i = 0; i < n_probs; ++i) {
+        const mc_problem &q = probs[i];
+        if (validate(&q.medium, q.src, q.n_src, &q.run) != MC_OK || q.run.n_harm != probs[0].run.n_harm) return 0;
+        pb[i] = BatchProblem{&q.medium, q.src, q.n_src, &q.run, q.adjoint ? 1 : 0, q.coeffs_d, q.ledger_d};
+    }
+    return batch_layout(pb.data(), n_probs).total;
+}
+
+mc_status mc_run_batch(const mc_problem *probs, int n_probs, void *workspace_d, size_t workspace_bytes,
+                       void *stream) {
+    if (!probs || n_probs < 1 || n_probs > MC_BATCH_MAX) return MC_ERR_INVALID_ARG;
+    std::vector<BatchProblem> pb(n_probs);
+    for (int i = 0; i < n_probs; ++i) {
+        const mc_problem &q = probs[i];
+        pb[i] = BatchProblem{&q.medium, q.src, q.n_src, &q.run, q.adjoint ? 1 : 0, q.coeffs_d, q.ledger_d};
+    }
+    return run_batch(pb.data(), n_probs, workspace_d, workspace_bytes, reinterpret_cast<hipStream_t>(stream));
 }
 
 mc_status mc_forward(const mc_medium *medium, const mc_source *src, int n_src, const mc_run *run, double *coeffs_d,

@@ -229,6 +229,43 @@ def mc_detect(medium: Medium, n_harm: int, coeffs: torch.Tensor, det: torch.Tens
     return out
 
 
+@dataclass
+class Problem:
+    """One problem of mc_run_batch: medium, sources, run and direction."""
+    medium: Medium
+    sources: Sequence
+    run: L.mc_run
+    adjoint: bool = False
+
+
+def mc_run_batch(problems: Sequence[Problem], ledger: bool = True, stream=None):
+    """Run many problems in one packet pool.  Returns a list of (coeffs, ledger
+    buffer or None), in the order given."""
+    lib = L.load()
+    n = len(problems)
+    arr = (L.mc_problem * n)()
+    keep, outs = [], []
+    for i, pr in enumerate(problems):
+        dev = pr.medium.mua.device
+        src = _Sources(pr.sources, dev)
+        keep.append(src)
+        K = 2 * pr.run.n_harm + 1
+        out = torch.empty((K, pr.medium.nz, pr.medium.nx), dtype=torch.float64, device=dev)
+        led = torch.zeros(C.sizeof(L.mc_ledger), dtype=torch.uint8, device=dev) if ledger else None
+        outs.append((out, led))
+        arr[i] = L.mc_problem(pr.medium.c(), src.arr, src.n, pr.run, int(bool(pr.adjoint)), out.data_ptr(), _ptr(led))
+    need = lib.mc_batch_workspace_bytes(arr, n)
+    if need == 0:
+        raise L.MCError("mc_batch_workspace_bytes", L.MC_ERR_INVALID_ARG)
+    dev = problems[0].medium.mua.device
+    ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+    off = (-ws.data_ptr()) % 256
+    L.check("mc_run_batch", lib.mc_run_batch(arr, n, ws.data_ptr() + off, ws.numel() - off, _stream(stream)))
+    if stream is not None:
+        ws.record_stream(stream)   # freed by the caching allocator only after the stream's work
+    return outs
+
+
 _EVENT_DTYPE = np.dtype([("pid", "<u8"), ("k", "<i4"), ("type", "<i4"), ("ix", "<i4"), ("iz", "<i4"),
                          ("x", "<f4"), ("z", "<f4"), ("sx", "<f4"), ("sz", "<f4"), ("w", "<f4"), ("t", "<f4")])
 

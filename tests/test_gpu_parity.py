@@ -401,6 +401,47 @@ def test_tuning_changes_schedule_not_results():
         rmc.mc_set_tuning(base)
 
 
+@pytest.mark.parametrize("live", [None, 1 << 16])
+def test_batch_equals_separate_runs(live):
+    """Problems of different grid sizes, sources, directions and seeds in one
+    packet pool give each the maps of its own run: the same packets move, only
+    the order of the FP64 additions differs.  The batch holds a grid that runs
+    in the whole-grid mode when alone, an adjoint map source and an all-zero
+    map source; a small pool (2^16 live packets) mixes the problems' packets
+    over many generations."""
+    rmc = _rmc()
+    base = rmc.mc_get_tuning()
+    ph1 = P.disc_phantom(64, 0.2, 0.02, 8.0, 0.9, seed=21, radius=(1.0, 2.5))
+    ph2 = P.homogeneous(20, 12, 0.5, 0.05, 5.0, 0.8)
+    ph3 = P.disc_phantom(40, 0.25, 0.03, 6.0, 0.85, seed=22, radius=(1.0, 2.0))
+    q3 = P.residual_like_map(ph3, seed=4)
+    cases = [(ph1, P.four_side_lines(ph1), False, 200_000, 5, 0),
+             (ph2, P.pencil_top_centre(ph2), False, 50_000, 6, 0),
+             (ph3, [P.map_source(q3)], True, 120_000, 7, 1),
+             (ph3, [P.map_source(np.zeros_like(q3))], True, 1000, 8, 1),
+             (ph1, [P.point_source(6.33, 5.91)], False, 80_000, 9, 0)]
+    try:
+        if live:
+            rmc.mc_set_tuning({**base, "live_packets": live})
+        probs = [rmc.Problem(rmc.Medium.from_phantom(ph), src, rmc.make_run(n, 16, seed=sd, stream_tag=tag), adj)
+                 for ph, src, adj, n, sd, tag in cases]
+        outs = rmc.mc_run_batch(probs)
+        for (ph, src, adj, n, sd, tag), (got, lg) in zip(cases, outs):
+            ref, lr = _gpu_run(rmc, ph, src, n, 16, seed=sd, adjoint=adj, tag=tag)
+            got, lg = got.cpu().numpy(), rmc.ledger_dict(lg)
+            if not np.abs(ref).max():
+                assert not np.abs(got).max()
+                continue
+            big = np.abs(ref) > 1e-6 * np.abs(ref).max()
+            rel = np.abs(got - ref)[big] / np.abs(ref)[big]
+            assert rel.max() < 1e-9, (ph.mua.shape, adj, rel.max())
+            for k in ("packets", "visits", "scatters", "segments"):
+                assert lg[k] == lr[k], (k, lg[k], lr[k])
+            assert lg["absorbed"] == pytest.approx(lr["absorbed"], rel=1e-9)
+    finally:
+        rmc.mc_set_tuning(base)
+
+
 # ---------------------------------------------------------------- FP64 post-processing
 def test_residual_gradient_detect_fp64():
     import torch
