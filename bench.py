@@ -127,6 +127,70 @@ def time_to_error(args) -> dict:
             "sweep": rows}
 
 
+def batch_workload(args) -> dict:
+    """64 problems in one packet pool: 16 sources x 4 wavelengths (mua scaled
+    0.5, 1, 2, 4), grids drawn from {128, 192, 256, 512}^2 over the same
+    25.6 mm square, packets per problem log-uniform in [args.batch_min,
+    args.batch_max], N = 16.  Timed as one mc_run_batch call and as the same
+    64 runs one after the other (the same packets), after autotuning on a
+    sample of the batch when args.autotune is set."""
+    import numpy as np
+    import torch
+    import phantoms as P
+    from paper_1608_05238_amd import rmc
+    rng = np.random.default_rng(3)
+    dev = torch.device("cuda", 0)
+    side = 25.6
+    sizes = rng.choice([128, 192, 256, 512], size=16)      # one grid per source
+    # 16 sources: four collimated segments along each side, inward
+    segs = []
+    for k in range(4):
+        a, b = side * k / 4, side * (k + 1) / 4
+        segs += [P.SourceSpec("line", a, 0.0, b, 0.0, 0.0, 1.0, 0, 1.0),
+                 P.SourceSpec("line", a, side, b, side, 0.0, -1.0, 0, 1.0),
+                 P.SourceSpec("line", 0.0, a, 0.0, b, 1.0, 0.0, 0, 1.0),
+                 P.SourceSpec("line", side, a, side, b, -1.0, 0.0, 0, 1.0)]
+    probs, meta = [], []
+    for si in range(16):
+        n = int(sizes[si])
+        base = P.disc_phantom(n, side / n, 0.01, 10.0, 0.9, seed=100 + si)
+        for wi, f in enumerate((0.5, 1.0, 2.0, 4.0)):
+            ph = base.copy()
+            ph.mua = (ph.mua * f).astype(np.float32)
+            npk = int(np.exp(rng.uniform(np.log(args.batch_min), np.log(args.batch_max))))
+            probs.append(rmc.Problem(rmc.Medium.from_phantom(ph, dev), [segs[si]],
+                                     rmc.make_run(npk, 16, seed=1000 + 4 * si + wi)))
+            meta.append((n, f, npk))
+    total = sum(m[2] for m in meta)
+    tuned = None
+    if args.autotune:
+        from paper_1608_05238_amd import autotune
+        log("autotune on every 4th problem at a quarter of its packets")
+        tuned = autotune.tune_batch(probs, every=4, scale=0.25, log=log)["tuning"]
+    rmc.mc_run_batch(probs[:2], ledger=False)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rmc.mc_run_batch(probs, ledger=False)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    log(f"batch: {t_batch:.2f} s for {total:.3e} packets")
+    t0 = time.perf_counter()
+    for pr in probs:
+        rmc.mc_forward(pr.medium, pr.sources, pr.run, ledger=False)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    log(f"one by one: {t_seq:.2f} s")
+    return {"metric": "packets/s fwd MC, 64 problems in one packet pool (N=16 harmonics)",
+            "value": total / t_batch, "unit": "packets/s", "higher_is_better": True, "n_gpus": 1,
+            "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "64 problems: 16 segment sources x 4 wavelengths (mua x0.5-4), grids "
+                                   "{128,192,256,512}^2 over 25.6 mm, disc phantoms",
+                       "packets_total": total, "packets_per_problem": [args.batch_min, args.batch_max],
+                       "grids": [int(x) for x in sizes]},
+            "batch_s": t_batch, "one_by_one_s": t_seq, "one_by_one_packets_per_s": total / t_seq,
+            "speedup": t_seq / t_batch, "tuning": tuned}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -140,6 +204,11 @@ def main() -> int:
     ap.add_argument("--time-to-error", action="store_true",
                     help="instead of the throughput line, measure the wall time to a gradient of fixed error")
     ap.add_argument("--ref-packets", type=float, default=1e9, help="packets of the reference gradient (each run)")
+    ap.add_argument("--batch", action="store_true",
+                    help="instead of the throughput line, time the 64-problem batched workload")
+    ap.add_argument("--batch-min", type=float, default=1e6)
+    ap.add_argument("--batch-max", type=float, default=1e7)
+    ap.add_argument("--autotune", action="store_true", help="with --batch: autotune before timing")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -155,6 +224,9 @@ def main() -> int:
     torch.cuda.set_device(0)
     if args.time_to_error:
         print(json.dumps(time_to_error(args)), flush=True)
+        return 0
+    if args.batch:
+        print(json.dumps(batch_workload(args)), flush=True)
         return 0
     dev = torch.device("cuda", 0)
     if args.copy_probe_mib > 0:

@@ -4,7 +4,8 @@ and tile side.
 `tune()` times short forward (or adjoint) runs of the caller's problem over a
 set of candidate tunings, keeps the fastest, applies it with mc_set_tuning
 and records it in an optional JSON cache keyed by grid size, harmonic order
-and run kind.  The tuning changes only the schedule (which packets move
+and run kind; `tune_batch()` does the same for a batch of problems
+(mc_run_batch) on a sample of it.  The tuning changes only the schedule (which packets move
 together, how often they are sorted); the result of a run is the same up to
 the order of the FP64 tally additions.
 
@@ -41,20 +42,26 @@ def _key(medium: rmc.Medium, n_harm: int, adjoint: bool) -> str:
     return f"{medium.nx}x{medium.nz}_N{n_harm}_{'adjoint' if adjoint else 'forward'}"
 
 
-def time_run(medium: rmc.Medium, sources: Sequence, n_harm: int, n_packets: int, adjoint: bool = False,
-             seed: int = 0) -> float:
-    """Seconds of one run (HIP events on the current stream); the workspace is
-    sized for the tuning in force."""
-    fn = rmc.mc_adjoint if adjoint else rmc.mc_forward
-    run = rmc.make_run(n_packets, n_harm, seed=seed, stream_tag=1 if adjoint else 0)
-    ws = torch.empty(rmc.mc_workspace_bytes(medium, sources, run) + 256, dtype=torch.uint8,
-                     device=medium.mua.device)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    fn(medium, sources, run, workspace=ws, ledger=False)
-    e1.record()
-    torch.cuda.synchronize()
-    return e0.elapsed_time(e1) * 1e-3
+def search(run, n_packets: int, space: Optional[dict] = None, log=None) -> dict:
+    """Time the zero-argument callable `run` (moving n_packets packets) under
+    every candidate tuning, apply the fastest and return it with the trials."""
+    base = rmc.mc_get_tuning()
+    trials = []
+    run()   # warm-up (code, caches)
+    for cand in candidates(space):
+        rmc.mc_set_tuning({**base, **cand})
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        run()
+        e1.record()
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) * 1e-3
+        trials.append({"tuning": {**base, **cand}, "packets_per_s": n_packets / t})
+        if log:
+            log(f"{cand}: {n_packets / t:.4e} packets/s")
+    best = max(trials, key=lambda r: r["packets_per_s"])
+    rmc.mc_set_tuning(best["tuning"])
+    return {"tuning": best["tuning"], "packets_per_s": best["packets_per_s"], "trials": trials}
 
 
 def tune(medium: rmc.Medium, sources: Sequence, n_harm: int, trial_packets: int = 10_000_000,
@@ -69,23 +76,29 @@ def tune(medium: rmc.Medium, sources: Sequence, n_harm: int, trial_packets: int 
         if key in cache:
             rmc.mc_set_tuning(cache[key]["tuning"])
             return cache[key]
-    base = rmc.mc_get_tuning()
-    trials = []
-    time_run(medium, sources, n_harm, min(trial_packets, 1_000_000), adjoint)   # warm-up (code, caches)
-    for cand in candidates(space):
-        rmc.mc_set_tuning({**base, **cand})
-        t = time_run(medium, sources, n_harm, trial_packets, adjoint, seed=1)
-        trials.append({"tuning": {**base, **cand}, "packets_per_s": trial_packets / t})
-        if log:
-            log(f"{cand}: {trial_packets / t:.4e} packets/s")
-    best = max(trials, key=lambda r: r["packets_per_s"])
-    rmc.mc_set_tuning(best["tuning"])
-    out = {"tuning": best["tuning"], "packets_per_s": best["packets_per_s"], "trials": trials}
+    fn = rmc.mc_adjoint if adjoint else rmc.mc_forward
+    run = rmc.make_run(trial_packets, n_harm, seed=1, stream_tag=1 if adjoint else 0)
+    out = search(lambda: fn(medium, sources, run, ledger=False), trial_packets, space, log)
     if cache_path:
-        cache[key] = {"tuning": best["tuning"], "packets_per_s": best["packets_per_s"]}
+        cache[key] = {"tuning": out["tuning"], "packets_per_s": out["packets_per_s"]}
         with open(cache_path, "w") as f:
             json.dump(cache, f, indent=1)
     return out
+
+
+def tune_batch(problems: Sequence[rmc.Problem], every: int = 4, scale: float = 0.25,
+               space: Optional[dict] = None, log=None) -> dict:
+    """Tune for a batch on a sample of it: every `every`-th problem with its
+    packet count scaled by `scale` (same grids, sources and seeds)."""
+    sub = []
+    for pr in problems[::every]:
+        r = pr.run
+        n = max(1, int(r.n_packets * scale))
+        sub.append(rmc.Problem(pr.medium, pr.sources,
+                               rmc.make_run(n, r.n_harm, r.seed, r.first_packet_id, r.stream_tag, r.w_threshold,
+                                            r.roulette_m, r.flags), pr.adjoint))
+    total = sum(p.run.n_packets for p in sub)
+    return search(lambda: rmc.mc_run_batch(sub, ledger=False), total, space, log)
 
 
 def main(argv=None) -> int:
