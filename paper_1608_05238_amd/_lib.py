@@ -21,7 +21,7 @@ MC_NHARM_MAX = 32
 SYMBOLS = ("mc_workspace_bytes", "mc_forward", "mc_adjoint", "mc_residual", "mc_gradient", "mc_absorbed",
            "mc_adjoint_source", "mc_gradient_h", "mc_detect", "mc_trace", "mc_philox_fill", "mc_profile_enable",
            "mc_profile_read", "mc_set_tuning", "mc_get_tuning", "mc_batch_workspace_bytes", "mc_run_batch",
-           "mc_status_string", "mc_build_info")
+           "mc_status_string", "mc_build_info", "dn_conv3x3_fwd", "dn_conv3x3_wgrad")
 
 
 class mc_medium(C.Structure):
@@ -112,6 +112,10 @@ def load() -> C.CDLL:
     lib.mc_set_tuning.restype = St
     lib.mc_get_tuning.argtypes = [P(mc_tuning)]
     lib.mc_get_tuning.restype = St
+    lib.dn_conv3x3_fwd.argtypes = [V, V, V, V, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, V]
+    lib.dn_conv3x3_fwd.restype = St
+    lib.dn_conv3x3_wgrad.argtypes = [V, V, V, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, V]
+    lib.dn_conv3x3_wgrad.restype = St
     lib.mc_status_string.argtypes = [C.c_int]
     lib.mc_status_string.restype = C.c_char_p
     lib.mc_build_info.argtypes = []

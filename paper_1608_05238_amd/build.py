@@ -15,7 +15,7 @@ import time
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-SRC = os.path.join(PKG, "csrc", "mcrad.hip")
+SRCS = [os.path.join(PKG, "csrc", "mcrad.hip"), os.path.join(PKG, "csrc", "denoise.hip")]
 OUT = os.path.join(PKG, "librmc.so")
 INCLUDE = os.path.join(ROOT, "include")
 
@@ -34,7 +34,7 @@ def flags() -> list:
 
 def build(verbose: bool = False) -> str:
     tmp = OUT + ".tmp"
-    cmd = [hipcc()] + flags() + [SRC, "-o", tmp]
+    cmd = [hipcc()] + flags() + SRCS + ["-o", tmp]
     t0 = time.time()
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

@@ -1,5 +1,5 @@
 """Host-side checks of librmc.so that need no GPU: it loads, exports every entry
-point declared in include/mcrad.h, its structs match the binding, and invalid
+point declared in include/*.h, its structs match the binding, and invalid
 arguments are rejected on the host before anything touches a device."""
 import ctypes as C
 import os
@@ -19,9 +19,13 @@ def _lib():
 
 
 def _declared_functions():
-    text = open(os.path.join(ROOT, "include", "mcrad.h")).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(mc_[a-z_]+)\s*\(", text)))
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", h)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b((?:mc|dn)_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_entry_point():
