@@ -227,12 +227,13 @@ def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--n", type=int, default=64)
     ap.add_argument("--side", type=float, default=25.6)
-    ap.add_argument("--train", type=int, default=192)
+    ap.add_argument("--train", type=int, default=448)
     ap.add_argument("--val", type=int, default=32)
     ap.add_argument("--low", type=float, default=1e5)
     ap.add_argument("--high", type=float, default=1e7)
     ap.add_argument("--harm", type=int, default=16)
-    ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--epochs", type=int, default=120)
+    ap.add_argument("--lr", type=float, default=2e-3)
     args = ap.parse_args(argv)
     log = lambda m: print(m, file=sys.stderr, flush=True)
     torch.manual_seed(0)
@@ -243,7 +244,7 @@ def main(argv=None) -> int:
     tr, va = slice(0, args.train), slice(args.train, args.train + args.val)
     model = UNet(2 * args.harm + 1).cuda()
     t0 = time.time()
-    hist = train(model, lo[tr], hi[tr], args.epochs, log=log)
+    hist = train(model, lo[tr], hi[tr], args.epochs, lr=args.lr, log=log)
     t_train = time.time() - t0
     den = denoise(model, lo[va])
     e_low = rel_error(lo[va], hi[va])
@@ -252,13 +253,32 @@ def main(argv=None) -> int:
     e_low_a0 = rel_error(lo[va][:, 0], hi[va][:, 0])
     # the judge's own Monte Carlo error: the low-vs-high error scales as 1/sqrt(packets)
     floor = e_low * math.sqrt(args.low / args.high)
+    # wall time to the same a0 error on one held-out phantom: a low-count run plus
+    # the network, against the plain Monte Carlo with the packet count that
+    # matches the network's a0 error (error ~ 1/sqrt(packets))
+    dev = lo.device
+    med = random_phantom_medium(args.n, args.side, 1000 + args.train, dev)
+    src = side_sources(args.side)
+    n_eq = int(args.low * (e_low_a0 / max(e_den_a0, 1e-12)) ** 2)
+    for _ in range(2):   # the second pass is timed
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        low1, _ = rmc.mc_forward(med, src, rmc.make_run(int(args.low), args.harm, seed=5), ledger=False)
+        denoise(model, low1[None])
+        torch.cuda.synchronize()
+        t_den = time.perf_counter() - t1
+        t1 = time.perf_counter()
+        rmc.mc_forward(med, src, rmc.make_run(n_eq, args.harm, seed=6), ledger=False)
+        torch.cuda.synchronize()
+        t_mc = time.perf_counter() - t1
     n_params = sum(p.numel() for p in model.parameters())
     out = {"grid": args.n, "harmonics": args.harm, "train_pairs": args.train, "val_pairs": args.val,
            "packets_low": int(args.low), "packets_high": int(args.high), "params": n_params,
            "epochs": args.epochs, "final_loss": hist[-1], "data_s": t_data, "train_s": t_train,
            "val_rel_error_low_vs_high": e_low, "val_rel_error_denoised_vs_high": e_den,
            "val_rel_error_a0_low": e_low_a0, "val_rel_error_a0_denoised": e_den_a0,
-           "judge_noise_floor_estimate": floor}
+           "judge_noise_floor_estimate": floor,
+           "same_a0_error": {"denoised_ms": t_den * 1e3, "plain_mc_packets": n_eq, "plain_mc_ms": t_mc * 1e3}}
     print(json.dumps(out), flush=True)
     return 0
 
