@@ -28,9 +28,9 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
 # reads for a plain 1 GiB device copy.  Valid only for the kernel source it
 # was measured on: reported as null once that source changes.
 TRAFFIC = {
-    "source_sha256": "e171396203168ebb3f0d35fee326d7731441e888d9df691b3c4219efe01719dc",
-    "fetch_kib_per_launch": 213458.45, "fetch_factor": 2.000,
-    "write_kib_per_launch": 601734.04, "write_factor": 1.000,
+    "source_sha256": "eda107506edd8c095af87e7e14986e119c69c352a58ed2f195617a5dd96ac034",
+    "fetch_kib_per_launch": 217749.94, "fetch_factor": 2.000,
+    "write_kib_per_launch": 652811.28, "write_factor": 1.000,
 }
 
 
