@@ -144,3 +144,35 @@ def test_tuning_set_get_and_workspace():
         assert rmc.mc_get_tuning()["job_packets"] == 4096
     finally:
         rmc.mc_set_tuning(base)
+
+
+def test_batch_arguments_checked_on_host():
+    """mc_batch_workspace_bytes / mc_run_batch reject empty or oversized
+    batches, mixed harmonic orders and invalid problems before any GPU work."""
+    L, lib = _lib()
+    m = _medium(L)
+    src = (L.mc_source * 1)(_pencil(L))
+    run4 = L.mc_run(1000, 0, 0, 0, 4, 1e-4, 10.0, 0)
+    run5 = L.mc_run(1000, 0, 0, 0, 5, 1e-4, 10.0, 0)
+    ok = L.mc_problem(m, src, 1, run4, 0, 0x2000, None)
+    assert lib.mc_batch_workspace_bytes((L.mc_problem * 1)(ok), 1) > 0
+    assert lib.mc_batch_workspace_bytes((L.mc_problem * 1)(ok), 0) == 0
+    assert lib.mc_batch_workspace_bytes(None, 1) == 0
+    mixed = (L.mc_problem * 2)(ok, L.mc_problem(m, src, 1, run5, 0, 0x2000, None))
+    assert lib.mc_batch_workspace_bytes(mixed, 2) == 0
+    assert lib.mc_run_batch(mixed, 2, 0x3000, 1 << 30, None) == L.MC_ERR_INVALID_ARG
+    bad = L.mc_problem(m, src, 1, L.mc_run(0, 0, 0, 0, 4, 1e-4, 10.0, 0), 0, 0x2000, None)
+    assert lib.mc_run_batch((L.mc_problem * 1)(bad), 1, 0x3000, 1 << 30, None) == L.MC_ERR_INVALID_ARG
+    nocoeffs = L.mc_problem(m, src, 1, run4, 0, None, None)
+    assert lib.mc_run_batch((L.mc_problem * 1)(nocoeffs), 1, 0x3000, 1 << 30, None) == L.MC_ERR_INVALID_ARG
+    assert lib.mc_run_batch((L.mc_problem * 1)(ok), 5000, 0x3000, 1 << 30, None) == \
+        L.MC_ERR_INVALID_ARG
+    # too small a workspace is reported before anything is enqueued
+    assert lib.mc_run_batch((L.mc_problem * 1)(ok), 1, 0x3000, 16, None) == L.MC_ERR_WORKSPACE
+
+
+def test_denoiser_arguments_checked_on_host():
+    L, lib = _lib()
+    assert lib.dn_conv3x3_fwd(None, 0x1000, None, 0x2000, 1, 1, 1, 4, 4, None) == L.MC_ERR_INVALID_ARG
+    assert lib.dn_conv3x3_fwd(0x1000, 0x1000, None, 0x2000, 0, 1, 1, 4, 4, None) == L.MC_ERR_INVALID_ARG
+    assert lib.dn_conv3x3_wgrad(0x1000, 0x1000, 0x2000, 1, 1, 1, 4, -1, None) == L.MC_ERR_INVALID_ARG
