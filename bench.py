@@ -191,6 +191,35 @@ def batch_workload(args) -> dict:
             "speedup": t_seq / t_batch, "tuning": tuned}
 
 
+def pencil32(args) -> dict:
+    """Forward MC on the 32x32 pencil-beam medium (0.5 mm pixels, mua 0.05,
+    mus 5, g 0.8) at args.packets packets, N = 8 and N = 16 (at 1e8 packets
+    both take the tiled transport; the whole-grid kernel serves small runs)."""
+    import torch
+    import phantoms as P
+    from paper_1608_05238_amd import rmc
+    c = P.config1()
+    med = rmc.Medium.from_phantom(c.phantom)
+    n = int(args.packets)
+    res = {}
+    for N in (8, 16):
+        rmc.mc_forward(med, c.sources, rmc.make_run(min(n, 1_000_000), N), ledger=False)   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, led = rmc.mc_forward(med, c.sources, rmc.make_run(n, N, seed=1))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        L = rmc.ledger_dict(led)
+        whole = 32 * 32 * (2 * N + 1) * 8 <= 144 * 1024 and n <= rmc.mc_get_tuning()["grid_max_packets"]
+        res[f"N{N}"] = {"packets_per_s": n / dt, "ms": dt * 1e3, "visits_per_packet": L["visits"] / n,
+                        "mode": "whole-grid LDS tally" if whole else "tiled"}
+        log(f"pencil32 N={N}: {n / dt:.3e} packets/s")
+    return {"metric": "packets/s fwd MC, 32x32 pencil beam", "value": res["N8"]["packets_per_s"],
+            "unit": "packets/s", "higher_is_better": True, "n_gpus": 1, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "pencil32: 32x32 pixels of 0.5 mm, mua 0.05, mus 5, g 0.8, pencil beam",
+                       "packets": n}, "runs": res}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -209,6 +238,8 @@ def main() -> int:
     ap.add_argument("--batch-min", type=float, default=1e6)
     ap.add_argument("--batch-max", type=float, default=1e7)
     ap.add_argument("--autotune", action="store_true", help="with --batch: autotune before timing")
+    ap.add_argument("--pencil32", action="store_true",
+                    help="instead of the throughput line, time the 32x32 pencil-beam forward run (N = 8 and 16)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -227,6 +258,9 @@ def main() -> int:
         return 0
     if args.batch:
         print(json.dumps(batch_workload(args)), flush=True)
+        return 0
+    if args.pencil32:
+        print(json.dumps(pencil32(args)), flush=True)
         return 0
     dev = torch.device("cuda", 0)
     if args.copy_probe_mib > 0:

@@ -259,13 +259,16 @@ mc_status mc_philox_fill(uint64_t seed, uint32_t tag, uint64_t pid0, uint64_t n,
  *                 per CU)
  *  finish_packets once every packet is launched and at most this many remain
  *                 they finish without migration (0: live_packets / 128)
+ *  grid_max_packets  a run whose FP64 tally fits one workgroup's LDS uses the
+ *                 whole-grid kernel only up to this many packets, larger runs
+ *                 the tiled transport (0: 2^21)
  * mc_set_tuning(NULL) restores the built-in defaults. */
 typedef struct {
     uint64_t live_packets;
     uint32_t job_packets;
     uint32_t max_visits;
     uint32_t tile;
-    uint32_t reserved;
+    uint32_t grid_max_packets;
     uint64_t finish_packets;
 } mc_tuning;
 mc_status mc_set_tuning(const mc_tuning *tuning_h);

@@ -62,7 +62,7 @@ class mc_problem(C.Structure):
 
 class mc_tuning(C.Structure):
     _fields_ = [("live_packets", C.c_uint64), ("job_packets", C.c_uint32), ("max_visits", C.c_uint32),
-                ("tile", C.c_uint32), ("reserved", C.c_uint32), ("finish_packets", C.c_uint64)]
+                ("tile", C.c_uint32), ("grid_max_packets", C.c_uint32), ("finish_packets", C.c_uint64)]
 
 
 _lib = None

@@ -43,7 +43,7 @@ constexpr int kMaxSrc = 8;
 constexpr int kMaxProf = 2 * (2 * MC_NHARM_MAX + 1);  // profile coefficients over all sources
 // whole-grid mode: 12 waves share one LDS tally (8 for high orders, whose
 // harmonic vectors need more registers)
-constexpr int grid_block(int nh) { return nh <= 16 ? 768 : 512; }
+constexpr int grid_block(int nh) { return nh <= 16 ? 1024 : 512; }
 constexpr int kBlockTile = 512;                        // tiled mode: 8 waves per workgroup, 2 workgroups per CU
 constexpr uint64_t kChunk = 1ull << 22;                // whole-grid mode: packets per launch
 constexpr size_t kLdsGridMax = 144 * 1024;             // whole-grid mode: FP64 tally bytes in LDS
@@ -564,14 +564,11 @@ __global__ void __launch_bounds__(grid_block(NH)) k_transport_grid(Params P) {
 
     Packet p;
     idle_packet(p, 0, 0);
-    float h[K], acc[K];
+    float acc[K];
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
-        h[j] = 0.f;
-        acc[j] = 0.f;
-    }
+    for (int j = 0; j < K; ++j) acc[j] = 0.f;
     LedgerRegs L;
-    bool more = true, dirty = false;
+    bool more = true;
     const unsigned long long lt_mask = (1ull << lane) - 1ull;
 
     for (;;) {
@@ -586,35 +583,30 @@ __global__ void __launch_bounds__(grid_block(NH)) k_transport_grid(Params P) {
                 if (base + ndead >= P.npk) more = false;
                 if (!p.alive) {
                     const unsigned long long my = base + __popcll(dead & lt_mask);
-                    if (my < P.npk && launch_state(P, P.pid0 + my, p, L)) dirty = true;
+                    if (my < P.npk) launch_state(P, P.pid0 + my, p, L);
                 }
             }
         }
         if (!__ballot(p.alive)) {
             if (!more) break;
         }
-        refresh_harmonics<NH>(dirty, p, h);
-        dirty = false;
-        int ev = EV_NONE, pix = 0;
+        // every lane steps and scatters (no branch); a free lane's results are discarded
+        const bool live = p.alive;
+        const int pix = live ? p.iz * P.nx + p.ix : 0;
         float T = 0.f, dw = 0.f;
-        if (p.alive) {
-            pix = p.iz * P.nx + p.ix;
-            ev = step(P, p, P.med[pix], T, dw);
-            L.absorbed += (double)dw;
-            L.segments += 1;
-        }
-#pragma unroll
-        for (int j = 0; j < K; ++j) acc[j] = fmaf(T, h[j], acc[j]);
-        bool flush = false;
-        if (ev == EV_SCATTER) {
-            if (scatter_dir(P, p, P.g[pix], L)) dirty = true;
-            else flush = true;
-        } else if (ev != EV_NONE) {
-            flush = true;
-            if (ev == EV_ESCAPE) {
-                L.escaped += p.w;
-                p.alive = false;
-            }
+        int ev = step(P, p, P.med[pix], T, dw);
+        ev = live ? ev : EV_NONE;
+        T = live ? T : 0.f;
+        dw = live ? dw : 0.f;
+        L.absorbed += (double)dw;
+        L.segments += live ? 1u : 0u;
+        deposit_harmonics<NH>(T, p.sx, p.sz, acc);   // direction of the segment, before any scatter
+        const bool at = ev == EV_SCATTER;
+        const bool killed = scatter_masked(P, p, at, P.g[pix], L);
+        const bool flush = killed || (ev != EV_NONE && !at);
+        if (ev == EV_ESCAPE) {
+            L.escaped += p.w;
+            p.alive = false;
         }
         if (flush) {
             L.visits += 1;
@@ -1461,6 +1453,7 @@ Profile &profile_state() {
 // Tiled-mode sizing.  Tiles are square, as large as lets two workgroups of a
 // CU hold their tile's FP64 tally and medium in LDS.
 constexpr uint64_t kLiveMax = 1ull << 24;     // live packets per generation
+constexpr uint64_t kGridMaxPackets = 1ull << 21;   // larger runs take the tiled transport
 constexpr uint32_t kJobSize = 4096;           // packets per job
 constexpr uint32_t kMaxVisitsPerStay = 32;    // a packet pauses after this many visits in one job
 constexpr int kTileWavesMax = 256 * 16;       // bound on resident waves of the tiled kernel
@@ -1474,6 +1467,7 @@ struct TileTuning {
     uint32_t job = kJobSize, maxvis = kMaxVisitsPerStay, tailvis = 1u << 30;
     uint64_t finish = 0;   // 0: live / 128
     int tile = 0;   // 0: largest square tile for two workgroups per CU
+    uint64_t grid_max = kGridMaxPackets;   // whole-grid kernel only up to this many packets
 };
 TileTuning tuning_from_env() {
     TileTuning v;
@@ -1520,8 +1514,13 @@ size_t tile_lds_bytes(int tw, int th, int K) {
     return tal + (size_t)tw * th * (sizeof(float4) + sizeof(float));
 }
 
-bool is_tiled(const mc_medium *m, const mc_run *run) {
-    return (size_t)m->nx * m->nz * (2 * run->n_harm + 1) * sizeof(double) > kLdsGridMax;
+// Tiled transport unless the whole FP64 tally fits one workgroup's LDS and the
+// run is small (the tiled mode's per-generation overhead is ~10 ms; measured
+// on a 32x32 pencil beam, the tiled mode overtakes the whole-grid kernel near
+// 2e6 packets and is 5x faster at 1e8).
+bool is_tiled(const mc_medium *m, const mc_run *run, const TileTuning &tt) {
+    if ((size_t)m->nx * m->nz * (2 * run->n_harm + 1) * sizeof(double) > kLdsGridMax) return true;
+    return run->n_packets > tt.grid_max;
 }
 
 // Whole-grid mode: medium, CDF, tally, ledger and per-chunk counters.
@@ -1529,7 +1528,7 @@ Layout layout(const mc_medium *m, const mc_source *src, const mc_run *run) {
     Layout L{};
     const size_t npix = (size_t)m->nx * m->nz;
     const int K = 2 * run->n_harm + 1;
-    L.tiled = is_tiled(m, run);
+    L.tiled = is_tiled(m, run, tuning_snapshot());
     size_t off = 0;
     L.med = off;
     off = align_up(off + npix * sizeof(float4));
@@ -1981,7 +1980,7 @@ mc_status run_mc(const mc_medium *m, const mc_source *src, int n_src, const mc_r
     if (st != MC_OK) return st;
     if (!coeffs) return MC_ERR_INVALID_ARG;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    if (is_tiled(m, run)) {
+    if (is_tiled(m, run, tuning_snapshot())) {
         const BatchProblem one{m, src, n_src, run, adjoint, coeffs, ledger};
         return run_batch(&one, 1, ws, ws_bytes, s);
     }
@@ -2036,7 +2035,7 @@ extern "C" {
 
 size_t mc_workspace_bytes(const mc_medium *medium, const mc_source *src, int n_src, const mc_run *run) {
     if (validate(medium, src, n_src, run) != MC_OK) return 0;
-    if (is_tiled(medium, run)) {
+    if (is_tiled(medium, run, tuning_snapshot())) {
         const BatchProblem one{medium, src, n_src, run, 0, nullptr, nullptr};
         return batch_layout(&one, 1).total;
     }
@@ -2223,6 +2222,7 @@ mc_status mc_set_tuning(const mc_tuning *t) {
             t->job_packets > (1u << 20) || t->max_visits < 1 || t->tile > 256 || t->finish_packets > (1ull << 26))
             return MC_ERR_INVALID_ARG;
         v.live = t->live_packets;
+        v.grid_max = t->grid_max_packets ? t->grid_max_packets : kGridMaxPackets;
         v.job = t->job_packets;
         v.maxvis = t->max_visits;
         v.tile = (int)t->tile;
@@ -2242,6 +2242,7 @@ mc_status mc_get_tuning(mc_tuning *t) {
     t->max_visits = v.maxvis;
     t->tile = (uint32_t)v.tile;
     t->finish_packets = v.finish;
+    t->grid_max_packets = (uint32_t)std::min<uint64_t>(v.grid_max, 0xFFFFFFFFull);
     return MC_OK;
 }
 

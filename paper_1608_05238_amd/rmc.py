@@ -306,7 +306,7 @@ def mc_profile_read(reset: bool = True):
     return ms.value, n.value
 
 
-_TUNING_FIELDS = ("live_packets", "job_packets", "max_visits", "tile", "finish_packets")
+_TUNING_FIELDS = ("live_packets", "job_packets", "max_visits", "tile", "finish_packets", "grid_max_packets")
 
 
 def mc_get_tuning() -> dict:

@@ -134,7 +134,7 @@ def test_tuning_set_get_and_workspace():
         small = lib.mc_workspace_bytes(C.byref(m), src, 1, C.byref(run))
         rmc.mc_set_tuning({"live_packets": 1 << 22, "job_packets": 1024, "max_visits": 7, "tile": 9})
         assert rmc.mc_get_tuning() == {"live_packets": 1 << 22, "job_packets": 1024, "max_visits": 7, "tile": 9,
-                                       "finish_packets": 0}
+                                       "finish_packets": 0, "grid_max_packets": 1 << 21}
         big = lib.mc_workspace_bytes(C.byref(m), src, 1, C.byref(run))
         assert big > small + 3 * (1 << 20) * 64
         for bad in ({"live_packets": 10}, {"job_packets": 1}, {"max_visits": 0}, {"tile": 1000}):
