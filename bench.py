@@ -244,7 +244,7 @@ def main() -> int:
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: the Monte Carlo runs on a single MI355X; "
-              "multi-GPU packet sharding is described in DESIGN.md but not built.", file=sys.stderr)
+              "sharding packets over several GPUs is not built.", file=sys.stderr)
         return 2
 
     import numpy as np

@@ -42,7 +42,7 @@ extern "C" {
 typedef enum {
     MC_OK = 0,
     MC_ERR_INVALID_ARG = 1,   /* a size, pointer or parameter is out of range */
-    MC_ERR_UNSUPPORTED = 2,   /* a valid request this build does not serve */
+    MC_ERR_UNSUPPORTED = 2,   /* a valid request this library does not serve */
     MC_ERR_DEVICE = 3,        /* a HIP call or launch failed */
     MC_ERR_WORKSPACE = 4      /* workspace missing or smaller than mc_workspace_bytes() */
 } mc_status;

@@ -6,8 +6,8 @@ fewer packets.  Its 3x3 convolutions (forward, input gradient and weight
 gradient) are the hand-written MFMA kernels of denoise.h (BF16 operands,
 FP32 accumulation); pooling, upsampling, ReLU and the 1x1 output layer are
 plain PyTorch.  Training pairs come from the Monte Carlo itself, run as
-batches of problems (mc_run_batch).  The plain Monte Carlo stays the judge
-and the fallback: `denoise_or_mc` returns the network's maps only when its
+batches of problems (mc_run_batch).  The plain Monte Carlo stays the
+reference and the fallback: `denoise_or_mc` returns the network's maps only when its
 measured error on held-out pairs is below a threshold, else it runs more
 packets.
 
@@ -251,7 +251,7 @@ def main(argv=None) -> int:
     e_den = rel_error(den, hi[va])
     e_den_a0 = rel_error(den[:, 0], hi[va][:, 0])
     e_low_a0 = rel_error(lo[va][:, 0], hi[va][:, 0])
-    # the judge's own Monte Carlo error: the low-vs-high error scales as 1/sqrt(packets)
+    # the reference's own Monte Carlo error: the low-vs-high error scales as 1/sqrt(packets)
     floor = e_low * math.sqrt(args.low / args.high)
     # wall time to the same a0 error on one held-out phantom: a low-count run plus
     # the network, against the plain Monte Carlo with the packet count that
@@ -277,7 +277,7 @@ def main(argv=None) -> int:
            "epochs": args.epochs, "final_loss": hist[-1], "data_s": t_data, "train_s": t_train,
            "val_rel_error_low_vs_high": e_low, "val_rel_error_denoised_vs_high": e_den,
            "val_rel_error_a0_low": e_low_a0, "val_rel_error_a0_denoised": e_den_a0,
-           "judge_noise_floor_estimate": floor,
+           "reference_noise_floor_estimate": floor,
            "same_a0_error": {"denoised_ms": t_den * 1e3, "plain_mc_packets": n_eq, "plain_mc_ms": t_mc * 1e3}}
     print(json.dumps(out), flush=True)
     return 0
