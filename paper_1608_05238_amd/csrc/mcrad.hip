@@ -384,9 +384,9 @@ __device__ __forceinline__ int step(const PP &P, Packet &p, const float4 m, floa
     const float d = fminf(dfx, dfz);
     const float od = m.y * d;
     const bool scat = od > p.tau;
-    const float l = scat ? p.tau * m.w : d;
+    const float l = scat ? p.tau * m.z : d;
     dw = -p.w * expm1_neg(m.x * l);   // weight absorbed on the segment
-    T = m.x > 0.f ? dw * m.z : p.w * l;
+    T = m.x > 0.f ? dw * __builtin_amdgcn_rcpf(m.x) : p.w * l;   // track length weighted by the weight
     p.w -= dw;
     const float nfx = fminf(fmaxf(p.fx + l * p.sx, 0.f), 1.f);
     const float nfz = fminf(fmaxf(p.fz + l * p.sz, 0.f), 1.f);
@@ -594,7 +594,8 @@ __global__ void __launch_bounds__(grid_block(NH)) k_transport_grid(Params P) {
         const bool live = p.alive;
         const int pix = live ? p.iz * P.nx + p.ix : 0;
         float T = 0.f, dw = 0.f;
-        int ev = step(P, p, P.med[pix], T, dw);
+        const float4 mm = P.med[pix];
+        int ev = step(P, p, mm, T, dw);
         ev = live ? ev : EV_NONE;
         T = live ? T : 0.f;
         dw = live ? dw : 0.f;
@@ -602,7 +603,7 @@ __global__ void __launch_bounds__(grid_block(NH)) k_transport_grid(Params P) {
         L.segments += live ? 1u : 0u;
         deposit_harmonics<NH>(T, p.sx, p.sz, acc);   // direction of the segment, before any scatter
         const bool at = ev == EV_SCATTER;
-        const bool killed = scatter_masked(P, p, at, P.g[pix], L);
+        const bool killed = scatter_masked(P, p, at, mm.w, L);
         const bool flush = killed || (ev != EV_NONE && !at);
         if (ev == EV_ESCAPE) {
             L.escaped += p.w;
@@ -935,7 +936,6 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
     constexpr int K = 2 * NH + 1;
     extern __shared__ double tally[];                  // [tw*th][K]
     float4 *smed = reinterpret_cast<float4 *>(tally + (((size_t)P.tw * P.th * K + 1) & ~size_t(1)));
-    float *sg = reinterpret_cast<float *>(smed + P.tw * P.th);
     __shared__ uint32_t s_job[5];
     __shared__ uint32_t s_next;
     const int lane = __lane_id();
@@ -971,7 +971,6 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
         const Hot H{pd.nx, pd.nz, pd.tag, pd.flags, pd.seed, pd.wth, pd.rm, pd.inv_rm};
         const int ntx = pd.ntx, local = (int)tile - pd.tile_base;
         const float4 *gmed = pd.med;
-        const float *gg = pd.g;
         double *t64 = pd.t64;
         const int tx0 = (local % ntx) * P.tw, tz0 = (local / ntx) * P.th;
         for (int i = threadIdx.x; i < ntp * K; i += blockDim.x) tally[i] = 0.0;
@@ -979,7 +978,6 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
             const int gx = tx0 + i % P.tw, gz = tz0 + i / P.tw;
             const bool in = gx < H.nx && gz < H.nz;
             smed[i] = in ? gmed[gz * H.nx + gx] : make_float4(0.f, 0.f, 0.f, 0.f);
-            sg[i] = in ? gg[gz * H.nx + gx] : 0.f;
         }
         __syncthreads();
 
@@ -1035,7 +1033,8 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
             const bool live = p.alive;
             const int lp = live ? (p.iz - tz0) * P.tw + (p.ix - tx0) : 0;
             float T = 0.f, dw = 0.f;
-            int ev = step(H, p, smed[lp], T, dw);
+            const float4 mm = smed[lp];
+            int ev = step(H, p, mm, T, dw);
             ev = live ? ev : EV_NONE;
             T = live ? T : 0.f;
             dw = live ? dw : 0.f;
@@ -1043,7 +1042,7 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
             L.segments += live ? 1u : 0u;
             deposit_harmonics<NH>(T, p.sx, p.sz, acc);   // direction of the segment, before any scatter
             const bool at = ev == EV_SCATTER;
-            const bool killed = scatter_masked(H, p, at, sg[lp], L);
+            const bool killed = scatter_masked(H, p, at, mm.w, L);
             const bool flush = killed || (ev != EV_NONE && !at);
             if (ev == EV_ESCAPE) {
                 L.escaped += p.w;
@@ -1247,11 +1246,14 @@ __global__ void k_trace(Params P, const uint64_t *pids, int n_pids, mc_event *ev
 }
 
 // ------------------------------------------------------------------ setup / post kernels
-__global__ void k_setup_medium(int npix, float dx, const float *mua, const float *mus, float4 *med) {
+// Medium table of the transport: {mua dx, mus dx, 1/(mus dx), g} per pixel,
+// one 16-byte load per step (the scatter reads g from the same load).
+__global__ void k_setup_medium(int npix, float dx, const float *mua, const float *mus, const float *g,
+                               float4 *med) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= npix) return;
     const float a = mua[i] * dx, s = mus[i] * dx;
-    med[i] = make_float4(a, s, a > 0.f ? 1.f / a : 0.f, s > 0.f ? 1.f / s : 0.f);
+    med[i] = make_float4(a, s, s > 0.f ? 1.f / s : 0.f, g[i]);
 }
 
 __global__ void k_fill_zero(uint32_t *p, size_t n) {
@@ -1511,7 +1513,7 @@ struct Layout {
 
 size_t tile_lds_bytes(int tw, int th, int K) {
     const size_t tal = ((size_t)tw * th * K * sizeof(double) + 15) & ~size_t(15);
-    return tal + (size_t)tw * th * (sizeof(float4) + sizeof(float));
+    return tal + (size_t)tw * th * sizeof(float4);
 }
 
 // Tiled transport unless the whole FP64 tally fits one workgroup's LDS and the
@@ -1828,7 +1830,7 @@ mc_status run_batch(const BatchProblem *pb, int n, void *ws, size_t ws_bytes, hi
         if ((st = launch_zero(base + B.led[i], B.ledc[i] + 8 * sizeof(unsigned long long) - B.led[i], s)) != MC_OK)
             return st;
         hipLaunchKernelGGL(k_setup_medium, dim3((npix + 255) / 256), dim3(256), 0, s, npix, m->dx, m->mua_d,
-                           m->mus_d, reinterpret_cast<float4 *>(base + B.med[i]));
+                           m->mus_d, m->g_d, reinterpret_cast<float4 *>(base + B.med[i]));
         double map_abs_sum = 0;
         todo[i] = pb[i].run->n_packets;
         if (pb[i].src[0].kind == MC_SRC_MAP) {
@@ -1993,7 +1995,7 @@ mc_status run_mc(const mc_medium *m, const mc_source *src, int n_src, const mc_r
     // zero the tally, ledger and chunk counters
     if ((st = launch_zero(base + L.t64, L.counters + L.n_chunks * sizeof(unsigned long long) - L.t64, s)) != MC_OK)
         return st;
-    hipLaunchKernelGGL(k_setup_medium, dim3((npix + 255) / 256), dim3(256), 0, s, npix, m->dx, m->mua_d, m->mus_d,
+    hipLaunchKernelGGL(k_setup_medium, dim3((npix + 255) / 256), dim3(256), 0, s, npix, m->dx, m->mua_d, m->mus_d, m->g_d,
                        reinterpret_cast<float4 *>(base + L.med));
     double map_abs_sum = 0;
     if (src[0].kind == MC_SRC_MAP) {
@@ -2157,7 +2159,7 @@ mc_status mc_trace(const mc_medium *m, const mc_source *src, int n_src, const mc
     char *base = static_cast<char *>(ws);
     Params P;
     double map_abs_sum = 0;
-    hipLaunchKernelGGL(k_setup_medium, dim3((npix + 255) / 256), dim3(256), 0, 0, npix, m->dx, m->mua_d, m->mus_d,
+    hipLaunchKernelGGL(k_setup_medium, dim3((npix + 255) / 256), dim3(256), 0, 0, npix, m->dx, m->mua_d, m->mus_d, m->g_d,
                        reinterpret_cast<float4 *>(base + L.med));
     if (src[0].kind == MC_SRC_MAP) {
         double *cdf = reinterpret_cast<double *>(base + L.cdf);
