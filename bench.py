@@ -28,9 +28,9 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
 # reads for a plain 1 GiB device copy.  Valid only for the kernel source it
 # was measured on: reported as null once that source changes.
 TRAFFIC = {
-    "source_sha256": "eda107506edd8c095af87e7e14986e119c69c352a58ed2f195617a5dd96ac034",
-    "fetch_kib_per_launch": 217749.94, "fetch_factor": 2.000,
-    "write_kib_per_launch": 652811.28, "write_factor": 1.000,
+    "source_sha256": "26c6f9b8e57d5f4e600c438818804e9fb0dd7177ed9964580f6bc0555c6c517c",
+    "fetch_kib_per_launch": 221246.53, "fetch_factor": 2.000,
+    "write_kib_per_launch": 641803.57, "write_factor": 1.000,
 }
 
 
