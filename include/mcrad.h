@@ -129,7 +129,17 @@ size_t mc_workspace_bytes(const mc_medium *medium, const mc_source *src, int n_s
  * track-length tally (eq. Fourier_terms) normalised by the packet count
  * (Sec. 6).  coeffs_d: FP64 [2N+1][nz][nx] (overwritten).  ledger_d: device
  * mc_ledger or NULL.  workspace_d: >= mc_workspace_bytes() bytes, 256-byte
- * aligned; its contents are scratch. */
+ * aligned; its contents are scratch.
+ * Tally precision: each pixel visit is summed in FP32 registers; the map is
+ * FP64.  Grids whose FP64 tally exceeds one workgroup's LDS stage the visits
+ * in LDS tiles as 64-bit fixed-point sums of value * 2^(32-e), where 2^e
+ * bounds the largest packet weight of the run (the source profile bound
+ * |c0| + 2 sum |c_n|, times max(1, m W_th) for roulette survivors, times
+ * max|q| / mean|q| for the equal-count map launch): every visit is rounded to
+ * a multiple of 2^(e-32) before the FP64 sum.  A run whose weight bound
+ * exceeds 2^32 returns MC_ERR_UNSUPPORTED.  Should a tile's sums ever risk
+ * leaving the 64-bit range (not reachable with physical media and the
+ * default tuning), the whole output of the run is NaN rather than wrong. */
 mc_status mc_forward(const mc_medium *medium, const mc_source *src, int n_src, const mc_run *run,
                      double *coeffs_d, mc_ledger *ledger_d, void *workspace_d, size_t workspace_bytes,
                      void *stream);
@@ -262,6 +272,10 @@ mc_status mc_philox_fill(uint64_t seed, uint32_t tag, uint64_t pid0, uint64_t n,
  *  grid_max_packets  a run whose FP64 tally fits one workgroup's LDS uses the
  *                 whole-grid kernel only up to this many packets, larger runs
  *                 the tiled transport (0: 2^21)
+ *  flush_track    a pixel visit whose accumulated track length, in units of
+ *                 the run's weight bound, exceeds this many pixels is added
+ *                 to the tile tally in parts, 0 .. 65536 (0: 65536)
+ *  reserved       0
  * mc_set_tuning(NULL) restores the built-in defaults. */
 typedef struct {
     uint64_t live_packets;
@@ -270,6 +284,8 @@ typedef struct {
     uint32_t tile;
     uint32_t grid_max_packets;
     uint64_t finish_packets;
+    float flush_track;
+    uint32_t reserved;
 } mc_tuning;
 mc_status mc_set_tuning(const mc_tuning *tuning_h);
 mc_status mc_get_tuning(mc_tuning *tuning_h);

@@ -17,11 +17,13 @@ MC_FLAG_LITERAL_TRUNCATION = 1
 MC_FLAG_EQUAL_COUNT = 2
 MC_NHARM_MAX = 32
 
-# exported symbols declared in include/mcrad.h
+# exported symbols declared in include/*.h
 SYMBOLS = ("mc_workspace_bytes", "mc_forward", "mc_adjoint", "mc_residual", "mc_gradient", "mc_absorbed",
            "mc_adjoint_source", "mc_gradient_h", "mc_detect", "mc_trace", "mc_philox_fill", "mc_profile_enable",
            "mc_profile_read", "mc_set_tuning", "mc_get_tuning", "mc_batch_workspace_bytes", "mc_run_batch",
-           "mc_status_string", "mc_build_info", "dn_conv3x3_fwd", "dn_conv3x3_wgrad")
+           "mc_status_string", "mc_build_info", "dn_conv3x3_fwd", "dn_conv3x3_wgrad",
+           "mb_lds_atomics", "mb_global_atomics_f64", "mb_copy", "mb_fma_f32", "mb_wall_clock_khz")
+MB_LDS_ADD_F64, MB_LDS_ADD_F32, MB_LDS_ADD_U64, MB_LDS_ADD_U32, MB_LDS_ADD_F64_ROW33 = range(5)
 
 
 class mc_medium(C.Structure):
@@ -62,7 +64,8 @@ class mc_problem(C.Structure):
 
 class mc_tuning(C.Structure):
     _fields_ = [("live_packets", C.c_uint64), ("job_packets", C.c_uint32), ("max_visits", C.c_uint32),
-                ("tile", C.c_uint32), ("grid_max_packets", C.c_uint32), ("finish_packets", C.c_uint64)]
+                ("tile", C.c_uint32), ("grid_max_packets", C.c_uint32), ("finish_packets", C.c_uint64),
+                ("flush_track", C.c_float), ("reserved", C.c_uint32)]
 
 
 _lib = None
@@ -116,6 +119,16 @@ def load() -> C.CDLL:
     lib.dn_conv3x3_fwd.restype = St
     lib.dn_conv3x3_wgrad.argtypes = [V, V, V, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, V]
     lib.dn_conv3x3_wgrad.restype = St
+    lib.mb_lds_atomics.argtypes = [C.c_int, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, V, V, V]
+    lib.mb_lds_atomics.restype = St
+    lib.mb_global_atomics_f64.argtypes = [V, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, V]
+    lib.mb_global_atomics_f64.restype = St
+    lib.mb_copy.argtypes = [V, V, C.c_uint64, V]
+    lib.mb_copy.restype = St
+    lib.mb_fma_f32.argtypes = [V, C.c_uint32, C.c_uint32, V, V]
+    lib.mb_fma_f32.restype = St
+    lib.mb_wall_clock_khz.argtypes = [C.c_int, P(C.c_int)]
+    lib.mb_wall_clock_khz.restype = St
     lib.mc_status_string.argtypes = [C.c_int]
     lib.mc_status_string.restype = C.c_char_p
     lib.mc_build_info.argtypes = []

@@ -15,7 +15,7 @@ import time
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-SRCS = [os.path.join(PKG, "csrc", "mcrad.hip"), os.path.join(PKG, "csrc", "denoise.hip")]
+SRCS = [os.path.join(PKG, "csrc", n) for n in ("mcrad.hip", "denoise.hip", "microbench.hip")]
 OUT = os.path.join(PKG, "librmc.so")
 INCLUDE = os.path.join(ROOT, "include")
 

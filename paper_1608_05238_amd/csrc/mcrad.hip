@@ -52,6 +52,10 @@ constexpr uint32_t kInvalidTile = 0xFFFFFFFFu;
 constexpr uint32_t kSlice = 256;                       // queue slots a wave reserves at a time
 constexpr float kPi = 3.14159265358979323846f;
 constexpr uint32_t kMaxInteractions = 1u << 24;         // hard cap per packet (guards invalid media)
+// tiled mode: the LDS tile tally holds 64-bit fixed-point sums, value * 2^(32 - e)
+// where 2^e bounds the magnitude of any packet weight of the run (fixed_add)
+constexpr int kFixBits = 32;
+constexpr double kFlushTrackMax = 65536.0;             // see TileTuning::flush_track
 
 enum : int { EV_LAUNCH = 0, EV_CROSS = 1, EV_SCATTER = 2, EV_ESCAPE = 3, EV_KILL = 4, EV_NONE = 5 };
 
@@ -68,12 +72,15 @@ struct ProbDev {
     int nx, nz, ntx, tile_base;   // grid, tiles across, first global tile index
     uint32_t tag, flags;
     uint64_t seed;
-    float wth, rm, inv_rm, pad;
+    float wth, rm, inv_rm;
+    float flush_at;               // scaled |a0 accumulator| at which a visit is flushed in parts
+    float fx;                     // fixed-point scale of the LDS tile tally (a power of two)
+    double fx_inv;                // its inverse
     const float4 *med;
     const float *g;
     double *t64;
     double *led;
-    unsigned long long *ledc;
+    unsigned long long *ledc;     // [4]: jobs whose tile tally may have left the fixed-point range
 };
 
 // The values a step and a scatter read, uniform over a workgroup's job.
@@ -93,6 +100,10 @@ struct Params {
     float wth, rm, inv_rm;
     double total;
     double inv_qbar;            // MAP: npix / sum |q| (equal-count launch)
+    double wbound;              // bound on |packet weight| (launch weight, roulette gain)
+    float fx;                   // fixed-point scale of the visit sums (a power of two, fixed_add)
+    float flush_at;             // scaled |a0| of a visit at which it is flushed in parts
+    double fx_inv;              // 1 / fx
     const float4 *med;          // {mua dx, mus dx, 1/(mua dx), 1/(mus dx)}
     const float *g;
     const double *map;          // MAP source values (sign)
@@ -549,21 +560,37 @@ __device__ __forceinline__ void ledger_flush_block(double *led, unsigned long lo
     __syncthreads();   // the staging arrays may be reused by a next call
 }
 
+// Add v (already scaled by the run's fixed-point factor), rounded to the
+// nearest integer, to a 64-bit fixed-point LDS slot.  For |v| < 2^51 the FP64
+// sum v + 1.5 2^52 lies in [2^52, 2^53), where the spacing of doubles is 1, so
+// its bit pattern minus that of 1.5 2^52 is the rounded integer in two's
+// complement.  Integer adds are associative, so the slot holds the same sum in
+// any order of arrival, and LDS 64-bit integer atomics outrun FP64 ones on
+// this device.
+__device__ __forceinline__ void fixed_add(unsigned long long *slot, float v) {
+    const double d = (double)v + 0x1.8p52;
+    atomicAdd(slot, (unsigned long long)__double_as_longlong(d) - 0x4338000000000000ull);
+}
+
 // ------------------------------------------------------------------ whole-grid transport
-// Small grids: the whole FP64 tally [npix][K] lives in LDS for the
-// workgroup's life (LDS FP64 atomics), flushed to the HBM FP64 tally with
+// Small grids: the whole tally [npix][K] lives in LDS for the workgroup's life
+// as 64-bit fixed-point sums (fixed_add), added to the HBM FP64 tally with
 // coalesced atomics at the end.  Persistent waves refill dead lanes from a
 // global packet counter with one wave-aggregated atomic.
 template <int NH>
 __global__ void __launch_bounds__(grid_block(NH)) k_transport_grid(Params P) {
     constexpr int K = 2 * NH + 1;
-    extern __shared__ double tally[];
+    extern __shared__ unsigned long long gfx[];   // [npix][K] fixed-point sums (fixed_add)
+    __shared__ float s_mag;
     const int lane = __lane_id();
-    for (int i = threadIdx.x; i < P.npix * K; i += blockDim.x) tally[i] = 0.0;
+    for (int i = threadIdx.x; i < P.npix * K; i += blockDim.x) gfx[i] = 0ull;
+    if (threadIdx.x == 0) s_mag = 0.f;
     __syncthreads();
+    const float fx = P.fx, flush_at = P.flush_at;
 
     Packet p;
     idle_packet(p, 0, 0);
+    float mag = 0.f;   // sum of the |a0| this lane flushed: bounds every slot's magnitude
     float acc[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) acc[j] = 0.f;
@@ -601,34 +628,41 @@ __global__ void __launch_bounds__(grid_block(NH)) k_transport_grid(Params P) {
         dw = live ? dw : 0.f;
         L.absorbed += (double)dw;
         L.segments += live ? 1u : 0u;
-        deposit_harmonics<NH>(T, p.sx, p.sz, acc);   // direction of the segment, before any scatter
+        deposit_harmonics<NH>(T * fx, p.sx, p.sz, acc);   // direction of the segment, before any scatter
         const bool at = ev == EV_SCATTER;
         const bool killed = scatter_masked(P, p, at, mm.w, L);
-        const bool flush = killed || (ev != EV_NONE && !at);
+        const bool vend = killed || (ev != EV_NONE && !at);   // the visit ends
+        const bool flush = vend || fabsf(acc[0]) > flush_at;  // a long stay is flushed in parts
         if (ev == EV_ESCAPE) {
             L.escaped += p.w;
             p.alive = false;
         }
         if (flush) {
-            L.visits += 1;
-            double *t = tally + pix * K;
+            unsigned long long *t = gfx + pix * K;
 #pragma unroll
-            for (int j = 0; j < K; ++j) atomicAdd(t + j, (double)acc[j]);
+            for (int j = 0; j < K; ++j) fixed_add(t + j, acc[j]);
+            mag += fabsf(acc[0]);
         }
+        L.visits += vend ? 1u : 0u;
 #pragma unroll
         for (int j = 0; j < K; ++j) acc[j] = flush ? 0.f : acc[j];
     }
     ledger_flush_block(P.led, P.ledc, L);
+    float wm = mag;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) wm += __shfl_xor(wm, o);
+    if (lane == 0) atomicAdd(&s_mag, wm);
     __syncthreads();
+    if (threadIdx.x == 0 && !(s_mag < 0x1p62f)) atomicAdd(P.ledc + 4, 1ull);   // see k_normalise
     for (int i = threadIdx.x; i < P.npix * K; i += blockDim.x) {
-        const double v = tally[i];
+        const double v = (double)(long long)gfx[i] * P.fx_inv;
         if (v != 0.0) unsafeAtomicAdd(P.t64 + i, v);
     }
 }
 
 // ------------------------------------------------------------------ tiled transport
-// Larger grids: the grid is cut into tw x th tiles whose FP64 tallies fit in
-// LDS.  A run proceeds in generations.  Each generation, the live packets
+// Larger grids: the grid is cut into tw x th tiles whose tallies (64-bit
+// fixed-point sums, fixed_add) fit in LDS.  A run proceeds in generations.  Each generation, the live packets
 // (sorted by tile) are split into jobs of at most job_size packets of one
 // tile; a workgroup takes a job, keeps that tile's tally and medium in LDS,
 // and moves each packet until it leaves the tile, dies, or has made
@@ -934,10 +968,12 @@ __global__ void __launch_bounds__(256) k_bin_scatter(Params P) {
 template <int NH>
 __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu(NH <= 16 ? 4 : 2))) k_transport_tile(Params P) {
     constexpr int K = 2 * NH + 1;
-    extern __shared__ double tally[];                  // [tw*th][K]
-    float4 *smed = reinterpret_cast<float4 *>(tally + (((size_t)P.tw * P.th * K + 1) & ~size_t(1)));
+    // [tw*th][K] fixed-point sums: value * fx of the job's problem (fixed_add)
+    extern __shared__ unsigned long long fxt[];
+    float4 *smed = reinterpret_cast<float4 *>(fxt + (((size_t)P.tw * P.th * K + 1) & ~size_t(1)));
     __shared__ uint32_t s_job[5];
     __shared__ uint32_t s_next;
+    __shared__ float s_mag;
     const int lane = __lane_id();
     const int ntp = P.tw * P.th;
     const unsigned long long lt_mask = (1ull << lane) - 1ull;
@@ -956,6 +992,7 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
             s_job[3] = jb.z;
             s_job[4] = jb.w;
             s_next = 0;
+            s_mag = 0.f;
         }
         __syncthreads();
         if (!s_job[0]) break;
@@ -972,8 +1009,10 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
         const int ntx = pd.ntx, local = (int)tile - pd.tile_base;
         const float4 *gmed = pd.med;
         double *t64 = pd.t64;
+        const float fx = pd.fx;   // power of two: the scaled FP32 sums round exactly as unscaled ones
+        const float flush_at = pd.flush_at;
         const int tx0 = (local % ntx) * P.tw, tz0 = (local / ntx) * P.th;
-        for (int i = threadIdx.x; i < ntp * K; i += blockDim.x) tally[i] = 0.0;
+        for (int i = threadIdx.x; i < ntp * K; i += blockDim.x) fxt[i] = 0ull;
         for (int i = threadIdx.x; i < ntp; i += blockDim.x) {
             const int gx = tx0 + i % P.tw, gz = tz0 + i / P.tw;
             const bool in = gx < H.nx && gz < H.nz;
@@ -984,6 +1023,7 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
         Packet p;
         idle_packet(p, tx0, tz0);
         uint32_t nvis = 0;
+        float mag = 0.f;   // sum of the |a0| this lane flushed in this job: bounds every slot's magnitude
         float acc[K];
 #pragma unroll
         for (int j = 0; j < K; ++j) acc[j] = 0.f;
@@ -1040,10 +1080,13 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
             dw = live ? dw : 0.f;
             L.absorbed += (double)dw;
             L.segments += live ? 1u : 0u;
-            deposit_harmonics<NH>(T, p.sx, p.sz, acc);   // direction of the segment, before any scatter
+            deposit_harmonics<NH>(T * fx, p.sx, p.sz, acc);   // direction of the segment, before any scatter
             const bool at = ev == EV_SCATTER;
             const bool killed = scatter_masked(H, p, at, mm.w, L);
-            const bool flush = killed || (ev != EV_NONE && !at);
+            const bool vend = killed || (ev != EV_NONE && !at);   // the visit ends
+            // |a_n| <= a0 (one sign per packet): a long stay in one pixel is
+            // flushed in parts, so every flush stays inside fixed_add's range
+            const bool flush = vend || fabsf(acc[0]) > flush_at;
             if (ev == EV_ESCAPE) {
                 L.escaped += p.w;
                 p.alive = false;
@@ -1051,11 +1094,14 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
             bool leave = false;
             uint32_t dest = tile;
             if (flush) {
+                unsigned long long *t = fxt + lp * K;
+#pragma unroll
+                for (int j = 0; j < K; ++j) fixed_add(t + j, acc[j]);
+                mag += fabsf(acc[0]);
+            }
+            if (vend) {
                 L.visits += 1;
                 nvis += 1;
-                double *t = tally + lp * K;
-#pragma unroll
-                for (int j = 0; j < K; ++j) atomicAdd(t + j, (double)acc[j]);
                 if (ev == EV_CROSS) {
                     const int ox = p.ix < tx0 ? -1 : (p.ix >= tx0 + P.tw ? 1 : 0);
                     const int oz = p.iz < tz0 ? -1 : (p.iz >= tz0 + P.th ? 1 : 0);
@@ -1075,9 +1121,17 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
                 nvis = 0;
             }
         }
+        // no slot can exceed the sum of the magnitudes flushed into the tile;
+        // a job that could have wrapped the 64-bit sums is counted and its
+        // run's output becomes NaN (k_normalise)
+        float wm = mag;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) wm += __shfl_xor(wm, o);
+        if (lane == 0) atomicAdd(&s_mag, wm);
         __syncthreads();
+        if (threadIdx.x == 0 && !(s_mag < 0x1p62f)) atomicAdd(pd.ledc + 4, 1ull);
         for (int i = threadIdx.x; i < ntp * K; i += blockDim.x) {
-            const double v = tally[i];
+            const double v = (double)(long long)fxt[i] * pd.fx_inv;
             const int lp = i / K, c = i - lp * K;
             const int gx = tx0 + lp % P.tw, gz = tz0 + lp / P.tw;
             if (v != 0.0 && gx < H.nx && gz < H.nz) unsafeAtomicAdd(t64 + (size_t)(gz * H.nx + gx) * K + c, v);
@@ -1114,6 +1168,10 @@ __global__ void __launch_bounds__(kBlockFinish) k_finish(Params P, uint32_t n_re
         h[j] = 0.f;
         acc[j] = 0.f;
     }
+    // visit sums are scaled and rounded as in the LDS tallies (fixed_add), so a
+    // visit adds the same value whichever kernel completes it
+    const float fx = P.fx, flush_at = P.flush_at;
+    const double fx_inv = P.fx_inv;
     bool more = true, dirty = false;
     for (;;) {
         if (more) {
@@ -1147,23 +1205,25 @@ __global__ void __launch_bounds__(kBlockFinish) k_finish(Params P, uint32_t n_re
             L.absorbed += (double)dw;
             L.segments += 1;
         }
+        const float Ts = T * fx;
 #pragma unroll
-        for (int j = 0; j < K; ++j) acc[j] = fmaf(T, h[j], acc[j]);
-        bool flush = false;
+        for (int j = 0; j < K; ++j) acc[j] = fmaf(Ts, h[j], acc[j]);
+        bool vend = false;
         if (ev == EV_SCATTER) {
             if (scatter_dir(P, p, P.g[pix], L)) dirty = true;
-            else flush = true;
+            else vend = true;
         } else if (ev != EV_NONE) {
-            flush = true;
+            vend = true;
             if (ev == EV_ESCAPE) {
                 L.escaped += p.w;
                 p.alive = false;
             }
         }
+        const bool flush = vend || fabsf(acc[0]) > flush_at;
+        L.visits += vend ? 1u : 0u;
         const unsigned long long fm = __ballot(flush);
         if (fm) {
             if (flush) {
-                L.visits += 1;
                 const int slot = __popcll(fm & lt_mask);
                 float *st = stage + slot * K;
 #pragma unroll
@@ -1177,7 +1237,8 @@ __global__ void __launch_bounds__(kBlockFinish) k_finish(Params P, uint32_t n_re
             for (int e = lane; e < total; e += 64) {
                 const int v = e / K;
                 const float val = stage[e];
-                if (val != 0.f) unsafeAtomicAdd(P.t64 + (size_t)stage_pix[v] * K + (e - v * K), (double)val);
+                if (val != 0.f)
+                    unsafeAtomicAdd(P.t64 + (size_t)stage_pix[v] * K + (e - v * K), __builtin_rint((double)val) * fx_inv);
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
@@ -1264,13 +1325,17 @@ __global__ void k_fill_zero(uint32_t *p, size_t n) {
 // Single-block inclusive scan of |map| in FP64 (fixed order: each thread a
 // contiguous run, then a sequential pass over the 1024 run totals).
 __global__ void __launch_bounds__(1024) k_map_cdf(int n, const double *map, double *cdf) {
-    __shared__ double part[1024];
+    __shared__ double part[1024], pmax[1024];
     const int t = threadIdx.x;
     const int per = (n + 1023) / 1024;
     const int a = t * per, b = min(n, a + per);
-    double s = 0;
-    for (int i = a; i < b; ++i) s += fabs(map[i]);
+    double s = 0, mx = 0;
+    for (int i = a; i < b; ++i) {
+        s += fabs(map[i]);
+        mx = fmax(mx, fabs(map[i]));
+    }
     part[t] = s;
+    pmax[t] = mx;
     __syncthreads();
     if (t == 0) {
         double acc = 0;
@@ -1278,7 +1343,9 @@ __global__ void __launch_bounds__(1024) k_map_cdf(int n, const double *map, doub
             const double v = part[i];
             part[i] = acc;
             acc += v;
+            mx = fmax(mx, pmax[i]);
         }
+        cdf[n] = mx;   // max |q| after the CDF
     }
     __syncthreads();
     s = part[t];
@@ -1292,14 +1359,18 @@ __global__ void __launch_bounds__(1024) k_map_cdf(int n, const double *map, doub
 // the track-length-to-fluence factor 1/(dx Np) in pixel units) and transpose
 // [npix][K] -> [K][npix]; the adjoint output reads the mirrored direction,
 // (-1)^n on orders n >= 1.
-__global__ void k_normalise(int npix, int N, int adjoint, double scale, const double *t64, double *out) {
+// A nonzero *range_errors (tiled mode: a job whose fixed-point tile tally may
+// have wrapped) turns the whole output into NaN.
+__global__ void k_normalise(int npix, int N, int adjoint, double scale, const double *t64,
+                            const unsigned long long *range_errors, double *out) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= npix) return;
     const int K = 2 * N + 1;
+    const bool bad = range_errors && *range_errors;
     for (int c = 0; c < K; ++c) {
         const int n = c <= N ? c : c - N;
         const double f = (adjoint && (n & 1)) ? -scale : scale;
-        out[(size_t)c * npix + i] = t64[(size_t)i * K + c] * f;
+        out[(size_t)c * npix + i] = bad ? __builtin_nan("") : t64[(size_t)i * K + c] * f;
     }
 }
 
@@ -1470,6 +1541,10 @@ struct TileTuning {
     uint64_t finish = 0;   // 0: live / 128
     int tile = 0;   // 0: largest square tile for two workgroups per CU
     uint64_t grid_max = kGridMaxPackets;   // whole-grid kernel only up to this many packets
+    // a visit whose accumulated track length times |weight| reaches flush_track
+    // pixels (in units of the run's weight bound) is flushed to the tile tally
+    // in parts; at most 2^16, which keeps every flush inside fixed_add's range
+    double flush_track = kFlushTrackMax;
 };
 TileTuning tuning_from_env() {
     TileTuning v;
@@ -1535,7 +1610,7 @@ Layout layout(const mc_medium *m, const mc_source *src, const mc_run *run) {
     L.med = off;
     off = align_up(off + npix * sizeof(float4));
     L.cdf = off;
-    if (src[0].kind == MC_SRC_MAP) off = align_up(off + npix * sizeof(double));
+    if (src[0].kind == MC_SRC_MAP) off = align_up(off + (npix + 1) * sizeof(double));   // CDF, max |q|
     L.t64 = off;
     off = align_up(off + npix * K * sizeof(double));
     L.led = off;
@@ -1591,7 +1666,7 @@ BatchLayout batch_layout(const BatchProblem *pb, int n) {
         B.med.push_back(off);
         off = align_up(off + npix * sizeof(float4));
         B.cdf.push_back(off);
-        if (pb[i].src[0].kind == MC_SRC_MAP) off = align_up(off + npix * sizeof(double));
+        if (pb[i].src[0].kind == MC_SRC_MAP) off = align_up(off + (npix + 1) * sizeof(double));   // CDF, max |q|
         B.t64.push_back(off);
         off = align_up(off + npix * B.K * sizeof(double));
         B.led.push_back(off);
@@ -1627,6 +1702,26 @@ BatchLayout batch_layout(const BatchProblem *pb, int n) {
     off = align_up(off + B.live * sizeof(PacketRec));
     B.total = off;
     return B;
+}
+
+// Bound on |packet weight|: a launch weight 2 pi p(s) of an angular profile
+// p = c0/2pi + (1/pi) sum (c_n cos nt + s_n sin nt) is at most
+// |c0| + 2 sum (|c_n| + |s_n|) (1 without a profile, and for pencils and
+// lines); a roulette survivor gains at most the factor m W_th.  The
+// equal-count map launch multiplies by q_i / mean |q|, bounded once max |q|
+// is known on the device.
+double weight_bound(const mc_source *src, int n_src, const mc_run *run) {
+    double wb = 0.0;
+    for (int s = 0; s < n_src; ++s) {
+        const mc_source &q = src[s];
+        double w = 1.0;
+        if ((q.kind == MC_SRC_POINT || q.kind == MC_SRC_MAP) && q.prof_h) {
+            w = std::fabs(q.prof_h[0]);
+            for (int k = 1; k <= 2 * q.n_prof; ++k) w += 2.0 * std::fabs(q.prof_h[k]);
+        }
+        wb = std::max(wb, w);
+    }
+    return wb * std::max(1.0, (double)run->roulette_m * (double)run->w_threshold);
 }
 
 mc_status validate(const mc_medium *m, const mc_source *src, int n_src, const mc_run *run) {
@@ -1665,6 +1760,8 @@ mc_status validate(const mc_medium *m, const mc_source *src, int n_src, const mc
         }
     }
     if (prof_total > kMaxProf) return MC_ERR_UNSUPPORTED;
+    // the fixed-point tile tally resolves weights up to 2^32 (see fixed_add)
+    if (!(weight_bound(src, n_src, run) <= 0x1p32)) return MC_ERR_UNSUPPORTED;
     return MC_OK;
 }
 
@@ -1685,6 +1782,7 @@ void fill_params(Params &P, const mc_medium *m, const mc_source *src, int n_src,
     P.wth = run->w_threshold;
     P.rm = run->roulette_m;
     P.inv_rm = 1.f / run->roulette_m;
+    P.wbound = weight_bound(src, n_src, run);
     P.g = m->g_d;
     double total = 0;
     int poff = 0;
@@ -1721,6 +1819,22 @@ void fill_params(Params &P, const mc_medium *m, const mc_source *src, int n_src,
         P.map = src[0].map_d;
         P.inv_qbar = map_abs_sum > 0 ? (double)P.npix / map_abs_sum : 0.0;
     }
+}
+
+// Fixed-point scale of the visit sums (fixed_add): fx = 2^(32 - e) with 2^e
+// above the run's weight bound (times max |q| / mean |q| for the equal-count
+// map launch), so a segment adds at most sqrt 2 * 2^32 in scaled units; a
+// visit is flushed in parts at flush_track * 2^32 <= 2^48, inside 2^51.
+mc_status fixed_point(Params &P, double map_abs_max, double flush_track) {
+    double wb = P.wbound;
+    if ((P.flags & MC_FLAG_EQUAL_COUNT) && P.map) wb *= map_abs_max * P.inv_qbar;
+    if (!(wb <= 0x1p32)) return MC_ERR_UNSUPPORTED;
+    int e = 0;
+    std::frexp(std::max(wb, 1.0), &e);   // 2^e > wb
+    P.fx = (float)std::ldexp(1.0, kFixBits - e);
+    P.fx_inv = std::ldexp(1.0, e - kFixBits);
+    P.flush_at = (float)std::ldexp(flush_track, kFixBits);
+    return MC_OK;
 }
 
 int occupancy_blocks(const void *fn, int block, size_t lds) {
@@ -1831,20 +1945,24 @@ mc_status run_batch(const BatchProblem *pb, int n, void *ws, size_t ws_bytes, hi
             return st;
         hipLaunchKernelGGL(k_setup_medium, dim3((npix + 255) / 256), dim3(256), 0, s, npix, m->dx, m->mua_d,
                            m->mus_d, m->g_d, reinterpret_cast<float4 *>(base + B.med[i]));
-        double map_abs_sum = 0;
+        double map_abs_sum = 0, map_abs_max = 0;
         todo[i] = pb[i].run->n_packets;
         if (pb[i].src[0].kind == MC_SRC_MAP) {
             double *cdf = reinterpret_cast<double *>(base + B.cdf[i]);
             hipLaunchKernelGGL(k_map_cdf, dim3(1), dim3(1024), 0, s, npix, pb[i].src[0].map_d, cdf);
-            // the normalisation needs sum |q|: read the last CDF entry
-            if (hipMemcpyAsync(&map_abs_sum, cdf + npix - 1, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            // the normalisation needs sum |q| (the last CDF entry), the weight bound max |q|
+            double h2[2];
+            if (hipMemcpyAsync(h2, cdf + npix - 1, 2 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
                 hipStreamSynchronize(s) != hipSuccess)
                 return MC_ERR_DEVICE;
+            map_abs_sum = h2[0];
+            map_abs_max = h2[1];
             if (map_abs_sum == 0.0) todo[i] = 0;   // an all-zero source: the field is zero
             else if (!(map_abs_sum > 0)) return MC_ERR_INVALID_ARG;   // NaN in the map
         }
         Params &P = PP[i];
         fill_params(P, m, pb[i].src, pb[i].n_src, pb[i].run, pb[i].adjoint, map_abs_sum);
+        if ((st = fixed_point(P, map_abs_max, B.tt.flush_track)) != MC_OK) return st;
         P.med = reinterpret_cast<const float4 *>(base + B.med[i]);
         P.t64 = reinterpret_cast<double *>(base + B.t64[i]);
         P.led = reinterpret_cast<double *>(base + B.led[i]);
@@ -1880,7 +1998,9 @@ mc_status run_batch(const BatchProblem *pb, int n, void *ws, size_t ws_bytes, hi
         d.wth = P.wth;
         d.rm = P.rm;
         d.inv_rm = P.inv_rm;
-        d.pad = 0.f;
+        d.flush_at = P.flush_at;
+        d.fx = P.fx;
+        d.fx_inv = P.fx_inv;
         d.med = P.med;
         d.g = P.g;
         d.t64 = P.t64;
@@ -1968,7 +2088,7 @@ mc_status run_batch(const BatchProblem *pb, int n, void *ws, size_t ws_bytes, hi
         const int npix = m->nx * m->nz;
         const double scale = PP[i].total / ((double)pb[i].run->n_packets);
         hipLaunchKernelGGL(k_normalise, dim3((npix + 255) / 256), dim3(256), 0, s, npix, N, pb[i].adjoint,
-                           todo[i] ? scale / (double)m->dx : 0.0, PP[i].t64, pb[i].coeffs);
+                           todo[i] ? scale / (double)m->dx : 0.0, PP[i].t64, PP[i].ledc + 4, pb[i].coeffs);
         if (pb[i].ledger)
             hipLaunchKernelGGL(k_ledger_out, dim3(1), dim3(1), 0, s, PP[i].led, PP[i].ledc, todo[i] ? scale : 0.0,
                                pb[i].ledger);
@@ -1997,14 +2117,17 @@ mc_status run_mc(const mc_medium *m, const mc_source *src, int n_src, const mc_r
         return st;
     hipLaunchKernelGGL(k_setup_medium, dim3((npix + 255) / 256), dim3(256), 0, s, npix, m->dx, m->mua_d, m->mus_d, m->g_d,
                        reinterpret_cast<float4 *>(base + L.med));
-    double map_abs_sum = 0;
+    double map_abs_sum = 0, map_abs_max = 0;
     if (src[0].kind == MC_SRC_MAP) {
         double *cdf = reinterpret_cast<double *>(base + L.cdf);
         hipLaunchKernelGGL(k_map_cdf, dim3(1), dim3(1024), 0, s, npix, src[0].map_d, cdf);
-        // the normalisation needs sum |q|: read the last CDF entry
-        if (hipMemcpyAsync(&map_abs_sum, cdf + npix - 1, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        // the normalisation needs sum |q| (the last CDF entry), the weight bound max |q|
+        double h2[2];
+        if (hipMemcpyAsync(h2, cdf + npix - 1, 2 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
             return MC_ERR_DEVICE;
+        map_abs_sum = h2[0];
+        map_abs_max = h2[1];
         if (map_abs_sum == 0.0) {   // an all-zero source: the field is zero
             st = launch_zero(coeffs, (size_t)npix * (2 * N + 1) * sizeof(double), s);
             if (st == MC_OK && ledger) st = launch_zero(ledger, sizeof(mc_ledger), s);
@@ -2015,6 +2138,7 @@ mc_status run_mc(const mc_medium *m, const mc_source *src, int n_src, const mc_r
     if (hipGetLastError() != hipSuccess) return MC_ERR_DEVICE;
     Params P;
     fill_params(P, m, src, n_src, run, adjoint, map_abs_sum);
+    if ((st = fixed_point(P, map_abs_max, tuning_snapshot().flush_track)) != MC_OK) return st;
     P.med = reinterpret_cast<const float4 *>(base + L.med);
     P.t64 = reinterpret_cast<double *>(base + L.t64);
     P.led = reinterpret_cast<double *>(base + L.led);
@@ -2025,7 +2149,7 @@ mc_status run_mc(const mc_medium *m, const mc_source *src, int n_src, const mc_r
     if (st != MC_OK) return st;
     const double scale = P.total / ((double)run->n_packets);
     hipLaunchKernelGGL(k_normalise, dim3((npix + 255) / 256), dim3(256), 0, s, npix, N, adjoint,
-                       scale / (double)m->dx, P.t64, coeffs);
+                       scale / (double)m->dx, P.t64, P.ledc + 4, coeffs);
     if (ledger)
         hipLaunchKernelGGL(k_ledger_out, dim3(1), dim3(1), 0, s, P.led, P.ledc, scale, ledger);
     return hipGetLastError() == hipSuccess ? MC_OK : MC_ERR_DEVICE;
@@ -2221,7 +2345,8 @@ mc_status mc_set_tuning(const mc_tuning *t) {
     TileTuning v;   // defaults
     if (t) {
         if (t->live_packets < 1024 || t->live_packets > (1ull << 26) || t->job_packets < 64 ||
-            t->job_packets > (1u << 20) || t->max_visits < 1 || t->tile > 256 || t->finish_packets > (1ull << 26))
+            t->job_packets > (1u << 20) || t->max_visits < 1 || t->tile > 256 || t->finish_packets > (1ull << 26) ||
+            !(t->flush_track >= 0.f && t->flush_track <= (float)kFlushTrackMax))
             return MC_ERR_INVALID_ARG;
         v.live = t->live_packets;
         v.grid_max = t->grid_max_packets ? t->grid_max_packets : kGridMaxPackets;
@@ -2229,6 +2354,7 @@ mc_status mc_set_tuning(const mc_tuning *t) {
         v.maxvis = t->max_visits;
         v.tile = (int)t->tile;
         v.finish = t->finish_packets;
+        v.flush_track = t->flush_track > 0.f ? (double)t->flush_track : kFlushTrackMax;
     }
     TuningState &s = tuning_state();
     std::lock_guard<std::mutex> g(s.mu);
@@ -2245,6 +2371,8 @@ mc_status mc_get_tuning(mc_tuning *t) {
     t->tile = (uint32_t)v.tile;
     t->finish_packets = v.finish;
     t->grid_max_packets = (uint32_t)std::min<uint64_t>(v.grid_max, 0xFFFFFFFFull);
+    t->flush_track = (float)v.flush_track;
+    t->reserved = 0;
     return MC_OK;
 }
 

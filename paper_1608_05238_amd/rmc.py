@@ -306,7 +306,8 @@ def mc_profile_read(reset: bool = True):
     return ms.value, n.value
 
 
-_TUNING_FIELDS = ("live_packets", "job_packets", "max_visits", "tile", "finish_packets", "grid_max_packets")
+_TUNING_FIELDS = ("live_packets", "job_packets", "max_visits", "tile", "finish_packets", "grid_max_packets",
+                  "flush_track")
 
 
 def mc_get_tuning() -> dict:
@@ -325,7 +326,8 @@ def mc_set_tuning(tuning: Optional[dict] = None) -> None:
     t = L.mc_tuning()
     cur = mc_get_tuning()
     for f in _TUNING_FIELDS:
-        setattr(t, f, int(tuning.get(f, cur[f])))
+        v = tuning.get(f, cur[f])
+        setattr(t, f, float(v) if f == "flush_track" else int(v))
     L.check("mc_set_tuning", lib.mc_set_tuning(C.byref(t)))
 
 

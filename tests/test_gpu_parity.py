@@ -358,27 +358,38 @@ def test_equal_count_map_launch():
     assert abs(bal) < 1e-5 * abs(led["launched"]) + 1e-6 * n
 
 
-def test_anisotropic_point_source_sin2_2theta():
+@pytest.mark.parametrize("tiled", [False, True])
+def test_anisotropic_point_source_sin2_2theta(tiled):
     """The anisotropic source of the adjoint validation (Sec. 4.1):
-    p(t) = sin^2(2t)/pi = 1/2pi - cos(4t)/2pi, i.e. c0 = 1, c4 = -1/2."""
+    p(t) = sin^2(2t)/pi = 1/2pi - cos(4t)/2pi, i.e. c0 = 1, c4 = -1/2.  Its
+    launch weights 1 - cos 4t reach 2 (the tiled run scales its fixed-point
+    tile tally for that bound)."""
     rmc = _rmc()
     O = _oracle()
+    base = rmc.mc_get_tuning()
     ph = P.homogeneous(32, 32, 0.25, 0.05, 8.0, 0.8)
     prof = np.zeros(2 * 4 + 1)
     prof[0], prof[4] = 1.0, -0.5
     specs = [P.point_source(4.03, 3.97, prof=prof)]
     n = 40_000
-    for adj, tag in ((False, 0), (True, 1)):
-        gpu, _ = _gpu_run(rmc, ph, specs, n, 8, seed=17, adjoint=adj, tag=tag)
-        ora, se = _oracle_batches(O, ph, specs, n, 8, B=8, seed=17, adjoint=adj, tag=tag)
-        _assert_maps(f"sin2_2theta_{'adj' if adj else 'fwd'}", gpu, ora, se)
+    try:
+        if tiled:
+            rmc.mc_set_tuning({**base, "grid_max_packets": 1})
+        for adj, tag in ((False, 0), (True, 1)):
+            gpu, _ = _gpu_run(rmc, ph, specs, n, 8, seed=17, adjoint=adj, tag=tag)
+            ora, se = _oracle_batches(O, ph, specs, n, 8, B=8, seed=17, adjoint=adj, tag=tag)
+            _assert_maps(f"sin2_2theta_{'adj' if adj else 'fwd'}{'_tiled' if tiled else ''}", gpu, ora, se)
+    finally:
+        rmc.mc_set_tuning(base)
 
 
 def test_tuning_changes_schedule_not_results():
     """Other tile sides, generation sizes, job sizes and pause lengths move the
     same packets in another order: the maps agree to FP64 rounding (the
-    per-visit FP32 sums are the same; only the order of the FP64 additions
-    differs).  The autotuner picks one of its candidates and applies it."""
+    per-visit FP32 sums and the tiles' fixed-point sums are the same; only the
+    order of the FP64 additions to the map differs).  Flushing visits in parts
+    changes only FP32 partial sums.  The autotuner picks one of its candidates
+    and applies it."""
     rmc = _rmc()
     from paper_1608_05238_amd import autotune
     base = rmc.mc_get_tuning()
@@ -395,6 +406,17 @@ def test_tuning_changes_schedule_not_results():
             rel = np.abs(got - ref)[big] / np.abs(ref)[big]
             assert rel.max() < 1e-9, (t, rel.max())
             assert lgot["visits"] == lref["visits"] and lgot["scatters"] == lref["scatters"], t
+        # a visit flushed in parts (here after a quarter pixel of track) adds the
+        # same contributions in other FP32 partial sums; high orders nearly cancel
+        # within a pixel, so the rounding is measured against the pixel's a0
+        # (|a_n| <= a0 for every visit)
+        rmc.mc_set_tuning({**base, "flush_track": 0.25})
+        got, lgot = _gpu_run(rmc, ph, specs, n, 16, seed=31)
+        a0 = np.abs(ref[0])
+        lit = a0 > 1e-6 * a0.max()
+        err = (np.abs(got - ref)[:, lit] / a0[lit]).ravel()
+        assert err.max() < 1e-6 and np.median(err) < 1e-8, (err.max(), np.median(err))
+        assert lgot["visits"] == lref["visits"] and lgot["scatters"] == lref["scatters"]
         rmc.mc_set_tuning(base)
         med = rmc.Medium.from_phantom(ph)
         res = autotune.tune(med, specs, 16, trial_packets=200_000,

@@ -24,7 +24,7 @@ def _declared_functions():
         if h.endswith(".h"):
             text = open(os.path.join(ROOT, "include", h)).read()
             text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-            names |= set(re.findall(r"\b((?:mc|dn)_[a-z0-9_]+)\s*\(", text))
+            names |= set(re.findall(r"\b((?:mc|dn|mb)_[a-z0-9_]+)\s*\(", text))
     return sorted(names)
 
 
@@ -134,14 +134,17 @@ def test_tuning_set_get_and_workspace():
         small = lib.mc_workspace_bytes(C.byref(m), src, 1, C.byref(run))
         rmc.mc_set_tuning({"live_packets": 1 << 22, "job_packets": 1024, "max_visits": 7, "tile": 9})
         assert rmc.mc_get_tuning() == {"live_packets": 1 << 22, "job_packets": 1024, "max_visits": 7, "tile": 9,
-                                       "finish_packets": 0, "grid_max_packets": 1 << 21}
+                                       "finish_packets": 0, "grid_max_packets": 1 << 21, "flush_track": 65536.0}
+        rmc.mc_set_tuning({"flush_track": 0.25})
+        assert rmc.mc_get_tuning()["flush_track"] == 0.25
         big = lib.mc_workspace_bytes(C.byref(m), src, 1, C.byref(run))
         assert big > small + 3 * (1 << 20) * 64
-        for bad in ({"live_packets": 10}, {"job_packets": 1}, {"max_visits": 0}, {"tile": 1000}):
+        for bad in ({"live_packets": 10}, {"job_packets": 1}, {"max_visits": 0}, {"tile": 1000},
+                    {"flush_track": 1e6}, {"flush_track": -1.0}, {"flush_track": float("nan")}):
             with pytest.raises(Exception):
                 rmc.mc_set_tuning(bad)
         rmc.mc_set_tuning(None)
-        assert rmc.mc_get_tuning()["job_packets"] == 4096
+        assert rmc.mc_get_tuning()["job_packets"] == 4096 and rmc.mc_get_tuning()["flush_track"] == 65536.0
     finally:
         rmc.mc_set_tuning(base)
 
@@ -176,3 +179,50 @@ def test_denoiser_arguments_checked_on_host():
     assert lib.dn_conv3x3_fwd(None, 0x1000, None, 0x2000, 1, 1, 1, 4, 4, None) == L.MC_ERR_INVALID_ARG
     assert lib.dn_conv3x3_fwd(0x1000, 0x1000, None, 0x2000, 0, 1, 1, 4, 4, None) == L.MC_ERR_INVALID_ARG
     assert lib.dn_conv3x3_wgrad(0x1000, 0x1000, 0x2000, 1, 1, 1, 4, -1, None) == L.MC_ERR_INVALID_ARG
+
+
+def test_microbenchmark_arguments_checked_on_host():
+    L, lib = _lib()
+    bad = L.MC_ERR_INVALID_ARG
+    sink = 0x1000
+    # LDS kinds, block shape and LDS size are checked before any launch
+    assert lib.mb_lds_atomics(9, 65536, 512, 8, 4, 0, sink, None, None) == bad
+    assert lib.mb_lds_atomics(L.MB_LDS_ADD_F64, 65536, 500, 8, 4, 0, sink, None, None) == bad
+    assert lib.mb_lds_atomics(L.MB_LDS_ADD_F64, 65536, 2048, 8, 4, 0, sink, None, None) == bad
+    assert lib.mb_lds_atomics(L.MB_LDS_ADD_F64, 160 * 1024 + 8, 512, 8, 4, 0, sink, None, None) == bad
+    assert lib.mb_lds_atomics(L.MB_LDS_ADD_F64, 512, 512, 8, 4, 0, sink, None, None) == bad
+    assert lib.mb_lds_atomics(L.MB_LDS_ADD_F64, 65540, 512, 8, 4, 0, sink, None, None) == bad
+    assert lib.mb_lds_atomics(L.MB_LDS_ADD_F64, 65536, 512, 0, 4, 0, sink, None, None) == bad
+    assert lib.mb_lds_atomics(L.MB_LDS_ADD_F64, 65536, 512, 8, 4, 0, None, None, None) == bad
+    assert lib.mb_global_atomics_f64(sink, 0, 8, 4, 0, None) == bad
+    assert lib.mb_global_atomics_f64(sink, 1 << 32, 8, 4, 0, None) == bad
+    assert lib.mb_copy(0x1000, 0x1008, 4, None) == bad          # misaligned destination
+    assert lib.mb_copy(0x1000, 0x1010, 4, None) == bad          # overlapping
+    assert lib.mb_copy(None, 0x100000, 4, None) == bad
+    assert lib.mb_fma_f32(None, 8, 4, None, None) == bad
+    assert lib.mb_wall_clock_khz(0, None) == bad
+
+
+def test_weight_bound_beyond_the_fixed_point_range_is_unsupported():
+    """The tile tally is 64-bit fixed point scaled by 2^(32 - e), 2^e >= the
+    largest packet weight; a profile or roulette gain that could exceed 2^32
+    is refused on the host.  The bound is |c0| + 2 sum |c_n|, times the
+    roulette factor max(1, m W_th)."""
+    L, lib = _lib()
+    m = _medium(L)
+    prof = (C.c_double * 3)(1.0, 0.5, 0.0)            # N = 1: c0, c1, s1 -> bound 2
+    pt = L.mc_source()
+    pt.kind, pt.x0, pt.z0, pt.power, pt.prof_h, pt.n_prof = L.MC_SRC_POINT, 1.0, 1.0, 1.0, prof, 1
+    src = (L.mc_source * 1)(pt)
+    run = L.mc_run(1000, 0, 0, 0, 4, 1e-4, 10.0, 0)
+    assert lib.mc_workspace_bytes(C.byref(m), src, 1, C.byref(run)) > 0
+    run.w_threshold, run.roulette_m = 1.0, 2.0 ** 31      # 2 x 2^31 = 2^32: still inside
+    assert lib.mc_workspace_bytes(C.byref(m), src, 1, C.byref(run)) > 0
+    run.roulette_m = 2.0 ** 32                           # 2^33
+    assert lib.mc_workspace_bytes(C.byref(m), src, 1, C.byref(run)) == 0
+    rc = lib.mc_forward(C.byref(m), src, 1, C.byref(run), 0x2000, None, 0x3000, 1 << 30, None)
+    assert rc == L.MC_ERR_UNSUPPORTED
+    run.roulette_m, run.w_threshold = 10.0, 1e-4
+    prof[0] = 1e10
+    assert lib.mc_forward(C.byref(m), src, 1, C.byref(run), 0x2000, None, 0x3000, 1 << 30, None) == \
+        L.MC_ERR_UNSUPPORTED
