@@ -28,9 +28,9 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
 # reads for a plain 1 GiB device copy.  Valid only for the kernel source it
 # was measured on: reported as null once that source changes.
 TRAFFIC = {
-    "source_sha256": "26c6f9b8e57d5f4e600c438818804e9fb0dd7177ed9964580f6bc0555c6c517c",
-    "fetch_kib_per_launch": 221246.53, "fetch_factor": 2.000,
-    "write_kib_per_launch": 641803.57, "write_factor": 1.000,
+    "source_sha256": "3d1b0e527469e1f03a9c540cb3270dec4d88cd4a3a46ef17df4db9ebf72932a6",
+    "fetch_kib_per_launch": 226920.22, "fetch_factor": 2.000,
+    "write_kib_per_launch": 647881.61, "write_factor": 1.000,
 }
 
 
@@ -42,6 +42,31 @@ def traffic_bytes_per_launch():
             return None
     t = TRAFFIC
     return 1024.0 * (t["fetch_kib_per_launch"] * t["fetch_factor"] + t["write_kib_per_launch"] * t["write_factor"])
+
+
+def lds_atomic_ceiling(dev) -> float:
+    """Lane-operations per second of random-address 64-bit integer LDS adds
+    (the tally's atomic) on this device, measured now with the microbenchmark
+    kernel in the transport's shape (512-thread workgroups, 64 KiB of LDS
+    each); best of three launches."""
+    import ctypes as C
+    import torch
+    from paper_1608_05238_amd import _lib as L
+    lib = L.load()
+    ncu = torch.cuda.get_device_properties(dev).multi_processor_count
+    nblk, block, iters = ncu * 16, 512, 2048
+    sink = torch.empty(nblk, dtype=torch.float64, device=dev)
+    stream = C.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    best = float("inf")
+    for _ in range(4):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        L.check("mb_lds_atomics", lib.mb_lds_atomics(L.MB_LDS_ADD_U64, 64 * 1024, block, nblk, iters, 7,
+                                                     sink.data_ptr(), None, stream))
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) * 1e-3)
+    return nblk * block * iters / best
 
 
 def log(msg: str) -> None:
@@ -345,7 +370,8 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": "disc256: 256x256 pixels of 0.1 mm, 3-6 seeded disc inclusions, 4 line sources, "
                                "forward + adjoint + gradient",
-                   "packets_forward": Np, "packets_adjoint": Np, "n_harm": N, "tally": "fp64 LDS tiles, packet migration"},
+                   "packets_forward": Np, "packets_adjoint": Np, "n_harm": N,
+                   "tally": "64-bit fixed-point LDS tiles, FP64 map, packet migration"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_bytes_per_launch(),
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
@@ -357,6 +383,13 @@ def main() -> int:
                      "scatters_per_packet": scatters / (2 * Np * args.steps),
                      "transport_share_of_step": tr_ms / ms_total},
     }
+    # the tally's own ceiling: K LDS atomic adds per visit against the device's
+    # random-address 64-bit LDS add rate, measured in this run
+    ceiling = lds_atomic_ceiling(dev)
+    lane_ops = visits * K / max(tr_launches, 1) / (avg_launch_ms * 1e-3) if tr_launches else 0.0
+    out["lds_roofline"] = {"bound": "lds_atomics", "achieved": lane_ops, "peak": ceiling, "unit": "lane-ops/s",
+                           "frac": lane_ops / ceiling, "kernel": "k_transport_tile<16> + k_finish<16>",
+                           "peak_source": "ds_add_u64 at random LDS addresses, mb_lds_atomics, this run"}
     if args.cpu_packets > 0:
         threads = min(16, os.cpu_count() or 1)
         log(f"cpu baseline: oracle with {args.cpu_packets}+{args.cpu_packets} packets on {threads} threads")

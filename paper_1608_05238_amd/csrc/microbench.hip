@@ -90,18 +90,17 @@ __global__ void __launch_bounds__(256) k_global_atomics_f64(double *buf, uint32_
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-// four independent 16-byte loads in flight per thread, then their stores
+// each workgroup copies one contiguous chunk of 4 x 256 16-byte elements:
+// four independent loads in flight per thread, then their stores
 __global__ void __launch_bounds__(256) k_copy16(const u32x4 *__restrict__ src, u32x4 *__restrict__ dst, uint64_t n) {
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (; i + 3 * stride < n; i += 4 * stride) {
-        u32x4 v[4];
+    const uint64_t base = (uint64_t)blockIdx.x * 1024u + threadIdx.x;
+    u32x4 v[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = __builtin_nontemporal_load(src + i + u * stride);
+    for (int u = 0; u < 4; ++u)
+        if (base + u * 256u < n) v[u] = src[base + u * 256u];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) __builtin_nontemporal_store(v[u], dst + i + u * stride);
-    }
-    for (; i < n; i += stride) dst[i] = src[i];
+    for (int u = 0; u < 4; ++u)
+        if (base + u * 256u < n) dst[base + u * 256u] = v[u];
 }
 
 __global__ void __launch_bounds__(256) k_fma_f32(float *sink, uint32_t iters, uint64_t *clk) {
@@ -177,12 +176,9 @@ mc_status mb_copy(const void *src_d, void *dst_d, uint64_t n16, void *stream) {
         return MC_ERR_INVALID_ARG;
     const uintptr_t a = reinterpret_cast<uintptr_t>(src_d), b = reinterpret_cast<uintptr_t>(dst_d);
     if (a < b + 16u * n16 && b < a + 16u * n16) return MC_ERR_INVALID_ARG;   // overlap
-    int dev = 0, ncu = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-        return MC_ERR_DEVICE;
-    const uint64_t want = (n16 + 1023u) / 1024u, cap = (uint64_t)ncu * 8u;
-    hipLaunchKernelGGL(k_copy16, dim3((unsigned)(want < cap ? want : cap)), dim3(256), 0,
+    const uint64_t blocks = (n16 + 1023u) / 1024u;
+    if (blocks > 0x7FFFFFFFull) return MC_ERR_INVALID_ARG;
+    hipLaunchKernelGGL(k_copy16, dim3((unsigned)blocks), dim3(256), 0,
                        reinterpret_cast<hipStream_t>(stream), reinterpret_cast<const u32x4 *>(src_d),
                        reinterpret_cast<u32x4 *>(dst_d), n16);
     return hipGetLastError() == hipSuccess ? MC_OK : MC_ERR_DEVICE;

@@ -83,6 +83,8 @@ def run_all(dev: int = 0) -> dict:
     b = torch.empty_like(a)
     t = _time(lambda: _check("mb_copy", lib.mb_copy(a.data_ptr(), b.data_ptr(), n16, stream)))
     out["hbm_copy"] = {"bytes": 32 * n16, "gb_per_s": 32 * n16 / t / 1e9, "seconds": t}
+    t = _time(lambda: b.copy_(a))   # the runtime's own device copy, for comparison
+    out["hbm_copy_runtime"] = {"bytes": 32 * n16, "gb_per_s": 32 * n16 / t / 1e9, "seconds": t}
     del a, b
 
     # FP32 FMA issue rate (non-packed)
@@ -105,6 +107,7 @@ def table(r: dict) -> str:
     for e in r["global_atomics"]:
         rows.append(f"| global FP64 atomic, random, {e['buffer']} | {e['atomics_per_s']:.3e} /s | | |")
     rows.append(f"| HBM copy (1 GiB read + 1 GiB write) | {r['hbm_copy']['gb_per_s']:.0f} GB/s | | |")
+    rows.append(f"| HBM copy, torch copy_ (same buffers) | {r['hbm_copy_runtime']['gb_per_s']:.0f} GB/s | | |")
     e = r["fma_f32"]
     rows.append(f"| FP32 FMA (non-packed) | {e['tflops']:.1f} TFLOP/s | {e['flops_per_clk_per_cu']:.1f} flops | "
                 f"{e['shader_mhz']:.0f} |")
