@@ -131,15 +131,18 @@ size_t mc_workspace_bytes(const mc_medium *medium, const mc_source *src, int n_s
  * mc_ledger or NULL.  workspace_d: >= mc_workspace_bytes() bytes, 256-byte
  * aligned; its contents are scratch.
  * Tally precision: each pixel visit is summed in FP32 registers; the map is
- * FP64.  Grids whose FP64 tally exceeds one workgroup's LDS stage the visits
- * in LDS tiles as 64-bit fixed-point sums of value * 2^(32-e), where 2^e
- * bounds the largest packet weight of the run (the source profile bound
- * |c0| + 2 sum |c_n|, times max(1, m W_th) for roulette survivors, times
- * max|q| / mean|q| for the equal-count map launch): every visit is rounded to
- * a multiple of 2^(e-32) before the FP64 sum.  A run whose weight bound
- * exceeds 2^32 returns MC_ERR_UNSUPPORTED.  Should a tile's sums ever risk
- * leaving the 64-bit range (not reachable with physical media and the
- * default tuning), the whole output of the run is NaN rather than wrong. */
+ * FP64.  The visits are staged in LDS (the whole grid when its tally fits
+ * one workgroup, else square tiles) as 64-bit fixed-point sums of
+ * value * 2^(32-e), where 2^e bounds the largest packet weight of the run
+ * (the source profile bound |c0| + 2 sum |c_n|, times max(1, m W_th) for
+ * roulette survivors, times max|q| / mean|q| for the equal-count map
+ * launch): every visit is rounded to a multiple of 2^(e-32) before the FP64
+ * sum, which is then exact while a pixel's total stays below 2^(21+e), so
+ * the output does not depend on the order in which visits are added (it is
+ * bitwise reproducible).  A run whose weight bound exceeds 2^32 returns
+ * MC_ERR_UNSUPPORTED.  Should a tile's sums ever risk leaving the 64-bit
+ * range (not reachable with physical media and the default tuning), the
+ * whole output of the run is NaN rather than wrong. */
 mc_status mc_forward(const mc_medium *medium, const mc_source *src, int n_src, const mc_run *run,
                      double *coeffs_d, mc_ledger *ledger_d, void *workspace_d, size_t workspace_bytes,
                      void *stream);
@@ -179,8 +182,8 @@ size_t mc_batch_workspace_bytes(const mc_problem *probs_h, int n_probs);
  * them by tile over one tile index space, and each workgroup job moves the
  * packets of one tile of one problem with that problem's medium and tally in
  * LDS.  Every problem's output equals what mc_forward / mc_adjoint gives for
- * it alone (the same packets; only the order of FP64 tally additions
- * differs).  probs_h: host array of n_probs (1 .. MC_BATCH_MAX) problems. */
+ * it alone (the same packets and visit values; bitwise while the FP64 sums
+ * are exact, see mc_forward).  probs_h: host array of n_probs (1 .. MC_BATCH_MAX) problems. */
 mc_status mc_run_batch(const mc_problem *probs_h, int n_probs, void *workspace_d, size_t workspace_bytes,
                        void *stream);
 
@@ -255,11 +258,12 @@ mc_status mc_trace(const mc_medium *medium, const mc_source *src, int n_src, con
 mc_status mc_philox_fill(uint64_t seed, uint32_t tag, uint64_t pid0, uint64_t n, uint32_t j,
                          uint32_t *out_d, void *stream);
 
-/* Tuning of the tiled transport (grids whose FP64 tally exceeds one
+/* Tuning of the tiled transport (grids whose tally exceeds one
  * workgroup's LDS).  Process-wide; a run uses the values current when its
  * layout is computed (mc_workspace_bytes, mc_forward, mc_adjoint), so call
  * mc_workspace_bytes again after a change (live_packets sizes the queues).
- * Results do not depend on these values beyond the order of FP64 additions.
+ * Results do not depend on these values (bitwise while the FP64 sums are
+ * exact, see mc_forward), except flush_track, which moves FP32 partial sums.
  *  live_packets   packets kept alive per generation, 1024 .. 2^26
  *  job_packets    packets of one tile handed to one workgroup, 64 .. 2^20
  *  max_visits     visits in one tile before a packet pauses until the next
@@ -269,7 +273,7 @@ mc_status mc_philox_fill(uint64_t seed, uint32_t tag, uint64_t pid0, uint64_t n,
  *                 per CU)
  *  finish_packets once every packet is launched and at most this many remain
  *                 they finish without migration (0: live_packets / 128)
- *  grid_max_packets  a run whose FP64 tally fits one workgroup's LDS uses the
+ *  grid_max_packets  a run whose tally fits one workgroup's LDS uses the
  *                 whole-grid kernel only up to this many packets, larger runs
  *                 the tiled transport (0: 2^21)
  *  flush_track    a pixel visit whose accumulated track length, in units of

@@ -5,9 +5,10 @@ and tile side.
 set of candidate tunings, keeps the fastest, applies it with mc_set_tuning
 and records it in an optional JSON cache keyed by grid size, harmonic order
 and run kind; `tune_batch()` does the same for a batch of problems
-(mc_run_batch) on a sample of it.  The tuning changes only the schedule (which packets move
-together, how often they are sorted); the result of a run is the same up to
-the order of the FP64 tally additions.
+(mc_run_batch) on a sample of it.  The tuning changes only the schedule
+(which packets move together, how often they are sorted); the result of a
+run is the same (bitwise while its FP64 sums are exact, see mc_forward in
+include/mcrad.h).
 
     python -m paper_1608_05238_amd.autotune      # tune the 256x256 disc workload
 """

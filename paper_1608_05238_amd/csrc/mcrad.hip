@@ -9,19 +9,24 @@
 // Sec. 6: adjoint source, signed weights, normalisation by packet count.
 //
 // GPU design (one process, one GPU):
-//  * one lane per packet, persistent waves that refill dead lanes from a
-//    global packet counter with one wave-aggregated atomic;
+//  * one lane per packet; every lane of a wave steps and scatters with the
+//    same instructions (results committed by select), dead lanes refill
+//    between steps;
 //  * FP32 transport in pixel-local coordinates (pixel index + offset in
 //    [0,1]), so precision does not degrade with the grid size;
-//  * the per-visit harmonic sum is accumulated in registers and flushed once
-//    per pixel visit:
-//      - LDS mode: the whole FP32 tally [npix][K] sits in LDS (small grids),
-//        flushed to the FP64 tally with coalesced atomics when the workgroup
-//        ends;
-//      - global mode: flushing lanes stage their K-vectors in LDS and the
-//        wave issues them as contiguous runs of atomics into an FP32 tally
-//        [npix][K] in HBM (one or two cache lines per visit instead of K
-//        scattered lines), folded into FP64 after every chunk of packets.
+//  * the per-visit harmonic sums (K FP32 registers, scaled by a power of two
+//    fixed per run) are flushed once per pixel visit as rounded 64-bit
+//    integers into LDS tallies (fixed_add):
+//      - whole-grid mode (small tallies): the whole grid's tally sits in each
+//        workgroup's LDS, added to the FP64 map when the workgroup ends;
+//      - tiled mode: square tiles of the grid, packets migrate between tiles
+//        in generations (launch, counting sort by tile, one workgroup job per
+//        tile batch, tile tally added to the FP64 map per job); a finisher
+//        kernel moves the last packets to their end without migration;
+//  * each visit adds the same integer multiple of the run's resolution
+//    whichever kernel, tile or generation completes it, so the maps depend
+//    on the schedule only through FP64 additions, which are exact while a
+//    pixel's total is below 2^53 resolution steps;
 //  * no MFMA: the transport is not a dense contraction.
 
 #include <hip/hip_runtime.h>
@@ -46,7 +51,7 @@ constexpr int kMaxProf = 2 * (2 * MC_NHARM_MAX + 1);  // profile coefficients ov
 constexpr int grid_block(int nh) { return nh <= 16 ? 1024 : 512; }
 constexpr int kBlockTile = 512;                        // tiled mode: 8 waves per workgroup, 2 workgroups per CU
 constexpr uint64_t kChunk = 1ull << 22;                // whole-grid mode: packets per launch
-constexpr size_t kLdsGridMax = 144 * 1024;             // whole-grid mode: FP64 tally bytes in LDS
+constexpr size_t kLdsGridMax = 144 * 1024;             // whole-grid mode: tally bytes in LDS
 constexpr size_t kLdsTileMax = 72 * 1024;              // tiled mode: tile tally + medium bytes (2 WGs/CU)
 constexpr uint32_t kInvalidTile = 0xFFFFFFFFu;
 constexpr uint32_t kSlice = 256;                       // queue slots a wave reserves at a time
@@ -572,6 +577,17 @@ __device__ __forceinline__ void fixed_add(unsigned long long *slot, float v) {
     atomicAdd(slot, (unsigned long long)__double_as_longlong(d) - 0x4338000000000000ull);
 }
 
+// The same without the subtraction: a slot that received k such adds holds
+// k * bits(1.5 2^52) more than the integer sum (mod 2^64), removed once when
+// the slot is read (fixed_value) from a count of the adds kept per pixel.
+constexpr unsigned long long kFixMagicBits = 0x4338000000000000ull;
+__device__ __forceinline__ void fixed_add_raw(unsigned long long *slot, float v) {
+    atomicAdd(slot, (unsigned long long)__double_as_longlong((double)v + 0x1.8p52));
+}
+__device__ __forceinline__ long long fixed_value(unsigned long long raw, uint32_t adds) {
+    return (long long)(raw - (unsigned long long)adds * kFixMagicBits);
+}
+
 // ------------------------------------------------------------------ whole-grid transport
 // Small grids: the whole tally [npix][K] lives in LDS for the workgroup's life
 // as 64-bit fixed-point sums (fixed_add), added to the HBM FP64 tally with
@@ -971,6 +987,7 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
     // [tw*th][K] fixed-point sums: value * fx of the job's problem (fixed_add)
     extern __shared__ unsigned long long fxt[];
     float4 *smed = reinterpret_cast<float4 *>(fxt + (((size_t)P.tw * P.th * K + 1) & ~size_t(1)));
+    uint32_t *sadds = reinterpret_cast<uint32_t *>(smed + P.tw * P.th);   // fixed_add_raw adds per pixel
     __shared__ uint32_t s_job[5];
     __shared__ uint32_t s_next;
     __shared__ float s_mag;
@@ -1013,6 +1030,7 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
         const float flush_at = pd.flush_at;
         const int tx0 = (local % ntx) * P.tw, tz0 = (local / ntx) * P.th;
         for (int i = threadIdx.x; i < ntp * K; i += blockDim.x) fxt[i] = 0ull;
+        for (int i = threadIdx.x; i < ntp; i += blockDim.x) sadds[i] = 0u;
         for (int i = threadIdx.x; i < ntp; i += blockDim.x) {
             const int gx = tx0 + i % P.tw, gz = tz0 + i / P.tw;
             const bool in = gx < H.nx && gz < H.nz;
@@ -1096,7 +1114,8 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
             if (flush) {
                 unsigned long long *t = fxt + lp * K;
 #pragma unroll
-                for (int j = 0; j < K; ++j) fixed_add(t + j, acc[j]);
+                for (int j = 0; j < K; ++j) fixed_add_raw(t + j, acc[j]);
+                atomicAdd(sadds + lp, 1u);
                 mag += fabsf(acc[0]);
             }
             if (vend) {
@@ -1131,8 +1150,8 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
         __syncthreads();
         if (threadIdx.x == 0 && !(s_mag < 0x1p62f)) atomicAdd(pd.ledc + 4, 1ull);
         for (int i = threadIdx.x; i < ntp * K; i += blockDim.x) {
-            const double v = (double)(long long)fxt[i] * pd.fx_inv;
             const int lp = i / K, c = i - lp * K;
+            const double v = (double)fixed_value(fxt[i], sadds[lp]) * pd.fx_inv;
             const int gx = tx0 + lp % P.tw, gz = tz0 + lp / P.tw;
             if (v != 0.0 && gx < H.nx && gz < H.nz) unsafeAtomicAdd(t64 + (size_t)(gz * H.nx + gx) * K + c, v);
         }
@@ -1524,7 +1543,7 @@ Profile &profile_state() {
 }
 
 // Tiled-mode sizing.  Tiles are square, as large as lets two workgroups of a
-// CU hold their tile's FP64 tally and medium in LDS.
+// CU hold their tile's tally, medium and flush counts in LDS.
 constexpr uint64_t kLiveMax = 1ull << 24;     // live packets per generation
 constexpr uint64_t kGridMaxPackets = 1ull << 21;   // larger runs take the tiled transport
 constexpr uint32_t kJobSize = 4096;           // packets per job
@@ -1586,12 +1605,13 @@ struct Layout {
     TileTuning tt;   // the tuning this layout was computed with
 };
 
+// tile LDS: fixed-point sums [tw*th][K], medium [tw*th], flush counts [tw*th]
 size_t tile_lds_bytes(int tw, int th, int K) {
     const size_t tal = ((size_t)tw * th * K * sizeof(double) + 15) & ~size_t(15);
-    return tal + (size_t)tw * th * sizeof(float4);
+    return tal + (size_t)tw * th * (sizeof(float4) + sizeof(uint32_t));
 }
 
-// Tiled transport unless the whole FP64 tally fits one workgroup's LDS and the
+// Tiled transport unless the whole tally (8 bytes per value) fits one workgroup's LDS and the
 // run is small (the tiled mode's per-generation overhead is ~10 ms; measured
 // on a 32x32 pencil beam, the tiled mode overtakes the whole-grid kernel near
 // 2e6 packets and is 5x faster at 1e8).
@@ -2400,8 +2420,8 @@ mc_status mc_profile_read(double *transport_ms, uint64_t *launches, int reset) {
 }
 
 const char *mc_build_info(void) {
-    return "librmc gfx950: FP32 transport; FP64 tally in LDS (whole grid when it fits, else square tiles with "
-           "packet migration between tiles), flushed to an FP64 HBM tally";
+    return "librmc gfx950: FP32 transport; 64-bit fixed-point tally in LDS (whole grid when it fits, else square "
+           "tiles with packet migration between tiles), added to an FP64 HBM map";
 }
 
 }  // extern "C"

@@ -385,11 +385,12 @@ def test_anisotropic_point_source_sin2_2theta(tiled):
 
 def test_tuning_changes_schedule_not_results():
     """Other tile sides, generation sizes, job sizes and pause lengths move the
-    same packets in another order: the maps agree to FP64 rounding (the
-    per-visit FP32 sums and the tiles' fixed-point sums are the same; only the
-    order of the FP64 additions to the map differs).  Flushing visits in parts
-    changes only FP32 partial sums.  The autotuner picks one of its candidates
-    and applies it."""
+    same packets in another order, and the maps are bitwise equal: every visit
+    adds the same multiple of 2^(e-32), and FP64 sums such values exactly
+    while a pixel's total stays below 2^(21+e) (here far below), so the order
+    of the additions no longer matters.  Flushing visits in parts changes only
+    FP32 partial sums.  The autotuner picks one of its candidates and applies
+    it."""
     rmc = _rmc()
     from paper_1608_05238_amd import autotune
     base = rmc.mc_get_tuning()
@@ -402,9 +403,7 @@ def test_tuning_changes_schedule_not_results():
                   {"live_packets": 1 << 17, "finish_packets": 50_000}):
             rmc.mc_set_tuning({**base, **t})
             got, lgot = _gpu_run(rmc, ph, specs, n, 16, seed=31)
-            big = np.abs(ref) > 1e-6 * np.abs(ref).max()
-            rel = np.abs(got - ref)[big] / np.abs(ref)[big]
-            assert rel.max() < 1e-9, (t, rel.max())
+            assert np.array_equal(got, ref), (t, np.abs(got - ref).max())
             assert lgot["visits"] == lref["visits"] and lgot["scatters"] == lref["scatters"], t
         # a visit flushed in parts (here after a quarter pixel of track) adds the
         # same contributions in other FP32 partial sums; high orders nearly cancel
@@ -429,11 +428,12 @@ def test_tuning_changes_schedule_not_results():
 @pytest.mark.parametrize("live", [None, 1 << 16])
 def test_batch_equals_separate_runs(live):
     """Problems of different grid sizes, sources, directions and seeds in one
-    packet pool give each the maps of its own run: the same packets move, only
-    the order of the FP64 additions differs.  The batch holds a grid that runs
-    in the whole-grid mode when alone, an adjoint map source and an all-zero
-    map source; a small pool (2^16 live packets) mixes the problems' packets
-    over many generations."""
+    packet pool give each, bit for bit, the maps of its own run: the same
+    packets move and every visit adds the same fixed-point value, whichever
+    kernel completes it (exact FP64 sums, see the tuning test).  The batch
+    holds a grid that runs in the whole-grid mode when alone, an adjoint map
+    source and an all-zero map source; a small pool (2^16 live packets) mixes
+    the problems' packets over many generations."""
     rmc = _rmc()
     base = rmc.mc_get_tuning()
     ph1 = P.disc_phantom(64, 0.2, 0.02, 8.0, 0.9, seed=21, radius=(1.0, 2.5))
@@ -457,9 +457,7 @@ def test_batch_equals_separate_runs(live):
             if not np.abs(ref).max():
                 assert not np.abs(got).max()
                 continue
-            big = np.abs(ref) > 1e-6 * np.abs(ref).max()
-            rel = np.abs(got - ref)[big] / np.abs(ref)[big]
-            assert rel.max() < 1e-9, (ph.mua.shape, adj, rel.max())
+            assert np.array_equal(got, ref), (ph.mua.shape, adj, np.abs(got - ref).max())
             for k in ("packets", "visits", "scatters", "segments"):
                 assert lg[k] == lr[k], (k, lg[k], lr[k])
             assert lg["absorbed"] == pytest.approx(lr["absorbed"], rel=1e-9)
