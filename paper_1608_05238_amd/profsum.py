@@ -3,11 +3,14 @@ measurements.
 
     python -m paper_1608_05238_amd.profsum stats <dir>      # --kernel-trace --stats -f csv
     python -m paper_1608_05238_amd.profsum counters <dir>   # --pmc ... -f csv
+    python -m paper_1608_05238_amd.profsum tail <dir> <n> <kernel>[,<kernel>...]
 
 `stats` prints the kernel summary table (calls, total, average); `counters`
 sums every counter per kernel over its dispatches and prints the per-dispatch
-average, so a counter of a plain copy of known size can calibrate the others.
-Only reads CSV files; no GPU work.
+average, so a counter of a plain copy of known size can calibrate the others;
+`tail` averages the durations of the last n dispatches of the named kernels
+(from the per-dispatch kernel trace), e.g. the launches of a benchmark's
+timed steps.  Only reads CSV files; no GPU work.
 """
 from __future__ import annotations
 
@@ -69,7 +72,34 @@ def counters(root: str) -> str:
     return "\n".join(out)
 
 
+def tail(root: str, n: int, kernels: list) -> str:
+    files = _find(root, "kernel_trace.csv")
+    if not files:
+        raise SystemExit(f"no *kernel_trace.csv under {root}")
+    rows = []
+    for f in files:
+        with open(f, newline="") as fh:
+            for r in csv.DictReader(fh):
+                k = _short(r["Kernel_Name"])
+                if k in kernels:
+                    rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), k))
+    rows.sort()
+    last = rows[-n:]
+    if not last:
+        raise SystemExit(f"no dispatch of {kernels} under {root}")
+    dur = [e - b for b, e, _ in last]
+    per = defaultdict(int)
+    for _, _, k in last:
+        per[k] += 1
+    mix = ", ".join(f"{k}: {c}" for k, c in sorted(per.items()))
+    return (f"last {len(last)} of {len(rows)} dispatches ({mix}): average {sum(dur) / len(dur) / 1e3:.2f} us, "
+            f"total {sum(dur) / 1e3:.1f} us")
+
+
 def main(argv) -> int:
+    if len(argv) == 5 and argv[1] == "tail":
+        print(tail(argv[2], int(argv[3]), argv[4].split(",")))
+        return 0
     if len(argv) != 3 or argv[1] not in ("stats", "counters"):
         print(__doc__, file=sys.stderr)
         return 2
