@@ -92,9 +92,19 @@ def cpu_baseline(n_packets: int, threads: int) -> dict:
                      n_threads=threads)
     O.gradient(om, 16, fo, ao, hm)
     dt = time.perf_counter() - t0
+    # one host thread on a tenth of the sample: the oracle's single-core rate
+    n1 = max(1, n_packets // 10)
+    t1 = time.perf_counter()
+    fo1, _ = O.run_mc(om, O.sources_from(c.sources), O.Run(n1, 0, 16), n_threads=1)
+    _, q1 = O.residual(om, fo1, hm)
+    ao1, _ = O.run_mc(om, [O.Source(O.MAP, map=q1)], O.Run(n1, 0, 16, stream_tag=1, adjoint=1), n_threads=1)
+    O.gradient(om, 16, fo1, ao1, hm)
+    dt1 = time.perf_counter() - t1
     return {"value": 2 * n_packets / dt, "unit": "packets/s", "cores": threads, "kind": "oracle",
             "sample": f"disc256 forward+adjoint+gradient, {n_packets}+{n_packets} packets, N=16, FP64, "
-                      f"{dt:.1f} s"}
+                      f"{dt:.1f} s",
+            "single_thread": {"value": 2 * n1 / dt1, "unit": "packets/s", "cores": 1,
+                              "sample": f"{n1}+{n1} packets, {dt1:.1f} s"}}
 
 
 def time_to_error(args) -> dict:
@@ -239,10 +249,19 @@ def pencil32(args) -> dict:
         res[f"N{N}"] = {"packets_per_s": n / dt, "ms": dt * 1e3, "visits_per_packet": L["visits"] / n,
                         "mode": "whole-grid LDS tally" if whole else "tiled"}
         log(f"pencil32 N={N}: {n / dt:.3e} packets/s")
-    return {"metric": "packets/s fwd MC, 32x32 pencil beam", "value": res["N8"]["packets_per_s"],
-            "unit": "packets/s", "higher_is_better": True, "n_gpus": 1, "dtype": "f32", "data": "synthetic",
-            "config": {"workload": "pencil32: 32x32 pixels of 0.5 mm, mua 0.05, mus 5, g 0.8, pencil beam",
-                       "packets": n}, "runs": res}
+    out = {"metric": "packets/s fwd MC, 32x32 pencil beam", "value": res["N8"]["packets_per_s"],
+           "unit": "packets/s", "higher_is_better": True, "n_gpus": 1, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "pencil32: 32x32 pixels of 0.5 mm, mua 0.05, mus 5, g 0.8, pencil beam",
+                      "packets": n}, "runs": res}
+    if args.cpu_packets > 0:   # the oracle on the configuration's own 1e5 packets, N = 8
+        import oracle as O
+        threads = min(16, os.cpu_count() or 1)
+        t0 = time.perf_counter()
+        O.run_mc(O.medium_from(c.phantom), O.sources_from(c.sources), O.Run(100_000, 0, 8), n_threads=threads)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": 1e5 / dt, "unit": "packets/s", "cores": threads, "kind": "oracle",
+                               "sample": f"pencil32 forward, 100000 packets, N=8, FP64, {dt:.2f} s"}
+    return out
 
 
 def main() -> int:
