@@ -234,7 +234,11 @@ def main(argv=None) -> int:
     ap.add_argument("--harm", type=int, default=16)
     ap.add_argument("--epochs", type=int, default=120)
     ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--widths", default="48,64,96",
+                    help="channels per U-Net level (24,32,48,64,96,128: six levels, 1.05M parameters)")
+    ap.add_argument("--batch", type=int, default=16)
     args = ap.parse_args(argv)
+    widths = tuple(int(w) for w in args.widths.split(","))
     log = lambda m: print(m, file=sys.stderr, flush=True)
     torch.manual_seed(0)
     t0 = time.time()
@@ -242,9 +246,9 @@ def main(argv=None) -> int:
     t_data = time.time() - t0
     log(f"pairs generated in {t_data:.1f} s")
     tr, va = slice(0, args.train), slice(args.train, args.train + args.val)
-    model = UNet(2 * args.harm + 1).cuda()
+    model = UNet(2 * args.harm + 1, widths).cuda()
     t0 = time.time()
-    hist = train(model, lo[tr], hi[tr], args.epochs, lr=args.lr, log=log)
+    hist = train(model, lo[tr], hi[tr], args.epochs, batch=args.batch, lr=args.lr, log=log)
     t_train = time.time() - t0
     den = denoise(model, lo[va])
     e_low = rel_error(lo[va], hi[va])
@@ -272,7 +276,8 @@ def main(argv=None) -> int:
         torch.cuda.synchronize()
         t_mc = time.perf_counter() - t1
     n_params = sum(p.numel() for p in model.parameters())
-    out = {"grid": args.n, "harmonics": args.harm, "train_pairs": args.train, "val_pairs": args.val,
+    out = {"grid": args.n, "harmonics": args.harm, "widths": list(widths), "train_pairs": args.train,
+           "val_pairs": args.val,
            "packets_low": int(args.low), "packets_high": int(args.high), "params": n_params,
            "epochs": args.epochs, "final_loss": hist[-1], "data_s": t_data, "train_s": t_train,
            "val_rel_error_low_vs_high": e_low, "val_rel_error_denoised_vs_high": e_den,
