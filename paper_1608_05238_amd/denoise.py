@@ -122,9 +122,14 @@ class UNet(nn.Module):
         return x + corr
 
 
+def _scale(maps: torch.Tensor) -> torch.Tensor:
+    """Per-sample scale: the RMS of the a0 map (positive for any nonzero map,
+    also for the signed adjoint fields)."""
+    return maps[:, 0].double().pow(2).mean(dim=(1, 2)).sqrt().clamp_min(1e-30).to(maps.dtype)
+
+
 def _normalise(maps: torch.Tensor) -> Tuple[torch.Tensor, torch.Tensor]:
-    """Divide each sample by the mean of its a0 map (a positive scale)."""
-    s = maps[:, 0].mean(dim=(1, 2)).clamp_min(1e-30)
+    s = _scale(maps)
     return maps / s[:, None, None, None], s
 
 
@@ -147,6 +152,22 @@ def random_phantom_medium(n: int, side: float, seed: int, device) -> rmc.Medium:
                       torch.full((n, n), 0.9, dtype=torch.float32, device=device), dx)
 
 
+def random_adjoint_source(med: rmc.Medium, seed: int) -> torch.Tensor:
+    """A signed map shaped like an adjoint source mua (Hmeas - H): smooth
+    random blobs of either sign times the medium's mua (relative to its mean)."""
+    rng = np.random.default_rng(seed)
+    n, dx = med.nx, med.dx
+    c = (np.arange(n) + 0.5) * dx
+    X, Z = np.meshgrid(c, c)
+    q = np.zeros((n, n))
+    for _ in range(int(rng.integers(3, 9))):
+        x0, z0 = rng.uniform(0, n * dx, 2)
+        w = rng.uniform(0.05, 0.3) * n * dx
+        q += rng.choice([-1.0, 1.0]) * rng.uniform(0.3, 1.5) * np.exp(-((X - x0) ** 2 + (Z - z0) ** 2) / (2 * w * w))
+    mua = med.mua.double()
+    return torch.as_tensor(q, device=mua.device) * (mua / mua.mean()) * 1e-3
+
+
 def side_sources(side: float) -> List[rmc.Source]:
     return [rmc.Source("line", 0.0, 0.0, side, 0.0, 0.0, 1.0, 0, 0.25),
             rmc.Source("line", 0.0, side, side, side, 0.0, -1.0, 0, 0.25),
@@ -155,18 +176,22 @@ def side_sources(side: float) -> List[rmc.Source]:
 
 
 def make_pairs(n_samples: int, n: int, side: float, n_low: int, n_high: int, n_harm: int, seed0: int,
-               batch: int = 32):
+               batch: int = 32, adjoint: bool = False):
     """(low, high) coefficient maps [S][2N+1][n][n] from independent runs of
-    n_low and n_high packets on seeded random phantoms (batched)."""
+    n_low and n_high packets on seeded random phantoms (batched): forward runs
+    of the four side sources, or adjoint runs of a random_adjoint_source."""
     dev = torch.device("cuda", torch.cuda.current_device())
-    src = side_sources(side)
     lows, highs = [], []
     for b0 in range(0, n_samples, batch):
         probs = []
         for i in range(b0, min(n_samples, b0 + batch)):
             med = random_phantom_medium(n, side, seed0 + i, dev)
-            probs.append(rmc.Problem(med, src, rmc.make_run(n_low, n_harm, seed=2 * (seed0 + i))))
-            probs.append(rmc.Problem(med, src, rmc.make_run(n_high, n_harm, seed=2 * (seed0 + i) + 1)))
+            src = [rmc.Source("map", map=random_adjoint_source(med, seed0 + i))] if adjoint else side_sources(side)
+            tag = 1 if adjoint else 0
+            probs.append(rmc.Problem(med, src, rmc.make_run(n_low, n_harm, seed=2 * (seed0 + i), stream_tag=tag),
+                                     adjoint))
+            probs.append(rmc.Problem(med, src, rmc.make_run(n_high, n_harm, seed=2 * (seed0 + i) + 1,
+                                                            stream_tag=tag), adjoint))
         outs = rmc.mc_run_batch(probs, ledger=False)
         lows += [o[0] for o in outs[0::2]]
         highs += [o[0] for o in outs[1::2]]
@@ -180,8 +205,7 @@ def rel_error(a: torch.Tensor, b: torch.Tensor) -> float:
 
 def train(model: UNet, low: torch.Tensor, high: torch.Tensor, epochs: int, batch: int = 16, lr: float = 2e-3,
           log=None):
-    xl, _ = _normalise(low)
-    s = low[:, 0].mean(dim=(1, 2)).clamp_min(1e-30)
+    xl, s = _normalise(low)
     yh = high / s[:, None, None, None]
     opt = torch.optim.Adam(model.parameters(), lr=lr)
     sched = torch.optim.lr_scheduler.CosineAnnealingLR(opt, epochs)
@@ -222,6 +246,54 @@ def denoise_or_mc(model: UNet, val_error: float, medium: rmc.Medium, sources, n_
     return maps, "monte-carlo"
 
 
+def gradient_study(model: UNet, n_harm: int, ref_packets: int, counts: Sequence[int], hmeas_packets: int = 20_000_000,
+                   margin: int = 10, log=None) -> dict:
+    """The gradient of the 256x256 disc workload (four side sources, measured
+    data from the second phantom) from plain Monte Carlo and from denoised
+    forward and adjoint maps (the residual is taken from the denoised forward
+    maps), at each packet count: relative L2 errors of d eps/d mua and
+    d eps/d mus against a reference from ref_packets + ref_packets plain
+    packets over pixels at least `margin` from the boundary, and wall times."""
+    import phantoms as P
+    c = P.config2()
+    dev = torch.device("cuda", torch.cuda.current_device())
+    med = rmc.Medium.from_phantom(c.phantom, dev)
+    tmed = rmc.Medium.from_phantom(c.extra["true"], dev)
+    ht, _ = rmc.mc_forward(tmed, c.sources, rmc.make_run(hmeas_packets, n_harm, seed=1), ledger=False)
+    hmeas = rmc.mc_absorbed(tmed, ht)
+
+    def grad(n, seed, den):
+        f, _ = rmc.mc_forward(med, c.sources, rmc.make_run(n, n_harm, seed=seed), ledger=False)
+        if den:
+            f = denoise(model, f[None])[0].double()
+        q, _ = rmc.mc_residual(med, f, hmeas)
+        a, _ = rmc.mc_adjoint(med, [rmc.Source("map", map=q)], rmc.make_run(n, n_harm, seed=seed, stream_tag=1),
+                              ledger=False)
+        if den:
+            a = denoise(model, a[None])[0].double()
+        return rmc.mc_gradient(med, n_harm, f, a, hmeas)
+
+    ra, rs = grad(ref_packets, 100, False)
+    m = margin
+    ra, rs = ra[m:-m, m:-m], rs[m:-m, m:-m]
+    rows = []
+    for n in counts:
+        for den in (False, True):
+            grad(n, 7, den)   # warm-up of this size
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ga, gs = grad(n, 7, den)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            r = {"packets": n, "denoised": den, "wall_ms": wall * 1e3,
+                 "err_dmua": float((ga[m:-m, m:-m] - ra).norm() / ra.norm()),
+                 "err_dmus": float((gs[m:-m, m:-m] - rs).norm() / rs.norm())}
+            rows.append(r)
+            if log:
+                log(json.dumps(r))
+    return {"reference_packets": ref_packets, "rows": rows}
+
+
 def main(argv=None) -> int:
     import argparse
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
@@ -237,12 +309,22 @@ def main(argv=None) -> int:
     ap.add_argument("--widths", default="48,64,96",
                     help="channels per U-Net level (24,32,48,64,96,128: six levels, 1.05M parameters)")
     ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--gradient-study", action="store_true",
+                    help="train on forward and adjoint pairs, then compare the gradient of the 256x256 disc "
+                         "workload from plain and from denoised maps (needs --n 256)")
+    ap.add_argument("--ref", type=float, default=4e8, help="gradient study: reference packets per run")
     args = ap.parse_args(argv)
     widths = tuple(int(w) for w in args.widths.split(","))
     log = lambda m: print(m, file=sys.stderr, flush=True)
     torch.manual_seed(0)
     t0 = time.time()
     lo, hi = make_pairs(args.train + args.val, args.n, args.side, int(args.low), int(args.high), args.harm, 1000)
+    if args.gradient_study:   # as many adjoint pairs, interleaved so both kinds are trained and held out
+        alo, ahi = make_pairs(args.train + args.val, args.n, args.side, int(args.low), int(args.high), args.harm,
+                              5000, adjoint=True)
+        lo = torch.stack([lo, alo], 1).flatten(0, 1)
+        hi = torch.stack([hi, ahi], 1).flatten(0, 1)
+        args.train, args.val = 2 * args.train, 2 * args.val
     t_data = time.time() - t0
     log(f"pairs generated in {t_data:.1f} s")
     tr, va = slice(0, args.train), slice(args.train, args.train + args.val)
@@ -284,6 +366,10 @@ def main(argv=None) -> int:
            "val_rel_error_a0_low": e_low_a0, "val_rel_error_a0_denoised": e_den_a0,
            "reference_noise_floor_estimate": floor,
            "same_a0_error": {"denoised_ms": t_den * 1e3, "plain_mc_packets": n_eq, "plain_mc_ms": t_mc * 1e3}}
+    if args.gradient_study:
+        out["gradient_study"] = gradient_study(model, args.harm, int(args.ref),
+                                               [int(args.low), 2 * int(args.low), 4 * int(args.low),
+                                                10 * int(args.low), 40 * int(args.low)], log=log)
     print(json.dumps(out), flush=True)
     return 0
 
