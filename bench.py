@@ -28,9 +28,9 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
 # reads for a plain 1 GiB device copy.  Valid only for the kernel source it
 # was measured on: reported as null once that source changes.
 TRAFFIC = {
-    "source_sha256": "67ce9ede4a4fb829a7cbdb400ce45d77d889c45355b673af218e3359a0353bed",
-    "fetch_kib_per_launch": 229254.79, "fetch_factor": 2.000,
-    "write_kib_per_launch": 649938.14, "write_factor": 1.000,
+    "source_sha256": "950f7891061db9588e74129aa97284c184617a89116d1ea8ada7eaab5e0f005b",
+    "fetch_kib_per_launch": 182539.03, "fetch_factor": 2.000,
+    "write_kib_per_launch": 518498.39, "write_factor": 1.000,
 }
 
 

@@ -279,7 +279,8 @@ mc_status mc_philox_fill(uint64_t seed, uint32_t tag, uint64_t pid0, uint64_t n,
  *  flush_track    a pixel visit whose accumulated track length, in units of
  *                 the run's weight bound, exceeds this many pixels is added
  *                 to the tile tally in parts, 0 .. 65536 (0: 65536)
- *  reserved       0
+ *  tail_visits    once a job has handed out its last packet, its packets
+ *                 pause after this many more visits, 0 .. 2^30 (0: 8)
  * mc_set_tuning(NULL) restores the built-in defaults. */
 typedef struct {
     uint64_t live_packets;
@@ -289,7 +290,7 @@ typedef struct {
     uint32_t grid_max_packets;
     uint64_t finish_packets;
     float flush_track;
-    uint32_t reserved;
+    uint32_t tail_visits;
 } mc_tuning;
 mc_status mc_set_tuning(const mc_tuning *tuning_h);
 mc_status mc_get_tuning(mc_tuning *tuning_h);

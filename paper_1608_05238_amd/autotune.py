@@ -1,5 +1,6 @@
 """Autotuner of the tiled transport: live packets, job size, visits per stay
-and tile side.
+and visits after a job's last packet (any other mc_tuning field, e.g. the
+tile side, can be searched through the `space` argument).
 
 `tune()` times short forward (or adjoint) runs of the caller's problem over a
 set of candidate tunings, keeps the fastest, applies it with mc_set_tuning
@@ -28,7 +29,7 @@ DEFAULT_CANDIDATES = {
     "live_packets": (1 << 23, 1 << 24),
     "job_packets": (2048, 4096, 8192),
     "max_visits": (16, 32, 64),
-    "tile": (0, 12),
+    "tail_visits": (4, 8, 16),
 }
 
 

@@ -307,7 +307,7 @@ def mc_profile_read(reset: bool = True):
 
 
 _TUNING_FIELDS = ("live_packets", "job_packets", "max_visits", "tile", "finish_packets", "grid_max_packets",
-                  "flush_track")
+                  "flush_track", "tail_visits")
 
 
 def mc_get_tuning() -> dict:

@@ -400,7 +400,8 @@ def test_tuning_changes_schedule_not_results():
     try:
         ref, lref = _gpu_run(rmc, ph, specs, n, 16, seed=31)
         for t in ({"tile": 7}, {"live_packets": 4096, "job_packets": 256, "max_visits": 3},
-                  {"live_packets": 1 << 17, "finish_packets": 50_000}):
+                  {"live_packets": 1 << 17, "finish_packets": 50_000}, {"tail_visits": 1 << 30},
+                  {"tail_visits": 1}):
             rmc.mc_set_tuning({**base, **t})
             got, lgot = _gpu_run(rmc, ph, specs, n, 16, seed=31)
             assert np.array_equal(got, ref), (t, np.abs(got - ref).max())

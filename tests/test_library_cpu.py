@@ -134,13 +134,15 @@ def test_tuning_set_get_and_workspace():
         small = lib.mc_workspace_bytes(C.byref(m), src, 1, C.byref(run))
         rmc.mc_set_tuning({"live_packets": 1 << 22, "job_packets": 1024, "max_visits": 7, "tile": 9})
         assert rmc.mc_get_tuning() == {"live_packets": 1 << 22, "job_packets": 1024, "max_visits": 7, "tile": 9,
-                                       "finish_packets": 0, "grid_max_packets": 1 << 21, "flush_track": 65536.0}
+                                       "finish_packets": 0, "grid_max_packets": 1 << 21, "flush_track": 65536.0,
+                                       "tail_visits": 8}
         rmc.mc_set_tuning({"flush_track": 0.25})
         assert rmc.mc_get_tuning()["flush_track"] == 0.25
         big = lib.mc_workspace_bytes(C.byref(m), src, 1, C.byref(run))
         assert big > small + 3 * (1 << 20) * 64
         for bad in ({"live_packets": 10}, {"job_packets": 1}, {"max_visits": 0}, {"tile": 1000},
-                    {"flush_track": 1e6}, {"flush_track": -1.0}, {"flush_track": float("nan")}):
+                    {"flush_track": 1e6}, {"flush_track": -1.0}, {"flush_track": float("nan")},
+                    {"tail_visits": (1 << 30) + 1}):
             with pytest.raises(Exception):
                 rmc.mc_set_tuning(bad)
         rmc.mc_set_tuning(None)
