@@ -28,7 +28,7 @@ from . import rmc
 DEFAULT_CANDIDATES = {
     "live_packets": (1 << 23, 1 << 24),
     "job_packets": (2048, 4096, 8192),
-    "max_visits": (16, 32, 64),
+    "max_visits": (32, 64, 128),
     "tail_visits": (4, 8, 16),
 }
 

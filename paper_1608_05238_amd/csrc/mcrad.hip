@@ -1547,7 +1547,7 @@ Profile &profile_state() {
 constexpr uint64_t kLiveMax = 1ull << 24;     // live packets per generation
 constexpr uint64_t kGridMaxPackets = 1ull << 21;   // larger runs take the tiled transport
 constexpr uint32_t kJobSize = 4096;           // packets per job
-constexpr uint32_t kMaxVisitsPerStay = 32;    // a packet pauses after this many visits in one job
+constexpr uint32_t kMaxVisitsPerStay = 64;    // a packet pauses after this many visits in one job
 // once a job has handed out its last packet, its packets pause after this many
 // more visits, so a wave does not idle behind its longest stay (measured on
 // the 256x256 disc: 8 beats 2, 4, 16 and no limit by 7-9%)
