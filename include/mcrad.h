@@ -272,7 +272,8 @@ mc_status mc_philox_fill(uint64_t seed, uint32_t tag, uint64_t pid0, uint64_t n,
  *                 not fit: the largest square tile that fits two workgroups
  *                 per CU)
  *  finish_packets once every packet is launched and at most this many remain
- *                 they finish without migration (0: live_packets / 128)
+ *                 they finish without migration (0: live_packets / 128,
+ *                 whatever the run's own packet count)
  *  grid_max_packets  a run whose tally fits one workgroup's LDS uses the
  *                 whole-grid kernel only up to this many packets, larger runs
  *                 the tiled transport (0: 2^21)
