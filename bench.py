@@ -7,6 +7,18 @@ The hot path follows Hochuli et al. (arXiv:1608.05238): forward radiance MC
 with the harmonic tally (Sec. 3, 3.1), adjoint source q* = mua (Hmeas - H)
 (Sec. 6), adjoint radiance MC (Sec. 4), gradients from harmonic products
 (Sec. 5).  Inputs are synthetic and resident in HBM before timing starts.
+
+Besides the throughput the line carries:
+  roofline      the transport kernels' algorithmic tally bytes (272 B per pixel
+                visit) per launch over their average launch time (HIP events on
+                the launch stream), against the 8 TB/s of HBM3E, and the
+                measured HBM traffic per launch (rocprofv3 counters, or null if
+                the kernel source changed since they were taken);
+  lds_roofline  the K LDS tally adds per visit per second against the
+                random-address 64-bit LDS add rate measured in the same run;
+  cpu_baseline  the FP64 oracle on the host's cores (and on one thread) on a
+                bounded sample of the same workload.
+Other modes: --time-to-error, --batch, --pencil32 (one JSON line each).
 """
 from __future__ import annotations
 
