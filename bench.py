@@ -24,6 +24,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -122,8 +123,9 @@ def cpu_baseline(n_packets: int, threads: int) -> dict:
 def time_to_error(args) -> dict:
     """Second half of the headline metric: wall time of one gradient evaluation
     (forward + residual + adjoint + gradient, N = 16) at the smallest packet
-    count, doubling from 1e6, whose gradients are within 5% (d eps/d mua) and
-    20% (d eps/d mus) relative L2 error of a reference gradient from
+    count (doubling from 1e6, then three geometric bisection steps) whose
+    gradients are within 5% (d eps/d mua) and 20% (d eps/d mus) relative L2
+    error of a reference gradient from
     args.ref_packets + args.ref_packets packets, over pixels at least 10
     pixels from the boundary."""
     import torch
@@ -149,8 +151,8 @@ def time_to_error(args) -> dict:
     m = 10
     ra, rs = ra[m:-m, m:-m], rs[m:-m, m:-m]
     rows = []
-    n = 1_000_000
-    while True:
+
+    def evaluate(n):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ga, gs = gradient(n, 7)
@@ -160,10 +162,22 @@ def time_to_error(args) -> dict:
         es = float((gs[m:-m, m:-m] - rs).norm() / rs.norm())
         rows.append({"packets": n, "wall_ms": wall * 1e3, "err_dmua": ea, "err_dmus": es})
         log(f"{n:.2e} packets: {wall * 1e3:.1f} ms, error dmua {ea:.4f}, dmus {es:.4f}")
-        if (ea <= 0.05 and es <= 0.20) or n >= args.ref_packets // 4:
-            break
-        n *= 2
-    hit = rows[-1]
+        return ea <= 0.05 and es <= 0.20
+
+    # doubling from 1e6 packets, then three geometric bisection steps between
+    # the last count that missed the targets and the first that met them
+    n, lo = 1_000_000, None
+    while not evaluate(n) and n < args.ref_packets // 4:
+        lo, n = n, 2 * n
+    hi = n
+    if lo is not None and rows[-1]["err_dmua"] <= 0.05 and rows[-1]["err_dmus"] <= 0.20:
+        for _ in range(3):
+            mid = int(round(math.sqrt(lo * hi) / 1e4)) * 10_000
+            if evaluate(mid):
+                hi = mid
+            else:
+                lo = mid
+    hit = next(r for r in rows if r["packets"] == hi)
     ok = hit["err_dmua"] <= 0.05 and hit["err_dmus"] <= 0.20
     return {"metric": "wall time to gradient at fixed rel. error (5% d eps/d mua, 20% d eps/d mus)",
             "value": hit["wall_ms"] if ok else None, "unit": "ms", "higher_is_better": False, "n_gpus": 1,
