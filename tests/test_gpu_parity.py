@@ -57,7 +57,8 @@ def _oracle_batches(O, ph, specs, n, N, B, seed=0, adjoint=False, first=0, tag=0
         outs.append(O.run_mc(med, src, r, n_threads=min(16, os.cpu_count() or 8))[0] * (e - a) / n)
     outs = np.array(outs)
     total = outs.sum(axis=0)
-    se = outs.std(axis=0, ddof=1) * np.sqrt(B)     # SE of the total from B equal batches
+    # SE of the total from B equal batches (none from a single batch)
+    se = outs.std(axis=0, ddof=1) * np.sqrt(B) if B > 1 else np.zeros_like(total)
     return total, se
 
 
