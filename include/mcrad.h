@@ -244,6 +244,25 @@ typedef struct {
     float t;          /* track-length deposit of the segment (mm) */
 } mc_event;
 
+/* Discrete-ordinates tally, for comparison with the harmonic tally (Sec. 3.1
+ * contrasts the harmonic expansion of the radiance with binning it in angle):
+ * the radiance averaged over n_bins equal bins of the direction angle
+ * theta in [-pi, pi) (bin b covers [-pi + b w, -pi + (b+1) w), w = 2pi/n_bins),
+ * per pixel, from the same transport as mc_forward (adjoint = 0) or
+ * mc_adjoint (adjoint = 1, read at the mirrored direction: bin b holds what
+ * the transport tallied in bin b + n_bins/2).  The same packets, seeds and
+ * segment deposits T as those calls; each segment adds its T to its
+ * direction's bin with one FP64 device atomic, so this serves comparison
+ * runs, not speed.  Normalised as the coefficients and divided by w, so
+ * sum_b binned[b] * w equals the a0 map.  binned_d: FP64 [n_bins][nz][nx]
+ * (overwritten); n_bins even, 2 .. 4096; ledger_d: device mc_ledger or NULL;
+ * workspace_d: >= mc_binned_workspace_bytes() bytes, 256-byte aligned. */
+size_t mc_binned_workspace_bytes(const mc_medium *medium, const mc_source *src, int n_src, const mc_run *run,
+                                 int n_bins);
+mc_status mc_run_binned(const mc_medium *medium, const mc_source *src, int n_src, const mc_run *run, int adjoint,
+                        int n_bins, double *binned_d, mc_ledger *ledger_d, void *workspace_d, size_t workspace_bytes,
+                        void *stream);
+
 /* Per-event trace of selected packets, run by the same device transport code
  * as mc_forward (adjoint != 0: as mc_adjoint).  Synchronous: allocates its own
  * device buffers, runs on the null stream and copies back.  pids_h: host

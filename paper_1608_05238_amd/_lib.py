@@ -21,6 +21,7 @@ MC_NHARM_MAX = 32
 SYMBOLS = ("mc_workspace_bytes", "mc_forward", "mc_adjoint", "mc_residual", "mc_gradient", "mc_absorbed",
            "mc_adjoint_source", "mc_gradient_h", "mc_detect", "mc_trace", "mc_philox_fill", "mc_profile_enable",
            "mc_profile_read", "mc_set_tuning", "mc_get_tuning", "mc_batch_workspace_bytes", "mc_run_batch",
+           "mc_binned_workspace_bytes", "mc_run_binned",
            "mc_status_string", "mc_build_info", "dn_conv3x3_fwd", "dn_conv3x3_wgrad",
            "mb_lds_atomics", "mb_global_atomics_f64", "mb_copy", "mb_fma_f32", "mb_wall_clock_khz")
 MB_LDS_ADD_F64, MB_LDS_ADD_F32, MB_LDS_ADD_U64, MB_LDS_ADD_U32, MB_LDS_ADD_F64_ROW33 = range(5)
@@ -111,6 +112,11 @@ def load() -> C.CDLL:
     lib.mc_batch_workspace_bytes.restype = C.c_size_t
     lib.mc_run_batch.argtypes = [P(mc_problem), C.c_int, V, C.c_size_t, V]
     lib.mc_run_batch.restype = St
+    lib.mc_binned_workspace_bytes.argtypes = [P(mc_medium), P(mc_source), C.c_int, P(mc_run), C.c_int]
+    lib.mc_binned_workspace_bytes.restype = C.c_size_t
+    lib.mc_run_binned.argtypes = [P(mc_medium), P(mc_source), C.c_int, P(mc_run), C.c_int, C.c_int, V, V, V,
+                                  C.c_size_t, V]
+    lib.mc_run_binned.restype = St
     lib.mc_set_tuning.argtypes = [P(mc_tuning)]
     lib.mc_set_tuning.restype = St
     lib.mc_get_tuning.argtypes = [P(mc_tuning)]

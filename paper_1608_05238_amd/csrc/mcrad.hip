@@ -1269,6 +1269,76 @@ __global__ void __launch_bounds__(kBlockFinish) k_finish(Params P, uint32_t n_re
     ledger_flush_block(P.led, P.ledc, L);
 }
 
+// ------------------------------------------------------------------ discrete-ordinates tally
+// The comparison tally of mc_run_binned: the same launch, step and scatter as
+// the whole-grid transport (persistent lanes refilled from a global packet
+// counter), but each segment adds its deposit T to raw[bin][pixel] of its
+// direction's angular bin with one FP64 device atomic.
+constexpr int kBinnedMax = 4096;
+
+__global__ void __launch_bounds__(256) k_transport_binned(Params P, int n_bins, double *raw) {
+    const int lane = __lane_id();
+    Packet p;
+    idle_packet(p, 0, 0);
+    LedgerRegs L;
+    bool more = true;
+    const unsigned long long lt_mask = (1ull << lane) - 1ull;
+    const double per_rad = (double)n_bins / (2.0 * M_PI);
+    for (;;) {
+        if (more) {
+            const unsigned long long dead = __ballot(!p.alive);
+            if (dead) {
+                const int ndead = __popcll(dead);
+                const int leader = __ffsll((long long)dead) - 1;
+                unsigned long long base = 0;
+                if (lane == leader) base = atomicAdd(P.counter, (unsigned long long)ndead);
+                base = __shfl(base, leader);
+                if (base + ndead >= P.npk) more = false;
+                if (!p.alive) {
+                    const unsigned long long my = base + __popcll(dead & lt_mask);
+                    if (my < P.npk) launch_state(P, P.pid0 + my, p, L);
+                }
+            }
+        }
+        if (!__ballot(p.alive)) {
+            if (!more) break;
+        }
+        const bool live = p.alive;
+        const int pix = live ? p.iz * P.nx + p.ix : 0;
+        float T = 0.f, dw = 0.f;
+        const float4 mm = P.med[pix];
+        int ev = step(P, p, mm, T, dw);
+        ev = live ? ev : EV_NONE;
+        dw = live ? dw : 0.f;
+        L.absorbed += (double)dw;
+        L.segments += live ? 1u : 0u;
+        if (live && T != 0.f) {   // direction of the segment, before any scatter
+            const double th = atan2((double)p.sx, (double)p.sz);
+            const int b = min(n_bins - 1, max(0, (int)floor((th + M_PI) * per_rad)));
+            unsafeAtomicAdd(raw + (size_t)b * P.npix + pix, (double)T);
+        }
+        const bool at = ev == EV_SCATTER;
+        const bool killed = scatter_masked(P, p, at, mm.w, L);
+        if (ev == EV_ESCAPE) {
+            L.escaped += p.w;
+            p.alive = false;
+        }
+        L.visits += (killed || (ev != EV_NONE && !at)) ? 1u : 0u;
+    }
+    ledger_flush_block(P.led, P.ledc, L);
+}
+
+// binned[b][i] = raw[b'][i] * scale, b' = b (forward) or b + n_bins/2 (adjoint:
+// the mirrored direction)
+__global__ void k_binned_normalise(int npix, int n_bins, int adjoint, double scale, const double *raw, double *out) {
+    const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (i >= (size_t)npix * n_bins) return;
+    const int b = (int)(i / npix);
+    const size_t px = i - (size_t)b * npix;
+    const int src = adjoint ? (b + n_bins / 2) % n_bins : b;
+    out[i] = raw[(size_t)src * npix + px] * scale;
+}
+
 // ------------------------------------------------------------------ trace kernel
 // Runs the listed packets one after the other through the same device
 // functions as k_transport and records every event.
@@ -2184,9 +2254,108 @@ mc_status run_mc(const mc_medium *m, const mc_source *src, int n_src, const mc_r
     return hipGetLastError() == hipSuccess ? MC_OK : MC_ERR_DEVICE;
 }
 
+// Discrete-ordinates runs (mc_run_binned): medium, CDF of a map source, raw
+// bins [n_bins][npix], ledger and per-chunk packet counters.
+struct BinnedLayout {
+    size_t med, cdf, raw, led, ledc, counters, total;
+    uint64_t n_chunks;
+};
+
+BinnedLayout binned_layout(const mc_medium *m, const mc_source *src, const mc_run *run, int n_bins) {
+    BinnedLayout L{};
+    const size_t npix = (size_t)m->nx * m->nz;
+    size_t off = 0;
+    L.med = off;
+    off = align_up(off + npix * sizeof(float4));
+    L.cdf = off;
+    if (src[0].kind == MC_SRC_MAP) off = align_up(off + (npix + 1) * sizeof(double));
+    L.raw = off;
+    off = align_up(off + npix * (size_t)n_bins * sizeof(double));
+    L.led = off;
+    off = align_up(off + 8 * sizeof(double));
+    L.ledc = off;
+    off = align_up(off + 8 * sizeof(unsigned long long));
+    L.n_chunks = (run->n_packets + kChunk - 1) / kChunk;
+    L.counters = off;
+    off = align_up(off + L.n_chunks * sizeof(unsigned long long));
+    L.total = off;
+    return L;
+}
+
+bool binned_args_ok(int n_bins) { return n_bins >= 2 && n_bins <= kBinnedMax && !(n_bins & 1); }
+
+mc_status run_binned(const mc_medium *m, const mc_source *src, int n_src, const mc_run *run, int adjoint, int n_bins,
+                     double *out, mc_ledger *ledger, void *ws, size_t ws_bytes, hipStream_t s) {
+    mc_status st = validate(m, src, n_src, run);
+    if (st != MC_OK) return st;
+    if (!out || !binned_args_ok(n_bins) || (adjoint != 0 && adjoint != 1)) return MC_ERR_INVALID_ARG;
+    const BinnedLayout L = binned_layout(m, src, run, n_bins);
+    if (!ws || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255)) return MC_ERR_WORKSPACE;
+    char *base = static_cast<char *>(ws);
+    const int npix = m->nx * m->nz;
+    const size_t nout = (size_t)npix * n_bins;
+    if ((st = launch_zero(base + L.raw, L.total - L.raw, s)) != MC_OK) return st;   // bins, ledger, counters
+    hipLaunchKernelGGL(k_setup_medium, dim3((npix + 255) / 256), dim3(256), 0, s, npix, m->dx, m->mua_d, m->mus_d,
+                       m->g_d, reinterpret_cast<float4 *>(base + L.med));
+    double map_abs_sum = 0;
+    if (src[0].kind == MC_SRC_MAP) {
+        double *cdf = reinterpret_cast<double *>(base + L.cdf);
+        hipLaunchKernelGGL(k_map_cdf, dim3(1), dim3(1024), 0, s, npix, src[0].map_d, cdf);
+        if (hipMemcpyAsync(&map_abs_sum, cdf + npix - 1, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return MC_ERR_DEVICE;
+        if (map_abs_sum == 0.0) {   // an all-zero source: the field is zero
+            st = launch_zero(out, nout * sizeof(double), s);
+            if (st == MC_OK && ledger) st = launch_zero(ledger, sizeof(mc_ledger), s);
+            return st;
+        }
+        if (!(map_abs_sum > 0)) return MC_ERR_INVALID_ARG;   // NaN in the map
+    }
+    Params P;
+    fill_params(P, m, src, n_src, run, adjoint, map_abs_sum);
+    P.med = reinterpret_cast<const float4 *>(base + L.med);
+    P.led = reinterpret_cast<double *>(base + L.led);
+    P.ledc = reinterpret_cast<unsigned long long *>(base + L.ledc);
+    P.cdf = reinterpret_cast<const double *>(base + L.cdf);
+    double *raw = reinterpret_cast<double *>(base + L.raw);
+    const int cus = device_cus();
+    const int occ = occupancy_blocks(reinterpret_cast<const void *>(&k_transport_binned), 256, 0);
+    for (uint64_t c = 0; c < L.n_chunks; ++c) {
+        const uint64_t a = c * kChunk;
+        const uint64_t n = std::min<uint64_t>(kChunk, run->n_packets - a);
+        P.pid0 = run->first_packet_id + a;
+        P.npk = n;
+        P.counter = reinterpret_cast<unsigned long long *>(base + L.counters) + c;
+        const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((n + 255) / 256, (uint64_t)cus * occ));
+        hipLaunchKernelGGL(k_transport_binned, dim3(grid), dim3(256), 0, s, P, n_bins, raw);
+        if (hipGetLastError() != hipSuccess) return MC_ERR_DEVICE;
+    }
+    // as the coefficients (source measure / packets, track length in pixel
+    // units over the pixel area), per unit angle of the bin
+    const double scale = P.total / (double)run->n_packets;
+    const double bw = 2.0 * M_PI / n_bins;
+    hipLaunchKernelGGL(k_binned_normalise, dim3((unsigned)((nout + 255) / 256)), dim3(256), 0, s, npix, n_bins, adjoint,
+                       scale / (double)m->dx / bw, raw, out);
+    if (ledger) hipLaunchKernelGGL(k_ledger_out, dim3(1), dim3(1), 0, s, P.led, P.ledc, scale, ledger);
+    return hipGetLastError() == hipSuccess ? MC_OK : MC_ERR_DEVICE;
+}
+
 }  // namespace
 
 extern "C" {
+
+size_t mc_binned_workspace_bytes(const mc_medium *medium, const mc_source *src, int n_src, const mc_run *run,
+                                 int n_bins) {
+    if (validate(medium, src, n_src, run) != MC_OK || !binned_args_ok(n_bins)) return 0;
+    return binned_layout(medium, src, run, n_bins).total;
+}
+
+mc_status mc_run_binned(const mc_medium *medium, const mc_source *src, int n_src, const mc_run *run, int adjoint,
+                        int n_bins, double *binned_d, mc_ledger *ledger_d, void *workspace_d, size_t workspace_bytes,
+                        void *stream) {
+    return run_binned(medium, src, n_src, run, adjoint, n_bins, binned_d, ledger_d, workspace_d, workspace_bytes,
+                      reinterpret_cast<hipStream_t>(stream));
+}
 
 size_t mc_workspace_bytes(const mc_medium *medium, const mc_source *src, int n_src, const mc_run *run) {
     if (validate(medium, src, n_src, run) != MC_OK) return 0;

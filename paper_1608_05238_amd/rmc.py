@@ -167,6 +167,30 @@ def mc_adjoint(medium: Medium, sources: Sequence, run: L.mc_run, out=None, works
     return out, led
 
 
+def mc_binned(medium: Medium, sources: Sequence, run: L.mc_run, n_bins: int, adjoint: bool = False, ledger=True,
+              stream=None):
+    """Discrete-ordinates comparison tally: radiance averaged over n_bins equal
+    angular bins of [-pi, pi), from the same transport as mc_forward /
+    mc_adjoint.  Returns (binned [n_bins][nz][nx] float64, ledger buffer or None)."""
+    lib = L.load()
+    dev = medium.mua.device
+    src = _Sources(sources, dev)
+    m = medium.c()
+    need = lib.mc_binned_workspace_bytes(C.byref(m), src.arr, src.n, C.byref(run), int(n_bins))
+    if need == 0:
+        raise L.MCError("mc_binned_workspace_bytes", L.MC_ERR_INVALID_ARG)
+    ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+    off = (-ws.data_ptr()) % 256
+    out = torch.empty((int(n_bins), medium.nz, medium.nx), dtype=torch.float64, device=dev)
+    led = torch.zeros(C.sizeof(L.mc_ledger), dtype=torch.uint8, device=dev) if ledger else None
+    L.check("mc_run_binned", lib.mc_run_binned(C.byref(m), src.arr, src.n, C.byref(run), int(bool(adjoint)),
+                                               int(n_bins), out.data_ptr(), _ptr(led), ws.data_ptr() + off,
+                                               ws.numel() - off, _stream(stream)))
+    if stream is not None:
+        ws.record_stream(stream)
+    return out, led
+
+
 def mc_residual(medium: Medium, coeffs: torch.Tensor, hmeas: torch.Tensor, stream=None):
     """Returns (q_star [nz][nx] float64, eps device scalar float64)."""
     lib = L.load()

@@ -467,6 +467,45 @@ def test_batch_equals_separate_runs(live):
         rmc.mc_set_tuning(base)
 
 
+# ---------------------------------------------------------------- discrete ordinates
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_discrete_ordinates_tally(adjoint):
+    """The angle-binned radiance (the comparison tally of Sec. 3.1) against the
+    oracle's binned tally on the same packets, and its angular integral
+    against the harmonic run's a0: both tally the same segment deposits, so
+    sum_b binned[b] * (2pi / n_bins) = a0 up to the fixed-point rounding of
+    the harmonic run."""
+    rmc = _rmc()
+    O = _oracle()
+    ph = P.disc_phantom(24, 0.25, 0.03, 6.0, 0.8, seed=15, radius=(0.8, 1.5))
+    if adjoint:
+        specs, tag = [P.map_source(P.residual_like_map(ph, seed=5))], 1
+    else:
+        specs, tag = [P.point_source(2.97, 3.11), P.SourceSpec("line", 0.0, 0.0, 6.0, 0.0, 0.0, 1.0, 0, 0.5)], 0
+    n, nb, B = 40_000, 16, 8
+    med = rmc.Medium.from_phantom(ph)
+    run = rmc.make_run(n, 4, seed=19, stream_tag=tag)
+    gb, led = rmc.mc_binned(med, specs, run, nb, adjoint=adjoint)
+    gb = gb.cpu().numpy()
+    L = rmc.ledger_dict(led)
+    assert L["packets"] == n
+    om, osrc = O.medium_from(ph), O.sources_from(specs)
+    parts = []
+    for b in range(B):
+        a, e = (n * b) // B, (n * (b + 1)) // B
+        r = O.Run(e - a, 19, 4, first_packet_id=a, stream_tag=tag, adjoint=int(adjoint))
+        parts.append(O.run_mc(om, osrc, r, n_threads=min(16, os.cpu_count() or 8), n_bins=nb)[2] * (e - a) / n)
+    parts = np.array(parts)
+    ob, se = parts.sum(axis=0), parts.std(axis=0, ddof=1) * np.sqrt(B)
+    _assert_maps(f"binned_{'adj' if adjoint else 'fwd'}", gb, ob, se)
+    fn = rmc.mc_adjoint if adjoint else rmc.mc_forward
+    co, _ = fn(med, specs, run, ledger=False)
+    a0 = co[0].cpu().numpy()
+    integral = gb.sum(axis=0) * (2 * np.pi / nb)
+    big = np.abs(a0) > 1e-6 * np.abs(a0).max()
+    np.testing.assert_allclose(integral[big], a0[big], rtol=1e-5)
+
+
 # ---------------------------------------------------------------- FP64 post-processing
 def test_residual_gradient_detect_fp64():
     import torch

@@ -228,3 +228,23 @@ def test_weight_bound_beyond_the_fixed_point_range_is_unsupported():
     prof[0] = 1e10
     assert lib.mc_forward(C.byref(m), src, 1, C.byref(run), 0x2000, None, 0x3000, 1 << 30, None) == \
         L.MC_ERR_UNSUPPORTED
+
+
+def test_binned_arguments_checked_on_host():
+    """The discrete-ordinates tally takes an even bin count in 2 .. 4096 and a
+    0/1 direction; anything else is refused before any device work."""
+    L, lib = _lib()
+    m = _medium(L)
+    src = (L.mc_source * 1)(_pencil(L))
+    run = L.mc_run(1000, 0, 0, 0, 4, 1e-4, 10.0, 0)
+    assert lib.mc_binned_workspace_bytes(C.byref(m), src, 1, C.byref(run), 16) > 0
+    for nb in (0, 1, 15, 4098):
+        assert lib.mc_binned_workspace_bytes(C.byref(m), src, 1, C.byref(run), nb) == 0
+        assert lib.mc_run_binned(C.byref(m), src, 1, C.byref(run), 0, nb, 0x2000, None, 0x3000, 1 << 30,
+                                 None) == L.MC_ERR_INVALID_ARG
+    assert lib.mc_run_binned(C.byref(m), src, 1, C.byref(run), 2, 16, 0x2000, None, 0x3000, 1 << 30,
+                             None) == L.MC_ERR_INVALID_ARG
+    assert lib.mc_run_binned(C.byref(m), src, 1, C.byref(run), 0, 16, None, None, 0x3000, 1 << 30,
+                             None) == L.MC_ERR_INVALID_ARG
+    assert lib.mc_run_binned(C.byref(m), src, 1, C.byref(run), 0, 16, 0x2000, None, 0x3000, 16,
+                             None) == L.MC_ERR_WORKSPACE
