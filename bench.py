@@ -41,9 +41,9 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
 # reads for a plain 1 GiB device copy.  Valid only for the kernel source it
 # was measured on: reported as null once that source changes.
 TRAFFIC = {
-    "source_sha256": "bc1ae130ae51ebdfdc9b5e0cd221f9dfdf96f670006a6ac12888ae866cbdc730",
-    "fetch_kib_per_launch": 248157.05, "fetch_factor": 2.000,
-    "write_kib_per_launch": 727043.03, "write_factor": 1.000,
+    "source_sha256": "078d52f71d9fd8815841535482f6be245d8462488ca7553cc1df2cfb35678173",
+    "fetch_kib_per_launch": 248168.89, "fetch_factor": 2.000,
+    "write_kib_per_launch": 727214.59, "write_factor": 1.000,
 }
 
 
