@@ -285,6 +285,8 @@ mc_status mc_philox_fill(uint64_t seed, uint32_t tag, uint64_t pid0, uint64_t n,
  * exact, see mc_forward), except flush_track, which moves FP32 partial sums.
  *  live_packets   packets kept alive per generation, 1024 .. 2^26
  *  job_packets    packets of one tile handed to one workgroup, 64 .. 2^20
+ *                 (a run or batch whose pool holds fewer than 2^23 live
+ *                 packets uses half that, to spread over more workgroups)
  *  max_visits     visits in one tile before a packet pauses until the next
  *                 generation, >= 1
  *  tile           tile side in pixels, 0 .. 256 (0, or a tile whose tally does
