@@ -41,9 +41,9 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
 # reads for a plain 1 GiB device copy.  Valid only for the kernel source it
 # was measured on: reported as null once that source changes.
 TRAFFIC = {
-    "source_sha256": "078d52f71d9fd8815841535482f6be245d8462488ca7553cc1df2cfb35678173",
-    "fetch_kib_per_launch": 248168.89, "fetch_factor": 2.000,
-    "write_kib_per_launch": 727214.59, "write_factor": 1.000,
+    "source_sha256": "d02f46c40dad14204a930406274800e4f3dc0c64277f4f2205667d8b30e74213",
+    "fetch_kib_per_launch": 247766.13, "fetch_factor": 2.000,
+    "write_kib_per_launch": 726078.27, "write_factor": 1.000,
 }
 
 
