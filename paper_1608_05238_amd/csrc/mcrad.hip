@@ -146,10 +146,12 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
             k0 += 0x9E3779B9u;
             k1 += 0xBB67AE85u;
         }
-        // one 32x32->64 product each (v_mad_u64_u32) rather than separate low and high multiplies
+        // one 32x32->64 product each (v_mad_u64_u32) rather than separate low and
+        // high multiplies; each three-way XOR is one v_bitop3_b32 (truth table 0x96)
         const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
-        c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
+        c = make_uint4(__builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c.y, k0, 0x96), (uint32_t)p1,
+                       __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c.w, k1, 0x96), (uint32_t)p0);
     }
     return c;
 }
@@ -480,40 +482,34 @@ __device__ __forceinline__ bool scatter(const Params &P, Packet &p, const float 
     return true;
 }
 
-// acc += T [1, cos t .. cos Nt, sin t .. sin Nt] with the harmonic values
-// generated on the fly by the same recurrence as harmonics(): the transport
-// loop would recompute the vector for nearly every iteration anyway (some lane
-// of the wave scatters), so not storing it saves 2N+1 registers per lane.
+// acc = keep * acc + T [1, cos t .. cos Nt, sin t .. sin Nt].  The products
+// y_n = T cos nt and T sin nt come straight from the recurrences of
+// harmonics() started at y_0 = T (they are linear, so scaling by T commutes
+// with them), and one FMA per channel both adds y_n and applies the reset
+// after a flush (keep = 0; keep = 1 adds exactly).  Every kernel deposits
+// through this function, so a visit's sums are the same bits whichever kernel
+// completes it.  The recurrences run for nearly every segment anyway (some
+// lane of the wave scatters), so no harmonic vector is stored.
 template <int NH>
-__device__ __forceinline__ void deposit_harmonics(float T, float sx, float sz, float *acc) {
-    acc[0] += T;
+__device__ __forceinline__ void deposit_harmonics(float T, float sx, float sz, float keep, float *acc) {
+    acc[0] = fmaf(acc[0], keep, T);
     if constexpr (NH >= 1) {
-        acc[1] = fmaf(T, sz, acc[1]);
-        acc[NH + 1] = fmaf(T, sx, acc[NH + 1]);
-    }
-    const float c2 = 2.f * sz;
-    float cm = 1.f, sm = 0.f, cn = sz, sn = sx;
+        const float c2 = 2.f * sz;
+        float cm = T, sm = 0.f, cn = T * sz, sn = T * sx;
+        acc[1] = fmaf(acc[1], keep, cn);
+        acc[NH + 1] = fmaf(acc[NH + 1], keep, sn);
 #pragma unroll
-    for (int n = 2; n <= NH; ++n) {
-        const float c = n == 2 ? fmaf(c2, sz, -1.f) : fmaf(c2, cn, -cm);
-        const float s_ = n == 2 ? c2 * sx : fmaf(c2, sn, -sm);
-        cm = cn;
-        sm = sn;
-        cn = c;
-        sn = s_;
-        acc[n] = fmaf(T, c, acc[n]);
-        acc[NH + n] = fmaf(T, s_, acc[NH + n]);
+        for (int n = 2; n <= NH; ++n) {
+            const float c = fmaf(c2, cn, -cm);
+            const float s_ = n == 2 ? c2 * sn : fmaf(c2, sn, -sm);
+            cm = cn;
+            sm = sn;
+            cn = c;
+            sn = s_;
+            acc[n] = fmaf(acc[n], keep, c);
+            acc[NH + n] = fmaf(acc[NH + n], keep, s_);
+        }
     }
-}
-
-// Recompute the harmonic vector when any lane of the wave changed direction.
-// Every lane recomputes: h is a pure function of the direction, so lanes
-// whose direction did not change get the same values back, and no select
-// per channel is needed.  One call site per loop keeps h in place.
-template <int NH>
-__device__ __forceinline__ void refresh_harmonics(bool dirty, const Packet &p, float *h) {
-    if (!__ballot(dirty)) return;
-    harmonics<NH>(p.sx, p.sz, h);
 }
 
 __device__ __forceinline__ void ledger_flush(const Params &P, LedgerRegs &L) {
@@ -607,7 +603,7 @@ __global__ void __launch_bounds__(grid_block(NH)) k_transport_grid(Params P) {
     Packet p;
     idle_packet(p, 0, 0);
     float mag = 0.f;   // sum of the |a0| this lane flushed: bounds every slot's magnitude
-    float acc[K];
+    float acc[K], keep = 1.f;   // keep = 0 after a flush: the next deposit restarts the sums
 #pragma unroll
     for (int j = 0; j < K; ++j) acc[j] = 0.f;
     LedgerRegs L;
@@ -644,7 +640,7 @@ __global__ void __launch_bounds__(grid_block(NH)) k_transport_grid(Params P) {
         dw = live ? dw : 0.f;
         L.absorbed += (double)dw;
         L.segments += live ? 1u : 0u;
-        deposit_harmonics<NH>(T * fx, p.sx, p.sz, acc);   // direction of the segment, before any scatter
+        deposit_harmonics<NH>(T * fx, p.sx, p.sz, keep, acc);   // direction of the segment, before any scatter
         const bool at = ev == EV_SCATTER;
         const bool killed = scatter_masked(P, p, at, mm.w, L);
         const bool vend = killed || (ev != EV_NONE && !at);   // the visit ends
@@ -660,8 +656,7 @@ __global__ void __launch_bounds__(grid_block(NH)) k_transport_grid(Params P) {
             mag += fabsf(acc[0]);
         }
         L.visits += vend ? 1u : 0u;
-#pragma unroll
-        for (int j = 0; j < K; ++j) acc[j] = flush ? 0.f : acc[j];
+        keep = flush ? 0.f : 1.f;
     }
     ledger_flush_block(P.led, P.ledc, L);
     float wm = mag;
@@ -1042,7 +1037,7 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
         idle_packet(p, tx0, tz0);
         uint32_t nvis = 0;
         float mag = 0.f;   // sum of the |a0| this lane flushed in this job: bounds every slot's magnitude
-        float acc[K];
+        float acc[K], keep = 1.f;   // keep = 0 after a flush: the next deposit restarts the sums
 #pragma unroll
         for (int j = 0; j < K; ++j) acc[j] = 0.f;
         // Each lane holds the record of its next packet in registers, loaded
@@ -1098,7 +1093,7 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
             dw = live ? dw : 0.f;
             L.absorbed += (double)dw;
             L.segments += live ? 1u : 0u;
-            deposit_harmonics<NH>(T * fx, p.sx, p.sz, acc);   // direction of the segment, before any scatter
+            deposit_harmonics<NH>(T * fx, p.sx, p.sz, keep, acc);   // direction of the segment, before any scatter
             const bool at = ev == EV_SCATTER;
             const bool killed = scatter_masked(H, p, at, mm.w, L);
             const bool vend = killed || (ev != EV_NONE && !at);   // the visit ends
@@ -1132,8 +1127,7 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
                     leave = out || nvis >= (more ? P.max_visits : min(P.max_visits, tail_nvis + P.tail_visits));
                 }
             }
-#pragma unroll
-            for (int j = 0; j < K; ++j) acc[j] = flush ? 0.f : acc[j];
+            keep = flush ? 0.f : 1.f;
             slice_put(P, q, leave, p, dest, prob);
             if (leave) {
                 p.alive = false;
@@ -1181,17 +1175,14 @@ __global__ void __launch_bounds__(kBlockFinish) k_finish(Params P, uint32_t n_re
     LedgerRegs L;
     Packet p;
     idle_packet(p, 0, 0);
-    float h[K], acc[K];
+    float acc[K], keep = 1.f;   // keep = 0 after a flush: the next deposit restarts the sums
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
-        h[j] = 0.f;
-        acc[j] = 0.f;
-    }
+    for (int j = 0; j < K; ++j) acc[j] = 0.f;
     // visit sums are scaled and rounded as in the LDS tallies (fixed_add), so a
     // visit adds the same value whichever kernel completes it
     const float fx = P.fx, flush_at = P.flush_at;
     const double fx_inv = P.fx_inv;
-    bool more = true, dirty = false;
+    bool more = true;
     for (;;) {
         if (more) {
             const unsigned long long dead = __ballot(!p.alive);
@@ -1204,18 +1195,13 @@ __global__ void __launch_bounds__(kBlockFinish) k_finish(Params P, uint32_t n_re
                 if (base + ndead >= n_rec) more = false;
                 if (!p.alive) {
                     const uint32_t my = base + __popcll(dead & lt_mask);
-                    if (my < n_rec && P.qtile[my] != kInvalidTile && P.qa[my].prob == P.prob) {
-                        rec_load(P.qa + my, p);
-                        dirty = true;
-                    }
+                    if (my < n_rec && P.qtile[my] != kInvalidTile && P.qa[my].prob == P.prob) rec_load(P.qa + my, p);
                 }
             }
         }
         if (!__ballot(p.alive)) {
             if (!more) break;
         }
-        refresh_harmonics<NH>(dirty, p, h);
-        dirty = false;
         int ev = EV_NONE, pix = 0;
         float T = 0.f, dw = 0.f;
         if (p.alive) {
@@ -1224,13 +1210,10 @@ __global__ void __launch_bounds__(kBlockFinish) k_finish(Params P, uint32_t n_re
             L.absorbed += (double)dw;
             L.segments += 1;
         }
-        const float Ts = T * fx;
-#pragma unroll
-        for (int j = 0; j < K; ++j) acc[j] = fmaf(Ts, h[j], acc[j]);
+        deposit_harmonics<NH>(T * fx, p.sx, p.sz, keep, acc);   // direction of the segment, before any scatter
         bool vend = false;
         if (ev == EV_SCATTER) {
-            if (scatter_dir(P, p, P.g[pix], L)) dirty = true;
-            else vend = true;
+            if (!scatter_dir(P, p, P.g[pix], L)) vend = true;
         } else if (ev != EV_NONE) {
             vend = true;
             if (ev == EV_ESCAPE) {
@@ -1263,8 +1246,7 @@ __global__ void __launch_bounds__(kBlockFinish) k_finish(Params P, uint32_t n_re
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
-#pragma unroll
-        for (int j = 0; j < K; ++j) acc[j] = flush ? 0.f : acc[j];
+        keep = flush ? 0.f : 1.f;
     }
     ledger_flush_block(P.led, P.ledc, L);
 }
