@@ -373,20 +373,22 @@ __device__ bool launch(const Params &P, uint64_t pid, Packet &p, float *h, Ledge
     return true;
 }
 
-// expm1(-x) for x >= 0.  Below 1/4 a Taylor polynomial in Horner form
-// (truncation below x^9/9! ~ 1e-11 relative there); above, the library call.
-__device__ __forceinline__ float expm1_neg(float x) {
+// f(x) = (1 - e^-x)/x for x >= 0, with f(0) = 1: the fraction of the weight
+// absorbed per unit optical depth on a segment.  Below 1/4 its Taylor series
+// sum_k (-x)^k/(k+1)! in Horner form, truncated after x^7 (remainder below
+// x^8/9! ~ 4e-11 there); above, the library expm1.
+__device__ __forceinline__ float absorbed_per_depth(float x) {
     if (x < 0.25f) {
-        float t = fmaf(-x, 1.f / 8.f, 1.f);
-        t = fmaf(-x * (1.f / 7.f), t, 1.f);
-        t = fmaf(-x * (1.f / 6.f), t, 1.f);
-        t = fmaf(-x * (1.f / 5.f), t, 1.f);
-        t = fmaf(-x * 0.25f, t, 1.f);
-        t = fmaf(-x * (1.f / 3.f), t, 1.f);
-        t = fmaf(-x * 0.5f, t, 1.f);
-        return -x * t;
+        float t = -1.f / 40320.f;
+        t = fmaf(t, x, 1.f / 5040.f);
+        t = fmaf(t, x, -1.f / 720.f);
+        t = fmaf(t, x, 1.f / 120.f);
+        t = fmaf(t, x, -1.f / 24.f);
+        t = fmaf(t, x, 1.f / 6.f);
+        t = fmaf(t, x, -0.5f);
+        return fmaf(t, x, 1.f);
     }
-    return expm1f(-x);
+    return -expm1f(-x) * __builtin_amdgcn_rcpf(x);
 }
 
 // One segment: run to the next pixel face or to the end of the free path,
@@ -403,8 +405,10 @@ __device__ __forceinline__ int step(const PP &P, Packet &p, const float4 m, floa
     const float od = m.y * d;
     const bool scat = od > p.tau;
     const float l = scat ? p.tau * m.z : d;
-    dw = -p.w * expm1_neg(m.x * l);   // weight absorbed on the segment
-    T = m.x > 0.f ? dw * __builtin_amdgcn_rcpf(m.x) : p.w * l;   // track length weighted by the weight
+    const float x = m.x * l;
+    const float wf = p.w * absorbed_per_depth(x);
+    dw = wf * x;   // weight absorbed on the segment
+    T = wf * l;    // track length weighted by the weight (= dw / mua)
     p.w -= dw;
     const float nfx = fminf(fmaxf(p.fx + l * p.sx, 0.f), 1.f);
     const float nfz = fminf(fmaxf(p.fz + l * p.sz, 0.f), 1.f);
@@ -416,6 +420,28 @@ __device__ __forceinline__ int step(const PP &P, Packet &p, const float4 m, floa
     p.fz = cz ? (pz ? 0.f : 1.f) : nfz;
     const bool out = (unsigned)p.ix >= (unsigned)P.nx || (unsigned)p.iz >= (unsigned)P.nz;
     return scat ? EV_SCATTER : (out ? EV_ESCAPE : EV_CROSS);
+}
+
+// sin(pi x) for |x| <= 1/2: the Taylor series of sin t at t = pi x, with pi
+// folded into the coefficients and truncated after t^13 (remainder below
+// (pi/2)^15/15! ~ 7e-10).  Both scatter factors use it: the cosine as
+// sin(pi min(u, 1 - u)), whose argument is exact and keeps full relative
+// accuracy where the cosine goes to zero.
+constexpr double kPiD = 3.14159265358979323846;
+__device__ __forceinline__ float sinpi_half(float x) {
+    constexpr double p2 = kPiD * kPiD;
+    constexpr float c1 = (float)kPiD, c3 = (float)(-kPiD * p2 / 6.0), c5 = (float)(kPiD * p2 * p2 / 120.0),
+                    c7 = (float)(-kPiD * p2 * p2 * p2 / 5040.0), c9 = (float)(kPiD * p2 * p2 * p2 * p2 / 362880.0),
+                    c11 = (float)(-kPiD * p2 * p2 * p2 * p2 * p2 / 39916800.0),
+                    c13 = (float)(kPiD * p2 * p2 * p2 * p2 * p2 * p2 / 6227020800.0);
+    const float x2 = x * x;
+    float q = fmaf(c13, x2, c11);
+    q = fmaf(q, x2, c9);
+    q = fmaf(q, x2, c7);
+    q = fmaf(q, x2, c5);
+    q = fmaf(q, x2, c3);
+    q = fmaf(q, x2, c1);
+    return x * q;
 }
 
 // Scatter site: termination test on |W| (Sec. 3, Sec. 6), then the 2D HG
@@ -442,8 +468,8 @@ __device__ __forceinline__ bool scatter_masked(const PP &P, Packet &p, const boo
             }
         }
     }
-    float sp, cp;
-    sincospif(p.uh - 0.5f, &sp, &cp);
+    const float sp = sinpi_half(p.uh - 0.5f);              // sin(pi (u - 1/2))
+    const float cp = sinpi_half(fminf(p.uh, 1.f - p.uh));  // cos(pi (u - 1/2)), exact argument
     const float a = (1.f + g) * cp, b = (1.f - g) * sp;
     const float inv = __builtin_amdgcn_rcpf(a * a + b * b);
     const float cd = (a * a - b * b) * inv, sd = 2.f * a * b * inv;
