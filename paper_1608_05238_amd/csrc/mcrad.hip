@@ -468,8 +468,9 @@ __device__ __forceinline__ bool scatter_masked(const PP &P, Packet &p, const boo
             }
         }
     }
-    const float sp = sinpi_half(p.uh - 0.5f);              // sin(pi (u - 1/2))
-    const float cp = sinpi_half(fminf(p.uh, 1.f - p.uh));  // cos(pi (u - 1/2)), exact argument
+    const float y = p.uh - 0.5f;                 // exact
+    const float sp = sinpi_half(y);              // sin(pi (u - 1/2))
+    const float cp = sinpi_half(0.5f - fabsf(y));  // cos(pi (u - 1/2)); the argument min(u, 1 - u) is exact
     const float a = (1.f + g) * cp, b = (1.f - g) * sp;
     const float inv = __builtin_amdgcn_rcpf(a * a + b * b);
     const float cd = (a * a - b * b) * inv, sd = 2.f * a * b * inv;
@@ -1110,7 +1111,8 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
             }
             // every lane steps (no branch); a free lane's result is discarded
             const bool live = p.alive;
-            const int lp = live ? (p.iz - tz0) * P.tw + (p.ix - tx0) : 0;
+            // 24-bit products (full-rate v_mad_i32_i24): tile sizes and offsets are small
+            const int lp = live ? __mul24(p.iz - tz0, P.tw) + (p.ix - tx0) : 0;
             float T = 0.f, dw = 0.f;
             const float4 mm = smed[lp];
             int ev = step(H, p, mm, T, dw);
@@ -1133,7 +1135,7 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
             bool leave = false;
             uint32_t dest = tile;
             if (flush) {
-                unsigned long long *t = fxt + lp * K;
+                unsigned long long *t = fxt + __umul24((uint32_t)lp, (uint32_t)K);
 #pragma unroll
                 for (int j = 0; j < K; ++j) fixed_add_raw(t + j, acc[j]);
                 atomicAdd(sadds + lp, 1u);
@@ -1146,7 +1148,7 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
                     const int ox = p.ix < tx0 ? -1 : (p.ix >= tx0 + P.tw ? 1 : 0);
                     const int oz = p.iz < tz0 ? -1 : (p.iz >= tz0 + P.th ? 1 : 0);
                     const bool out = (ox | oz) != 0;
-                    dest = (uint32_t)((int)tile + oz * ntx + ox);   // a crossing moves one pixel: a neighbour tile
+                    dest = (uint32_t)((int)tile + __mul24(oz, ntx) + ox);   // a crossing moves one pixel: a neighbour tile
                     // once the job has no packets left to hand out, a packet pauses
                     // after tail_visits more visits so the workgroup is not held by
                     // its longest stay (it resumes next generation)
