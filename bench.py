@@ -16,6 +16,10 @@ Besides the throughput the line carries:
                 the kernel source changed since they were taken);
   lds_roofline  the K LDS tally adds per visit per second against the
                 random-address 64-bit LDS add rate measured in the same run;
+  valu_roofline the transport launches' VALU wave-instructions per second
+                (rocprofv3's count per visit for this kernel source, null once
+                it changes) against one wave64 instruction per SIMD every 4
+                cycles at 2.4 GHz;
   cpu_baseline  the FP64 oracle on the host's cores (and on one thread) on a
                 bounded sample of the same workload.
 Other modes: --time-to-error, --batch, --pencil32 (one JSON line each).
@@ -41,9 +45,12 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
 # reads for a plain 1 GiB device copy.  Valid only for the kernel source it
 # was measured on: reported as null once that source changes.
 TRAFFIC = {
-    "source_sha256": "d02f46c40dad14204a930406274800e4f3dc0c64277f4f2205667d8b30e74213",
-    "fetch_kib_per_launch": 247766.13, "fetch_factor": 2.000,
-    "write_kib_per_launch": 726078.27, "write_factor": 1.000,
+    "source_sha256": "eb872102c233b78485941fdb7c79ed5ac83a540148621bb192db0cb7d0284957",
+    "fetch_kib_per_launch": 258649.07, "fetch_factor": 2.000,
+    "write_kib_per_launch": 736893.69, "write_factor": 1.000,
+    # VALU wave-instructions per pixel visit (rocprofv3 SQ_INSTS_VALU over the
+    # k_transport_tile<16> and k_finish<16> dispatches of one benchmark step)
+    "valu_per_visit": 13.665,
 }
 
 
@@ -55,6 +62,17 @@ def traffic_bytes_per_launch():
             return None
     t = TRAFFIC
     return 1024.0 * (t["fetch_kib_per_launch"] * t["fetch_factor"] + t["write_kib_per_launch"] * t["write_factor"])
+
+
+def valu_per_visit():
+    """SQ_INSTS_VALU per pixel visit of the transport kernels, or None once
+    the kernel source differs from the one it was counted on."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_1608_05238_amd", "csrc", "mcrad.hip")
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != TRAFFIC["source_sha256"]:
+            return None
+    return TRAFFIC["valu_per_visit"]
 
 
 def lds_atomic_ceiling(dev) -> float:
@@ -435,6 +453,17 @@ def main() -> int:
     out["lds_roofline"] = {"bound": "lds_atomics", "achieved": lane_ops, "peak": ceiling, "unit": "lane-ops/s",
                            "frac": lane_ops / ceiling, "kernel": "k_transport_tile<16> + k_finish<16>",
                            "peak_source": "ds_add_u64 at random LDS addresses, mb_lds_atomics, this run"}
+    # the issue ceiling the loop actually meets: VALU wave-instructions (counted
+    # once per source by rocprofv3) per launch over the live launch time, against
+    # one wave64 VALU instruction per SIMD every 4 cycles at the 2.4 GHz peak clock
+    vpv = valu_per_visit()
+    ncu = torch.cuda.get_device_properties(dev).multi_processor_count
+    vpeak = ncu * 4 * 2.4e9 / 4
+    vach = vpv * visits / max(tr_launches, 1) / (avg_launch_ms * 1e-3) if (vpv and tr_launches) else None
+    out["valu_roofline"] = {"bound": "alu", "achieved": vach, "peak": vpeak, "unit": "wave64 VALU instructions/s",
+                            "frac": vach / vpeak if vach else None, "valu_per_visit": vpv,
+                            "kernel": "k_transport_tile<16> + k_finish<16>",
+                            "peak_source": f"{ncu} CUs x 4 SIMDs x 2.4 GHz / 4 cycles per wave64 instruction"}
     if args.cpu_packets > 0:
         threads = min(16, os.cpu_count() or 1)
         log(f"cpu baseline: oracle with {args.cpu_packets}+{args.cpu_packets} packets on {threads} threads")
