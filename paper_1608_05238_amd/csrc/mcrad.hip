@@ -214,6 +214,16 @@ struct LedgerRegs {
     uint32_t packets = 0, segments = 0, visits = 0, scatters = 0;
 };
 
+// The tile transport's ledger.  Escape and roulette come about once per
+// packet, so a lane meets only a few of them between two flushes (one launch
+// or problem): FP32 sums carry them, which keeps the transport loop's
+// loop-carried FP64 state to the per-segment absorbed weight.
+struct LedgerTile {
+    double absorbed = 0;
+    float escaped = 0.f, gain = 0.f, loss = 0.f;
+    uint32_t segments = 0, visits = 0, scatters = 0;
+};
+
 // h = [1, cos t .. cos Nt, sin t .. sin Nt] for the direction (sin t, cos t)
 // by the three-term recurrences cos (n+1)t = 2 cos t cos nt - cos (n-1)t and
 // sin (n+1)t = 2 cos t sin nt - sin (n-1)t: one FMA per value.  A rounding
@@ -452,9 +462,8 @@ __device__ __forceinline__ float sinpi_half(float x) {
 // same instructions and only those lanes commit (selects, so the Philox
 // rounds and the deflection form one basic block the scheduler can
 // interleave).  Returns true for the lanes whose packet was terminated.
-template <class PP>
-__device__ __forceinline__ bool scatter_masked(const PP &P, Packet &p, const bool at, const float g,
-                                               LedgerRegs &L) {
+template <class PP, class LG>
+__device__ __forceinline__ bool scatter_masked(const PP &P, Packet &p, const bool at, const float g, LG &L) {
     bool kill = false;
     const bool low = at && (p.k >= kMaxInteractions || fabsf(p.w) < P.wth * p.w0abs);
     if (__ballot(low)) {   // rare: roulette or the hard cap on interactions
@@ -463,7 +472,7 @@ __device__ __forceinline__ bool scatter_masked(const PP &P, Packet &p, const boo
                 kill = true;
                 L.loss += p.w;
             } else {
-                L.gain += (double)((P.rm - 1.f) * p.w);
+                L.gain += (P.rm - 1.f) * p.w;
                 p.w *= P.rm;
             }
         }
@@ -586,6 +595,18 @@ __device__ __forceinline__ void ledger_flush_block(double *led, unsigned long lo
             if (c[i]) atomicAdd(ledc + i, c[i]);
     }
     __syncthreads();   // the staging arrays may be reused by a next call
+}
+
+__device__ __forceinline__ void ledger_flush_tile(double *led, unsigned long long *ledc, const LedgerTile &L) {
+    LedgerRegs R;
+    R.absorbed = L.absorbed;
+    R.escaped = L.escaped;
+    R.gain = L.gain;
+    R.loss = L.loss;
+    R.segments = L.segments;
+    R.visits = L.visits;
+    R.scatters = L.scatters;
+    ledger_flush_block(led, ledc, R);
 }
 
 // Add v (already scaled by the run's fixed-point factor), rounded to the
@@ -1016,7 +1037,7 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
     const int lane = __lane_id();
     const int ntp = P.tw * P.th;
     const unsigned long long lt_mask = (1ull << lane) - 1ull;
-    LedgerRegs L;
+    LedgerTile L;
     QueueSlice q;
     int cur = -1;   // problem whose ledger L holds
 
@@ -1039,8 +1060,8 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
         const ProbDev &pd = P.probs[prob];
         if ((int)prob != cur) {   // the ledger follows the problem (uniform in the workgroup)
             if (cur >= 0) {
-                ledger_flush_block(P.probs[cur].led, P.probs[cur].ledc, L);
-                L = LedgerRegs();
+                ledger_flush_tile(P.probs[cur].led, P.probs[cur].ledc, L);
+                L = LedgerTile();
             }
             cur = (int)prob;
         }
@@ -1180,7 +1201,7 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
         __syncthreads();
     }
     slice_finish(P, q);
-    if (cur >= 0) ledger_flush_block(P.probs[cur].led, P.probs[cur].ledc, L);   // cur is uniform
+    if (cur >= 0) ledger_flush_tile(P.probs[cur].led, P.probs[cur].ledc, L);   // cur is uniform
 }
 
 // ------------------------------------------------------------------ tail finisher
