@@ -1212,6 +1212,32 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
 // contiguous runs of atomics.
 constexpr int kBlockFinish = 256;
 
+// Adds a wave's staged visit sums (n visits of K values) to the HBM tally:
+// consecutive lanes take consecutive values, so each pixel's K channels go
+// out as one contiguous run of atomics.
+__device__ __forceinline__ void finish_flush_stage(const Params &P, const float *stage, const int *stage_pix, int n,
+                                                   int K, double fx_inv) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int total = n * K;
+    for (int e = __lane_id(); e < total; e += 64) {
+        const int v = e / K;
+        const float val = stage[e];
+        if (val != 0.f)
+            unsafeAtomicAdd(P.t64 + (size_t)stage_pix[v] * K + (e - v * K), __builtin_rint((double)val) * fx_inv);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Few packets per lane and long histories make this kernel latency-bound, so
+// its loop keeps global memory off the dependent chain where it can: the
+// medium of the pixel a packet enters is loaded one iteration ahead of its
+// use, and a wave gathers the sums of up to 64 completed visits in LDS before
+// it adds them to the tally (the wait for those atomics then comes once per
+// buffer, not once per visit).
 template <int NH>
 __global__ void __launch_bounds__(kBlockFinish) k_finish(Params P, uint32_t n_rec) {
     constexpr int K = 2 * NH + 1;
@@ -1224,6 +1250,7 @@ __global__ void __launch_bounds__(kBlockFinish) k_finish(Params P, uint32_t n_re
     LedgerRegs L;
     Packet p;
     idle_packet(p, 0, 0);
+    float4 mm = make_float4(0.f, 0.f, 0.f, 0.f);   // medium of the packet's pixel
     float acc[K], keep = 1.f;   // keep = 0 after a flush: the next deposit restarts the sums
 #pragma unroll
     for (int j = 0; j < K; ++j) acc[j] = 0.f;
@@ -1232,6 +1259,7 @@ __global__ void __launch_bounds__(kBlockFinish) k_finish(Params P, uint32_t n_re
     const float fx = P.fx, flush_at = P.flush_at;
     const double fx_inv = P.fx_inv;
     bool more = true;
+    int used = 0;   // visits staged in this wave's buffer (wave-uniform)
     for (;;) {
         if (more) {
             const unsigned long long dead = __ballot(!p.alive);
@@ -1244,7 +1272,10 @@ __global__ void __launch_bounds__(kBlockFinish) k_finish(Params P, uint32_t n_re
                 if (base + ndead >= n_rec) more = false;
                 if (!p.alive) {
                     const uint32_t my = base + __popcll(dead & lt_mask);
-                    if (my < n_rec && P.qtile[my] != kInvalidTile && P.qa[my].prob == P.prob) rec_load(P.qa + my, p);
+                    if (my < n_rec && P.qtile[my] != kInvalidTile && P.qa[my].prob == P.prob) {
+                        rec_load(P.qa + my, p);   // a queued packet is inside the grid
+                        mm = P.med[p.iz * P.nx + p.ix];
+                    }
                 }
             }
         }
@@ -1253,16 +1284,21 @@ __global__ void __launch_bounds__(kBlockFinish) k_finish(Params P, uint32_t n_re
         }
         int ev = EV_NONE, pix = 0;
         float T = 0.f, dw = 0.f;
+        const float g = mm.w;   // read before mm is reloaded: the scatter need not wait for that load
         if (p.alive) {
             pix = p.iz * P.nx + p.ix;
-            ev = step(P, p, P.med[pix], T, dw);
+            ev = step(P, p, mm, T, dw);
             L.absorbed += (double)dw;
             L.segments += 1;
         }
+        // the medium of the pixel the next step starts in (a crossing's new
+        // pixel, else the same one), loaded by every lane outside any branch so
+        // the load lands in mm directly and is waited for only at that step
+        mm = P.med[ev == EV_CROSS ? p.iz * P.nx + p.ix : pix];
         deposit_harmonics<NH>(T * fx, p.sx, p.sz, keep, acc);   // direction of the segment, before any scatter
         bool vend = false;
         if (ev == EV_SCATTER) {
-            if (!scatter_dir(P, p, P.g[pix], L)) vend = true;
+            if (!scatter_dir(P, p, g, L)) vend = true;   // the pixel of the step
         } else if (ev != EV_NONE) {
             vend = true;
             if (ev == EV_ESCAPE) {
@@ -1274,29 +1310,23 @@ __global__ void __launch_bounds__(kBlockFinish) k_finish(Params P, uint32_t n_re
         L.visits += vend ? 1u : 0u;
         const unsigned long long fm = __ballot(flush);
         if (fm) {
+            const int nf = __popcll(fm);
+            if (used + nf > 64) {   // no room: the staged visits go to the tally first
+                finish_flush_stage(P, stage, stage_pix, used, K, fx_inv);
+                used = 0;
+            }
             if (flush) {
-                const int slot = __popcll(fm & lt_mask);
+                const int slot = used + __popcll(fm & lt_mask);
                 float *st = stage + slot * K;
 #pragma unroll
                 for (int j = 0; j < K; ++j) st[j] = acc[j];
                 stage_pix[slot] = pix;
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            const int total = __popcll(fm) * K;
-            for (int e = lane; e < total; e += 64) {
-                const int v = e / K;
-                const float val = stage[e];
-                if (val != 0.f)
-                    unsafeAtomicAdd(P.t64 + (size_t)stage_pix[v] * K + (e - v * K), __builtin_rint((double)val) * fx_inv);
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            used += nf;
         }
         keep = flush ? 0.f : 1.f;
     }
+    if (used) finish_flush_stage(P, stage, stage_pix, used, K, fx_inv);
     ledger_flush_block(P.led, P.ledc, L);
 }
 
