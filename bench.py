@@ -206,6 +206,45 @@ def time_to_error(args) -> dict:
             "sweep": rows}
 
 
+def single_gradient(args) -> dict:
+    """Wall time of one gradient evaluation on disc256 at args.gradient
+    packets per run (the measured data from args.hmeas_packets packets), best
+    of args.steps after args.warmup; the time-to-error search's unit of work
+    at the packet count it settles on."""
+    import torch
+    import phantoms as P
+    from paper_1608_05238_amd import rmc
+    dev = torch.device("cuda", 0)
+    c = P.config2()
+    N = c.n_harm
+    n = int(args.gradient)
+    med = rmc.Medium.from_phantom(c.phantom, dev)
+    tmed = rmc.Medium.from_phantom(c.extra["true"], dev)
+    ht, _ = rmc.mc_forward(tmed, c.sources, rmc.make_run(int(args.hmeas_packets), N, seed=1), ledger=False)
+    hmeas = rmc.mc_absorbed(tmed, ht)
+
+    def gradient():
+        f, _ = rmc.mc_forward(med, c.sources, rmc.make_run(n, N, seed=7), ledger=False)
+        q, _ = rmc.mc_residual(med, f, hmeas)
+        a, _ = rmc.mc_adjoint(med, [rmc.Source("map", map=q)], rmc.make_run(n, N, seed=7, stream_tag=1),
+                              ledger=False)
+        return rmc.mc_gradient(med, N, f, a, hmeas)
+
+    walls = []
+    for i in range(args.warmup + args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gradient()
+        torch.cuda.synchronize()
+        if i >= args.warmup:
+            walls.append((time.perf_counter() - t0) * 1e3)
+        log(f"gradient at {n:.3g} packets: {(time.perf_counter() - t0) * 1e3:.1f} ms")
+    return {"metric": "wall time of one gradient (forward + residual + adjoint + gradient, N=16)",
+            "value": min(walls), "unit": "ms", "higher_is_better": False, "n_gpus": 1,
+            "packets_forward": n, "packets_adjoint": n, "walls_ms": walls, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "disc256 gradient"}}
+
+
 def batch_workload(args) -> dict:
     """64 problems in one packet pool: 16 sources x 4 wavelengths (mua scaled
     0.5, 1, 2, 4), grids drawn from {128, 192, 256, 512}^2 over the same
@@ -321,6 +360,9 @@ def main() -> int:
     ap.add_argument("--time-to-error", action="store_true",
                     help="instead of the throughput line, measure the wall time to a gradient of fixed error")
     ap.add_argument("--ref-packets", type=float, default=1e9, help="packets of the reference gradient (each run)")
+    ap.add_argument("--gradient", type=float, default=0,
+                    help="time single gradients (forward + residual + adjoint + gradient) at this many packets "
+                         "per run, without the reference and the search of --time-to-error")
     ap.add_argument("--batch", action="store_true",
                     help="instead of the throughput line, time the 64-problem batched workload")
     ap.add_argument("--batch-min", type=float, default=1e6)
@@ -346,6 +388,9 @@ def main() -> int:
         return 0
     if args.batch:
         print(json.dumps(batch_workload(args)), flush=True)
+        return 0
+    if args.gradient > 0:
+        print(json.dumps(single_gradient(args)), flush=True)
         return 0
     if args.pencil32:
         print(json.dumps(pencil32(args)), flush=True)

@@ -743,7 +743,7 @@ __device__ __forceinline__ void rec_store(PacketRec *r, const Packet &p, uint32_
     u[3] = make_uint4((uint32_t)p.pid, (uint32_t)(p.pid >> 32), tile, prob);
 }
 
-__device__ __forceinline__ void rec_decode(const uint4 a, const uint4 b, const uint4 c, const uint4 d, Packet &p) {
+__device__ __forceinline__ void rec_decode(const uint4 a, const uint4 b, const uint4 c, const uint2 d, Packet &p) {
     p.fx = __uint_as_float(a.x);
     p.fz = __uint_as_float(a.y);
     set_dir(p, __uint_as_float(a.z), __uint_as_float(a.w));
@@ -1092,7 +1092,11 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
         // one whole stay ahead, so a refill never waits for memory.
         bool more = true, has_next = false;
         uint32_t tail_nvis = 0;   // visits of the current stay when the job ran out of packets
-        uint4 nr0 = make_uint4(0u, 0u, 0u, 0u), nr1 = nr0, nr2 = nr0, nr3 = nr0;
+        // (the last word is the packet id alone: a load whose destination
+        // registers are partly dead lets them be reused, and the reuse must then
+        // wait for the load)
+        uint4 nr0 = make_uint4(0u, 0u, 0u, 0u), nr1 = nr0, nr2 = nr0;
+        uint2 nr3 = make_uint2(0u, 0u);
         for (;;) {
             // a free lane takes its prefetched record (the only decode site)
             if (!p.alive && has_next) {
@@ -1121,7 +1125,8 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
                             nr0 = r[0];
                             nr1 = r[1];
                             nr2 = r[2];
-                            nr3 = r[3];
+                            const uint64_t id = P.qb[first + my].pid;
+                            nr3 = make_uint2((uint32_t)id, (uint32_t)(id >> 32));
                             has_next = true;
                         }
                     }
