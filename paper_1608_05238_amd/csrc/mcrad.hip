@@ -1105,6 +1105,12 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
                 nvis = 0;
                 tail_nvis = 0;
             }
+            // the medium of the pixel of this step, read before the claim below
+            // so its LDS latency overlaps with that work
+            const bool live = p.alive;
+            // 24-bit products (full-rate v_mad_i32_i24): tile sizes and offsets are small
+            const int lp = live ? __mul24(p.iz - tz0, P.tw) + (p.ix - tx0) : 0;
+            const float4 mm = smed[lp];
             // lanes without a prefetched record claim the next ones of the job
             if (more) {
                 const unsigned long long want = __ballot(!has_next);
@@ -1136,11 +1142,7 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
                 if (!more && !__ballot(has_next)) break;
             }
             // every lane steps (no branch); a free lane's result is discarded
-            const bool live = p.alive;
-            // 24-bit products (full-rate v_mad_i32_i24): tile sizes and offsets are small
-            const int lp = live ? __mul24(p.iz - tz0, P.tw) + (p.ix - tx0) : 0;
             float T = 0.f, dw = 0.f;
-            const float4 mm = smed[lp];
             int ev = step(H, p, mm, T, dw);
             ev = live ? ev : EV_NONE;
             T = live ? T : 0.f;
