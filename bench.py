@@ -45,12 +45,12 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
 # reads for a plain 1 GiB device copy.  Valid only for the kernel source it
 # was measured on: reported as null once that source changes.
 TRAFFIC = {
-    "source_sha256": "eb872102c233b78485941fdb7c79ed5ac83a540148621bb192db0cb7d0284957",
-    "fetch_kib_per_launch": 258649.07, "fetch_factor": 2.000,
-    "write_kib_per_launch": 736893.69, "write_factor": 1.000,
+    "source_sha256": "0f90f2e95474d0b5ba49bf684e8d7c9b96d0b6dd5a5bdc0115fa267111ee7a61",
+    "fetch_kib_per_launch": 225777.56, "fetch_factor": 2.000,
+    "write_kib_per_launch": 696179.51, "write_factor": 1.000,
     # VALU wave-instructions per pixel visit (rocprofv3 SQ_INSTS_VALU over the
     # k_transport_tile<16> and k_finish<16> dispatches of one benchmark step)
-    "valu_per_visit": 13.665,
+    "valu_per_visit": 13.039,
 }
 
 
