@@ -454,19 +454,14 @@ __device__ __forceinline__ float sinpi_half(float x) {
     return x * q;
 }
 
-// Scatter site: termination test on |W| (Sec. 3, Sec. 6), then the 2D HG
-// deflection (eq. scattering_angle) written without atan/tan: with
-// a = (1+g) cos(pi(u-1/2)), b = (1-g) sin(pi(u-1/2)), tan(dt/2) = b/a, so
-// cos dt = (a^2-b^2)/(a^2+b^2), sin dt = 2ab/(a^2+b^2); then the next block
-// of random numbers.  `at` marks the lanes that scatter; every lane runs the
-// same instructions and only those lanes commit (selects, so the Philox
-// rounds and the deflection form one basic block the scheduler can
-// interleave).  Returns true for the lanes whose packet was terminated.
+// Scatter site, in two parts.  First the termination test on |W| (Sec. 3,
+// Sec. 6): Russian roulette below the threshold, or the hard cap on
+// interactions; returns true for the lanes whose packet is terminated.
 template <class PP, class LG>
-__device__ __forceinline__ bool scatter_masked(const PP &P, Packet &p, const bool at, const float g, LG &L) {
+__device__ __forceinline__ bool scatter_roulette(const PP &P, Packet &p, const bool at, LG &L) {
     bool kill = false;
     const bool low = at && (p.k >= kMaxInteractions || fabsf(p.w) < P.wth * p.w0abs);
-    if (__ballot(low)) {   // rare: roulette or the hard cap on interactions
+    if (__ballot(low)) {   // rare
         if (low) {
             if (p.k >= kMaxInteractions || (P.flags & MC_FLAG_LITERAL_TRUNCATION) || !(p.ur < P.inv_rm)) {
                 kill = true;
@@ -477,6 +472,19 @@ __device__ __forceinline__ bool scatter_masked(const PP &P, Packet &p, const boo
             }
         }
     }
+    return kill;
+}
+
+// Then the 2D HG deflection (eq. scattering_angle) written without atan/tan:
+// with a = (1+g) cos(pi(u-1/2)), b = (1-g) sin(pi(u-1/2)), tan(dt/2) = b/a,
+// so cos dt = (a^2-b^2)/(a^2+b^2), sin dt = 2ab/(a^2+b^2); and the next
+// block of random numbers.  `go` marks the lanes that scatter and survived;
+// every lane runs the same instructions and only those lanes commit
+// (selects, so the Philox rounds and the deflection form one basic block the
+// scheduler can interleave).  `kill` (from the roulette) ends the packet.
+template <class PP, class LG>
+__device__ __forceinline__ void scatter_deflect(const PP &P, Packet &p, const bool go, const bool kill, const float g,
+                                                LG &L) {
     const float y = p.uh - 0.5f;                 // exact
     const float sp = sinpi_half(y);              // sin(pi (u - 1/2))
     const float cp = sinpi_half(0.5f - fabsf(y));  // cos(pi (u - 1/2)); the argument min(u, 1 - u) is exact
@@ -490,7 +498,6 @@ __device__ __forceinline__ bool scatter_masked(const PP &P, Packet &p, const boo
     nz_ *= rn;
     const uint4 r = rng_block(P, p.pid, p.k + 1);
     const float tau = __builtin_amdgcn_logf(u01(r.x)) * -0.693147180559945309f;   // see new_leg
-    const bool go = at && !kill;
     const float isx = nx_ != 0.f ? __builtin_amdgcn_rcpf(nx_) : INFINITY;
     const float isz = nz_ != 0.f ? __builtin_amdgcn_rcpf(nz_) : INFINITY;
     p.sx = go ? nx_ : p.sx;
@@ -503,6 +510,14 @@ __device__ __forceinline__ bool scatter_masked(const PP &P, Packet &p, const boo
     p.ur = go ? u01(r.z) : p.ur;
     p.alive = p.alive && !kill;
     L.scatters += go ? 1u : 0u;
+}
+
+// Both parts in order; `at` marks the lanes that scatter.  Returns true for
+// the lanes whose packet was terminated.
+template <class PP, class LG>
+__device__ __forceinline__ bool scatter_masked(const PP &P, Packet &p, const bool at, const float g, LG &L) {
+    const bool kill = scatter_roulette(P, p, at, L);
+    scatter_deflect(P, p, at && !kill, kill, g, L);
     return kill;
 }
 
@@ -1151,7 +1166,10 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
             L.segments += live ? 1u : 0u;
             deposit_harmonics<NH>(T * fx, p.sx, p.sz, keep, acc);   // direction of the segment, before any scatter
             const bool at = ev == EV_SCATTER;
-            const bool killed = scatter_masked(H, p, at, mm.w, L);
+            // the roulette decides whether the visit ends here; the deflection
+            // and its random numbers come after the flush below, so that their
+            // arithmetic overlaps the flush's LDS atomics
+            const bool killed = scatter_roulette(H, p, at, L);
             const bool vend = killed || (ev != EV_NONE && !at);   // the visit ends
             // |a_n| <= a0 (one sign per packet): a long stay in one pixel is
             // flushed in parts, so every flush stays inside fixed_add's range
@@ -1169,6 +1187,7 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
                 atomicAdd(sadds + lp, 1u);
                 mag += fabsf(acc[0]);
             }
+            scatter_deflect(H, p, at && !killed, killed, mm.w, L);
             if (vend) {
                 L.visits += 1;
                 nvis += 1;
