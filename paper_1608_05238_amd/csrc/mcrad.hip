@@ -2213,9 +2213,18 @@ mc_status run_batch(const BatchProblem *pb, int n, void *ws, size_t ws_bytes, hi
     const unsigned bgrid = (unsigned)std::min<uint64_t>((B.cap_a + 255) / 256, 4096);
     const unsigned cgrid = (unsigned)std::min<uint64_t>((B.cap_a + 255) / 256, 4 * (uint64_t)cus);
     const Params &P0 = PP[0];   // the sort and transport kernels read only batch-wide fields
-    static thread_local uint32_t *host_cnt = nullptr;
-    if (!host_cnt && hipHostMalloc(reinterpret_cast<void **>(&host_cnt), 8 * sizeof(uint32_t)) != hipSuccess)
+    static thread_local uint32_t *host_cnt = nullptr;   // two slots of the 8 queue counters
+    if (!host_cnt && hipHostMalloc(reinterpret_cast<void **>(&host_cnt), 16 * sizeof(uint32_t)) != hipSuccess)
         return MC_ERR_DEVICE;
+    struct CountEvents {   // one event per counter slot, on the device of this call
+        hipEvent_t e[2] = {nullptr, nullptr};
+        ~CountEvents() {
+            for (hipEvent_t x : e)
+                if (x) (void)hipEventDestroy(x);
+        }
+    } cev;
+    for (hipEvent_t &x : cev.e)
+        if (hipEventCreateWithFlags(&x, hipEventDisableTiming) != hipSuccess) return MC_ERR_DEVICE;
     // the tail is handed to the finisher at a fixed count (the tuning's pool
     // size / 128, 131072 by default) whatever the run's size: a small run whose
     // pool is small would otherwise spend hundreds of latency-bound
@@ -2223,11 +2232,39 @@ mc_status run_batch(const BatchProblem *pb, int n, void *ws, size_t ws_bytes, hi
     // disc256 gradient 241 -> 173 ms)
     const uint64_t finish_at = B.tt.finish ? B.tt.finish : B.tt.live / 128;
     uint64_t total_todo = 0, total_launched = 0, carried = 0;
+    uint32_t n_rec = 0;   // records in the unsorted queue after the last generation read
     for (int i = 0; i < n; ++i) total_todo += todo[i];
-    for (uint64_t gen = 0;; ++gen) {
+    // one generation: sort the queue by tile, transport, then the queue
+    // counters are copied to host slot `slot` and its event recorded
+    auto enqueue_gen = [&](int slot) -> mc_status {
+        hipLaunchKernelGGL(k_bin_count, dim3(cgrid), dim3(256), 0, s, P0);
+        hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, s, P0);
+        hipLaunchKernelGGL(k_bin_scatter, dim3(bgrid), dim3(256), 0, s, P0);
+        LaunchTimer tm;
+        mc_status r;
+        if ((r = tm.begin(s)) != MC_OK) return r;
+        hipLaunchKernelGGL(fn, dim3(tgrid), dim3(kBlockTile), B.tile_lds, s, P0);
+        if ((r = tm.end(s)) != MC_OK) return r;
+        if (hipGetLastError() != hipSuccess) return MC_ERR_DEVICE;
+        if (hipMemcpyAsync(host_cnt + 8 * slot, P0.qcnt, 8 * sizeof(uint32_t), hipMemcpyDeviceToHost, s) !=
+                hipSuccess ||
+            hipEventRecord(cev.e[slot], s) != hipSuccess)
+            return MC_ERR_DEVICE;
+        return MC_OK;
+    };
+    auto read_gen = [&](int slot) -> mc_status {
+        if (hipEventSynchronize(cev.e[slot]) != hipSuccess) return MC_ERR_DEVICE;
+        const uint32_t *c = host_cnt + 8 * slot;
+        if (c[4]) return MC_ERR_DEVICE;   // queue overflow (not expected by construction)
+        carried = c[6];   // valid records; qa also holds the padding of partly used slices
+        n_rec = (uint32_t)std::min<uint64_t>(c[0], B.cap_a);
+        return MC_OK;
+    };
+    // Refill phase: one generation at a time, each refill sized by the count
+    // the previous generation left.
+    for (uint64_t gen = 0; total_launched < total_todo; ++gen) {
         if (gen > (1ull << 32)) return MC_ERR_DEVICE;
         uint64_t budget = carried < B.live ? B.live - carried : 0;
-        if (carried == 0 && total_launched == total_todo) break;
         for (int i = 0; i < n && budget; ++i) {   // refill the pool, problems in order
             const uint64_t n_new = std::min<uint64_t>(budget, todo[i] - launched[i]);
             if (!n_new) continue;
@@ -2238,40 +2275,49 @@ mc_status run_batch(const BatchProblem *pb, int n, void *ws, size_t ws_bytes, hi
             total_launched += n_new;
             budget -= n_new;
         }
-        hipLaunchKernelGGL(k_bin_count, dim3(cgrid), dim3(256), 0, s, P0);
-        hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, s, P0);
-        hipLaunchKernelGGL(k_bin_scatter, dim3(bgrid), dim3(256), 0, s, P0);
-        LaunchTimer tm;
-        if ((st = tm.begin(s)) != MC_OK) return st;
-        hipLaunchKernelGGL(fn, dim3(tgrid), dim3(kBlockTile), B.tile_lds, s, P0);
-        if ((st = tm.end(s)) != MC_OK) return st;
-        if (hipGetLastError() != hipSuccess) return MC_ERR_DEVICE;
-        if (hipMemcpyAsync(host_cnt, P0.qcnt, 8 * sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess)
-            return MC_ERR_DEVICE;
-        if (host_cnt[4]) return MC_ERR_DEVICE;   // queue overflow (not expected by construction)
-        carried = host_cnt[6];   // valid records; qa also holds the padding of partly used slices
-        if (total_launched == total_todo && carried > 0 && carried <= finish_at) {
-            // finish the remaining packets without migration, one launch per
-            // problem (each takes only its own records; qcnt[5]: record cursor)
-            const uint32_t n_rec = (uint32_t)std::min<uint64_t>(host_cnt[0], B.cap_a);
-            const FinishFn ff = kernels().fin[N];
-            const size_t flds = (size_t)(kBlockFinish / 64) * 64 * (2 * N + 1) * sizeof(float) +
-                                (kBlockFinish / 64) * 64 * sizeof(int);
-            if ((st = set_lds_limit(reinterpret_cast<const void *>(ff), flds)) != MC_OK) return st;
-            const int focc = occupancy_blocks(reinterpret_cast<const void *>(ff), kBlockFinish, flds);
-            const unsigned fgrid = (unsigned)std::max<uint64_t>(
-                1, std::min<uint64_t>((carried + kBlockFinish - 1) / kBlockFinish, (uint64_t)cus * focc));
-            for (int i = 0; i < n; ++i) {
-                if (!todo[i]) continue;
-                if ((st = launch_zero(PP[i].qcnt + 5, sizeof(uint32_t), s)) != MC_OK) return st;
-                LaunchTimer tf;
-                if ((st = tf.begin(s)) != MC_OK) return st;
-                hipLaunchKernelGGL(ff, dim3(fgrid), dim3(kBlockFinish), flds, s, PP[i], n_rec);
-                if ((st = tf.end(s)) != MC_OK) return st;
-                if (hipGetLastError() != hipSuccess) return MC_ERR_DEVICE;
+        if (total_launched == total_todo) break;   // this generation is the drain's first
+        if ((st = enqueue_gen(0)) != MC_OK || (st = read_gen(0)) != MC_OK) return st;
+    }
+    // Drain phase (every packet launched): generations run back to back, the
+    // host reading one generation's counters while the next already runs on
+    // its output, so the device does not wait for the host in between.  Once
+    // at most finish_at packets remain, the generation in flight completes and
+    // the finisher takes what it leaves.
+    if (total_todo > 0) {
+        int inflight = 0, head = 0;   // generations enqueued and not yet read; slot of the oldest
+        for (uint64_t gen = 0;; ++gen) {
+            if (gen > (1ull << 32)) return MC_ERR_DEVICE;
+            while (inflight < 2) {
+                if ((st = enqueue_gen((head + inflight) & 1)) != MC_OK) return st;
+                ++inflight;
             }
-            break;
+            if ((st = read_gen(head)) != MC_OK) return st;
+            head ^= 1;
+            --inflight;
+            if (carried <= finish_at) {
+                if ((st = read_gen(head)) != MC_OK) return st;
+                break;
+            }
+        }
+    }
+    if (carried > 0) {
+        // finish the remaining packets without migration, one launch per
+        // problem (each takes only its own records; qcnt[5]: record cursor)
+        const FinishFn ff = kernels().fin[N];
+        const size_t flds = (size_t)(kBlockFinish / 64) * 64 * (2 * N + 1) * sizeof(float) +
+                            (kBlockFinish / 64) * 64 * sizeof(int);
+        if ((st = set_lds_limit(reinterpret_cast<const void *>(ff), flds)) != MC_OK) return st;
+        const int focc = occupancy_blocks(reinterpret_cast<const void *>(ff), kBlockFinish, flds);
+        const unsigned fgrid = (unsigned)std::max<uint64_t>(
+            1, std::min<uint64_t>((carried + kBlockFinish - 1) / kBlockFinish, (uint64_t)cus * focc));
+        for (int i = 0; i < n; ++i) {
+            if (!todo[i]) continue;
+            if ((st = launch_zero(PP[i].qcnt + 5, sizeof(uint32_t), s)) != MC_OK) return st;
+            LaunchTimer tf;
+            if ((st = tf.begin(s)) != MC_OK) return st;
+            hipLaunchKernelGGL(ff, dim3(fgrid), dim3(kBlockFinish), flds, s, PP[i], n_rec);
+            if ((st = tf.end(s)) != MC_OK) return st;
+            if (hipGetLastError() != hipSuccess) return MC_ERR_DEVICE;
         }
     }
     // normalisation and ledgers
