@@ -283,7 +283,7 @@ mc_status mc_philox_fill(uint64_t seed, uint32_t tag, uint64_t pid0, uint64_t n,
  * mc_workspace_bytes again after a change (live_packets sizes the queues).
  * Results do not depend on these values (bitwise while the FP64 sums are
  * exact, see mc_forward), except flush_track, which moves FP32 partial sums.
- *  live_packets   packets kept alive per generation, 1024 .. 2^26
+ *  live_packets   packets kept alive per generation, 1024 .. 2^26 (default 2^25)
  *  job_packets    packets of one tile handed to one workgroup, 64 .. 2^20
  *                 (a run or batch whose pool holds fewer than 2^23 live
  *                 packets uses half that, to spread over more workgroups)
@@ -293,8 +293,8 @@ mc_status mc_philox_fill(uint64_t seed, uint32_t tag, uint64_t pid0, uint64_t n,
  *                 not fit: the largest square tile that fits two workgroups
  *                 per CU)
  *  finish_packets once every packet is launched and at most this many remain
- *                 they finish without migration (0: live_packets / 128,
- *                 whatever the run's own packet count)
+ *                 they finish without migration (0: the smaller of 2^17
+ *                 and live_packets / 128, whatever the run's own packet count)
  *  grid_max_packets  a run whose tally fits one workgroup's LDS uses the
  *                 whole-grid kernel only up to this many packets, larger runs
  *                 the tiled transport (0: 2^21)

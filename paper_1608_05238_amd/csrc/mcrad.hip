@@ -1701,7 +1701,11 @@ Profile &profile_state() {
 
 // Tiled-mode sizing.  Tiles are square, as large as lets two workgroups of a
 // CU hold their tile's tally, medium and flush counts in LDS.
-constexpr uint64_t kLiveMax = 1ull << 24;     // live packets per generation
+// live packets per generation (2^25 against 2^24: -1.8% time on the 10^8-packet
+// disc256 gradient, the same on small runs once the finisher threshold below
+// is kept at 2^17)
+constexpr uint64_t kLiveMax = 1ull << 25;
+constexpr uint64_t kFinishMax = 1ull << 17;   // default finisher threshold: min(this, live / 128)
 constexpr uint64_t kGridMaxPackets = 1ull << 21;   // larger runs take the tiled transport
 constexpr uint32_t kJobSize = 4096;           // packets per job
 constexpr uint64_t kSmallPool = 1ull << 23;   // pools below this many live packets use half-size jobs
@@ -1719,7 +1723,7 @@ constexpr int kTileWavesMax = 256 * 16;       // bound on resident waves of the 
 struct TileTuning {
     uint64_t live = kLiveMax;
     uint32_t job = kJobSize, maxvis = kMaxVisitsPerStay, tailvis = kTailVisits;
-    uint64_t finish = 0;   // 0: live / 128
+    uint64_t finish = 0;   // 0: min(2^17, live / 128)
     int tile = 0;   // 0: largest square tile for two workgroups per CU
     uint64_t grid_max = kGridMaxPackets;   // whole-grid kernel only up to this many packets
     // a visit whose accumulated track length times |weight| reaches flush_track
@@ -2230,7 +2234,7 @@ mc_status run_batch(const BatchProblem *pb, int n, void *ws, size_t ws_bytes, hi
     // pool is small would otherwise spend hundreds of latency-bound
     // generations on its last few thousand packets (measured: a 1e6-packet
     // disc256 gradient 241 -> 173 ms)
-    const uint64_t finish_at = B.tt.finish ? B.tt.finish : B.tt.live / 128;
+    const uint64_t finish_at = B.tt.finish ? B.tt.finish : std::min<uint64_t>(kFinishMax, B.tt.live / 128);
     uint64_t total_todo = 0, total_launched = 0, carried = 0;
     uint32_t n_rec = 0;   // records in the unsorted queue after the last generation read
     for (int i = 0; i < n; ++i) total_todo += todo[i];

@@ -286,7 +286,8 @@ def test_forward_global_tally_across_chunks():
     O = _oracle()
     ph = P.disc_phantom(96, 0.1, 0.02, 8.0, 0.9, seed=4)
     specs = P.four_side_lines(ph)
-    n = (1 << 24) + 5000
+    live = rmc.mc_get_tuning()["live_packets"]   # the first refill happens at this many packets
+    n = live + 5000
     full, _ = _gpu_run(rmc, ph, specs, n, 16, seed=9)
     B = 8
     parts = []
@@ -301,7 +302,7 @@ def test_forward_global_tally_across_chunks():
                                  "median_gap_over_se": float(np.median(gap / np.maximum(se, 1e-300)))})
     assert np.all(gap <= 0.05 * se + 1e-12 * np.abs(full).max())
     m = 8000
-    first = (1 << 24) - 4000
+    first = live - 4000
     gpu, _ = _gpu_run(rmc, ph, specs, m, 16, seed=9, first=first)
     ora, se = _oracle_batches(O, ph, specs, m, 16, B=8, seed=9, first=first)
     _assert_maps("forward_chunk_edge", gpu, ora, se)
