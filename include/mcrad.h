@@ -283,7 +283,7 @@ mc_status mc_philox_fill(uint64_t seed, uint32_t tag, uint64_t pid0, uint64_t n,
  * mc_workspace_bytes again after a change (live_packets sizes the queues).
  * Results do not depend on these values (bitwise while the FP64 sums are
  * exact, see mc_forward), except flush_track, which moves FP32 partial sums.
- *  live_packets   packets kept alive per generation, 1024 .. 2^26 (default 2^25)
+ *  live_packets   packets kept alive per generation, 1024 .. 2^26 (default 2^26)
  *  job_packets    packets of one tile handed to one workgroup, 64 .. 2^20
  *                 (a run or batch whose pool holds fewer than 2^23 live
  *                 packets uses half that, to spread over more workgroups)

@@ -26,7 +26,7 @@ import torch
 from . import rmc
 
 DEFAULT_CANDIDATES = {
-    "live_packets": (1 << 24, 1 << 25),
+    "live_packets": (1 << 25, 1 << 26),
     "job_packets": (2048, 4096, 8192),
     "max_visits": (32, 64, 128),
     "tail_visits": (4, 8, 16),

@@ -1701,10 +1701,11 @@ Profile &profile_state() {
 
 // Tiled-mode sizing.  Tiles are square, as large as lets two workgroups of a
 // CU hold their tile's tally, medium and flush counts in LDS.
-// live packets per generation (2^25 against 2^24: -1.8% time on the 10^8-packet
-// disc256 gradient, the same on small runs once the finisher threshold below
-// is kept at 2^17)
-constexpr uint64_t kLiveMax = 1ull << 25;
+// live packets per generation (on the 10^8-packet disc256 gradient 2^25
+// against 2^24: -1.8% time, 2^26 against 2^25: -1.1%; small runs unchanged
+// once the finisher threshold below is kept at 2^17).  The queues then take
+// ~13 GB of HBM.
+constexpr uint64_t kLiveMax = 1ull << 26;
 constexpr uint64_t kFinishMax = 1ull << 17;   // default finisher threshold: min(this, live / 128)
 constexpr uint64_t kGridMaxPackets = 1ull << 21;   // larger runs take the tiled transport
 constexpr uint32_t kJobSize = 4096;           // packets per job
