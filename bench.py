@@ -45,12 +45,12 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
 # reads for a plain 1 GiB device copy.  Valid only for the kernel source it
 # was measured on: reported as null once that source changes.
 TRAFFIC = {
-    "source_sha256": "d6e8c2e8ff9dba16f2cff6b1bcdd5c822621e268b283b11a6f7510d11dd8bbc1",
-    "fetch_kib_per_launch": 261294.28, "fetch_factor": 2.000,
-    "write_kib_per_launch": 801148.02, "write_factor": 1.000,
+    "source_sha256": "a5c35f30ae02519b68e9213970c4e8fc4afcffefdac7e93fbe93439d2e97815e",
+    "fetch_kib_per_launch": 273266.81, "fetch_factor": 2.000,
+    "write_kib_per_launch": 836925.70, "write_factor": 1.000,
     # VALU wave-instructions per pixel visit (rocprofv3 SQ_INSTS_VALU over the
     # k_transport_tile<16> and k_finish<16> dispatches of one benchmark step)
-    "valu_per_visit": 13.026,
+    "valu_per_visit": 13.023,
 }
 
 
