@@ -563,22 +563,6 @@ __device__ __forceinline__ void deposit_harmonics(float T, float sx, float sz, f
     }
 }
 
-__device__ __forceinline__ void ledger_flush(const Params &P, LedgerRegs &L) {
-    double v[5] = {L.launched, L.absorbed, L.escaped, L.gain, L.loss};
-    unsigned long long c[4] = {L.packets, L.segments, L.visits, L.scatters};
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-#pragma unroll
-        for (int i = 0; i < 5; ++i) v[i] += __shfl_xor(v[i], off);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) c[i] += __shfl_xor(c[i], off);
-    }
-    if (__lane_id() == 0) {
-        for (int i = 0; i < 5; ++i) atomicAdd(P.led + i, v[i]);
-        for (int i = 0; i < 4; ++i) atomicAdd(P.ledc + i, c[i]);
-    }
-}
-
 // Ledger of a whole workgroup (every thread calls it): wave sums, then one
 // set of device atomics per workgroup.
 __device__ __forceinline__ void ledger_flush_block(double *led, unsigned long long *ledc, LedgerRegs &L) {
