@@ -45,9 +45,9 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
 # reads for a plain 1 GiB device copy.  Valid only for the kernel source it
 # was measured on: reported as null once that source changes.
 TRAFFIC = {
-    "source_sha256": "a5c35f30ae02519b68e9213970c4e8fc4afcffefdac7e93fbe93439d2e97815e",
-    "fetch_kib_per_launch": 273266.81, "fetch_factor": 2.000,
-    "write_kib_per_launch": 836925.70, "write_factor": 1.000,
+    "source_sha256": "acb2c6d744c7990c7892e442ad93cc19e8cc09672bd7207f78f9c803cf6eaf7c",
+    "fetch_kib_per_launch": 272942.70, "fetch_factor": 2.000,
+    "write_kib_per_launch": 835908.56, "write_factor": 1.000,
     # VALU wave-instructions per pixel visit (rocprofv3 SQ_INSTS_VALU over the
     # k_transport_tile<16> and k_finish<16> dispatches of one benchmark step)
     "valu_per_visit": 13.023,
