@@ -9,17 +9,27 @@ with the harmonic tally (Sec. 3, 3.1), adjoint source q* = mua (Hmeas - H)
 (Sec. 5).  Inputs are synthetic and resident in HBM before timing starts.
 
 Besides the throughput the line carries:
-  roofline      the transport kernels' algorithmic tally bytes (272 B per pixel
-                visit) per launch over their average launch time (HIP events on
-                the launch stream), against the 8 TB/s of HBM3E, and the
-                measured HBM traffic per launch (rocprofv3 counters, or null if
-                the kernel source changed since they were taken);
-  lds_roofline  the K LDS tally adds per visit per second against the
-                random-address 64-bit LDS add rate measured in the same run;
-  valu_roofline the transport launches' VALU wave-instructions per second
+  roofline      the transport kernels' algorithmic arithmetic (lane-operations
+                the method itself demands per segment, scatter and launch,
+                ALGO_OPS) per launch over their average launch time (HIP
+                events on the launch stream), against the chip's vector issue
+                rate in lane-operations (157.3 TFLOP/s of packed FP32 FMA =
+                2 flops x 2 lanes per issued lane-operation: 3.93e13 /s);
+  valu_issue    the VALU wave-instructions the compiled kernels actually issue
                 (rocprofv3's count per visit for this kernel source, null once
                 it changes) against one wave64 instruction per SIMD every 4
-                cycles at 2.4 GHz;
+                cycles at 2.4 GHz: how busy the SIMDs are, method or not;
+  lds_atomics   the K LDS tally adds per visit per second against the
+                random-address 64-bit LDS add rate measured in the same run
+                (addresses generated once per 33 adds, as in a tally flush);
+  hbm           the transport launches' measured HBM traffic (rocprofv3
+                FETCH_SIZE + WRITE_SIZE per launch, calibrated; null once the
+                source changes) per average launch time against 8 TB/s;
+  time_to_error the other half of the metric: wall time of one gradient
+                (forward + residual + adjoint + gradient) at the smallest
+                packet count whose gradient errors, averaged over 4 seeds, are
+                within 5% (d eps/d mua) and 20% (d eps/d mus) relative L2 of a
+                1e9 + 1e9-packet reference;
   cpu_baseline  the FP64 oracle on the host's cores (and on one thread) on a
                 bounded sample of the same workload.
 Other modes: --time-to-error, --batch, --pencil32 (one JSON line each).
@@ -53,6 +63,30 @@ TRAFFIC = {
     "valu_per_visit": 13.023,
 }
 
+# Algorithmic arithmetic of the method, in lane-operations (one FMA, compare,
+# logic or integer op, or one transcendental = 1), counted from the steps as
+# the paper states them, independent of how the kernels are written:
+#  per segment (free path through a pixel, Sec. 3; tally, Sec. 3.1, eq.
+#  Fourier_terms): distances to the two pixel faces 4, their minimum 1,
+#  optical depth and the scatter test 2, segment length 1, mua l 1, absorbed
+#  fraction (1 - e^-x)/x 3, deposit T, weight loss and update 4, position 2,
+#  remaining depth 1, pixel step 2, escape test 2; the harmonic tally
+#  a_n += T cos n t, b_n += T sin n t: K = 2N+1 multiply-adds;
+#  per scatter: Philox4x32-10 10 rounds x (2 products, 2 three-way XORs, 2 key
+#  additions) = 60, three uniforms 9, free path -ln u 2, roulette test 2, HG
+#  angle 2 atan(((1-g)/(1+g)) tan(pi (u - 1/2))) 6, new direction 3, harmonic
+#  vector cos n t, sin n t by recurrence 2N;
+#  per launched packet: one Philox block 69, source position and direction 20.
+ALGO_OPS = {"segment_base": 23, "scatter_base": 82, "launch": 89}
+ISSUE_PEAK_LANE_OPS = 157.3e12 / 4.0   # MI355X fp32 vector peak / (2 flops per FMA x 2 packed lanes)
+
+
+def algo_ops(segments, scatters, packets, n_harm):
+    """Lane-operations of the method for the given event counts."""
+    K = 2 * n_harm + 1
+    return ((ALGO_OPS["segment_base"] + K) * segments + (ALGO_OPS["scatter_base"] + 2 * n_harm) * scatters
+            + ALGO_OPS["launch"] * packets)
+
 
 def traffic_bytes_per_launch():
     import hashlib
@@ -79,32 +113,52 @@ def lds_atomic_ceiling(dev) -> float:
     """Lane-operations per second of random-address 64-bit integer LDS adds
     (the tally's atomic) on this device, measured now with the microbenchmark
     kernel in the transport's shape (512-thread workgroups, 64 KiB of LDS
-    each); best of three launches."""
+    each), each lane adding to all 33 slots of a random row (one address per
+    33 adds, the pattern of a tally flush at N = 16); best of four launches."""
     import ctypes as C
     import torch
     from paper_1608_05238_amd import _lib as L
     lib = L.load()
     ncu = torch.cuda.get_device_properties(dev).multi_processor_count
-    nblk, block, iters = ncu * 16, 512, 2048
+    nblk, block, iters = ncu * 16, 512, 128
     sink = torch.empty(nblk, dtype=torch.float64, device=dev)
     stream = C.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
     best = float("inf")
     for _ in range(4):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        L.check("mb_lds_atomics", lib.mb_lds_atomics(L.MB_LDS_ADD_U64, 64 * 1024, block, nblk, iters, 7,
+        L.check("mb_lds_atomics", lib.mb_lds_atomics(L.MB_LDS_ADD_U64_ROW33, 64 * 1024, block, nblk, iters, 7,
                                                      sink.data_ptr(), None, stream))
         e1.record()
         e1.synchronize()
         best = min(best, e0.elapsed_time(e1) * 1e-3)
-    return nblk * block * iters / best
+    return nblk * block * iters * 33 / best
+
+
+def host_cpu() -> dict:
+    """Threads the oracle may use on this host (the OpenMP thread count the
+    environment sets, else every core this process may run on), the cores
+    the OS shows, and the CPU model."""
+    visible = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    threads = min(int(env), visible) if env.isdigit() and int(env) > 0 else visible
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"threads": threads, "cores_visible": visible, "cpu_model": model}
 
 
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(n_packets: int, threads: int) -> dict:
+def cpu_baseline(n_packets: int, threads: int, host: dict) -> dict:
     """The FP64 oracle on a bounded sample of the same workload: forward,
     residual, adjoint and gradient with n_packets each, timed on host cores."""
     import numpy as np
@@ -123,8 +177,8 @@ def cpu_baseline(n_packets: int, threads: int) -> dict:
                      n_threads=threads)
     O.gradient(om, 16, fo, ao, hm)
     dt = time.perf_counter() - t0
-    # one host thread on a tenth of the sample: the oracle's single-core rate
-    n1 = max(1, n_packets // 10)
+    # one host thread on a twentieth of the sample: the oracle's single-core rate
+    n1 = max(1, n_packets // 20)
     t1 = time.perf_counter()
     fo1, _ = O.run_mc(om, O.sources_from(c.sources), O.Run(n1, 0, 16), n_threads=1)
     _, q1 = O.residual(om, fo1, hm)
@@ -134,18 +188,23 @@ def cpu_baseline(n_packets: int, threads: int) -> dict:
     return {"value": 2 * n_packets / dt, "unit": "packets/s", "cores": threads, "kind": "oracle",
             "sample": f"disc256 forward+adjoint+gradient, {n_packets}+{n_packets} packets, N=16, FP64, "
                       f"{dt:.1f} s",
+            "cpu_model": host["cpu_model"], "cores_visible": host["cores_visible"],
             "single_thread": {"value": 2 * n1 / dt1, "unit": "packets/s", "cores": 1,
                               "sample": f"{n1}+{n1} packets, {dt1:.1f} s"}}
 
 
-def time_to_error(args) -> dict:
+def time_to_error(args, seeds: int = 4) -> dict:
     """Second half of the headline metric: wall time of one gradient evaluation
     (forward + residual + adjoint + gradient, N = 16) at the smallest packet
-    count (doubling from 1e6, then three geometric bisection steps) whose
-    gradients are within 5% (d eps/d mua) and 20% (d eps/d mus) relative L2
-    error of a reference gradient from
-    args.ref_packets + args.ref_packets packets, over pixels at least 10
-    pixels from the boundary."""
+    count whose gradients, with their relative L2 errors averaged over `seeds`
+    independent seeds, are within 5% (d eps/d mua) and 20% (d eps/d mus) of a
+    reference gradient from args.ref_packets + args.ref_packets packets, over
+    pixels at least 10 pixels from the boundary.  Search: doubling from
+    5e5 packets until the mean errors meet both targets, then three geometric
+    bisection steps between the last count that missed and the first that met
+    them.  The reported time is the mean wall time of one gradient at that
+    count (each timed alone, bracketed by device synchronisations)."""
+    import numpy as np
     import torch
     import phantoms as P
     from paper_1608_05238_amd import rmc
@@ -164,46 +223,56 @@ def time_to_error(args) -> dict:
                               ledger=False)
         return rmc.mc_gradient(med, N, f, a, hmeas)
 
-    log(f"reference gradient: {args.ref_packets:.0e} + {args.ref_packets:.0e} packets")
+    log(f"time to error: reference gradient from {args.ref_packets:.0e} + {args.ref_packets:.0e} packets")
+    t0 = time.perf_counter()
     ra, rs = gradient(int(args.ref_packets), 100)
+    torch.cuda.synchronize()
+    log(f"reference: {time.perf_counter() - t0:.1f} s")
     m = 10
     ra, rs = ra[m:-m, m:-m], rs[m:-m, m:-m]
-    rows = []
+    rows = {}
 
     def evaluate(n):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ga, gs = gradient(n, 7)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        ea = float((ga[m:-m, m:-m] - ra).norm() / ra.norm())
-        es = float((gs[m:-m, m:-m] - rs).norm() / rs.norm())
-        rows.append({"packets": n, "wall_ms": wall * 1e3, "err_dmua": ea, "err_dmus": es})
-        log(f"{n:.2e} packets: {wall * 1e3:.1f} ms, error dmua {ea:.4f}, dmus {es:.4f}")
-        return ea <= 0.05 and es <= 0.20
+        ea, es, walls = [], [], []
+        for k in range(seeds):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ga, gs = gradient(n, 7 + 1000 * k)
+            torch.cuda.synchronize()
+            walls.append((time.perf_counter() - t0) * 1e3)
+            ea.append(float((ga[m:-m, m:-m] - ra).norm() / ra.norm()))
+            es.append(float((gs[m:-m, m:-m] - rs).norm() / rs.norm()))
+        se = lambda v: float(np.std(v, ddof=1) / np.sqrt(len(v)))
+        r = {"packets": n, "wall_ms": float(np.mean(walls)), "wall_ms_min": float(np.min(walls)),
+             "err_dmua": float(np.mean(ea)), "err_dmua_se": se(ea),
+             "err_dmus": float(np.mean(es)), "err_dmus_se": se(es)}
+        rows[n] = r
+        log(f"{n:.3e} packets: {r['wall_ms']:.1f} ms, error dmua {r['err_dmua']:.4f} +- {r['err_dmua_se']:.4f}, "
+            f"dmus {r['err_dmus']:.4f} +- {r['err_dmus_se']:.4f}")
+        return r["err_dmua"] <= 0.05 and r["err_dmus"] <= 0.20
 
-    # doubling from 1e6 packets, then three geometric bisection steps between
-    # the last count that missed the targets and the first that met them
-    n, lo = 1_000_000, None
-    while not evaluate(n) and n < args.ref_packets // 4:
+    n, lo = 500_000, None
+    while not evaluate(n) and n < args.ref_packets // 8:
         lo, n = n, 2 * n
     hi = n
-    if lo is not None and rows[-1]["err_dmua"] <= 0.05 and rows[-1]["err_dmus"] <= 0.20:
+    ok = rows[hi]["err_dmua"] <= 0.05 and rows[hi]["err_dmus"] <= 0.20
+    if ok and lo is not None:
         for _ in range(3):
             mid = int(round(math.sqrt(lo * hi) / 1e4)) * 10_000
+            if mid in rows or mid <= lo or mid >= hi:
+                break
             if evaluate(mid):
                 hi = mid
             else:
                 lo = mid
-    hit = next(r for r in rows if r["packets"] == hi)
-    ok = hit["err_dmua"] <= 0.05 and hit["err_dmus"] <= 0.20
-    return {"metric": "wall time to gradient at fixed rel. error (5% d eps/d mua, 20% d eps/d mus)",
-            "value": hit["wall_ms"] if ok else None, "unit": "ms", "higher_is_better": False, "n_gpus": 1,
-            "packets_forward": hit["packets"], "packets_adjoint": hit["packets"], "reached": ok,
-            "reference_packets": int(args.ref_packets), "dtype": "f32", "data": "synthetic",
-            "config": {"workload": "disc256: forward + residual + adjoint + gradient, N = 16, interior pixels "
-                                   "(10-pixel margin)"},
-            "sweep": rows}
+    hit = rows[hi]
+    return {"value": hit["wall_ms"] if ok else None, "unit": "ms", "higher_is_better": False, "reached": ok,
+            "packets_forward": hi, "packets_adjoint": hi,
+            "err_dmua": hit["err_dmua"], "err_dmua_se": hit["err_dmua_se"],
+            "err_dmus": hit["err_dmus"], "err_dmus_se": hit["err_dmus_se"],
+            "targets": {"dmua": 0.05, "dmus": 0.20}, "seeds": seeds, "reference_packets": int(args.ref_packets),
+            "pixels": "interior, 10-pixel margin",
+            "sweep": [rows[k] for k in sorted(rows)]}
 
 
 def single_gradient(args) -> dict:
@@ -223,11 +292,13 @@ def single_gradient(args) -> dict:
     ht, _ = rmc.mc_forward(tmed, c.sources, rmc.make_run(int(args.hmeas_packets), N, seed=1), ledger=False)
     hmeas = rmc.mc_absorbed(tmed, ht)
 
+    gens = []
+
     def gradient():
-        f, _ = rmc.mc_forward(med, c.sources, rmc.make_run(n, N, seed=7), ledger=False)
+        f, lf = rmc.mc_forward(med, c.sources, rmc.make_run(n, N, seed=7))
         q, _ = rmc.mc_residual(med, f, hmeas)
-        a, _ = rmc.mc_adjoint(med, [rmc.Source("map", map=q)], rmc.make_run(n, N, seed=7, stream_tag=1),
-                              ledger=False)
+        a, la = rmc.mc_adjoint(med, [rmc.Source("map", map=q)], rmc.make_run(n, N, seed=7, stream_tag=1))
+        gens.append((lf, la))
         return rmc.mc_gradient(med, N, f, a, hmeas)
 
     walls = []
@@ -239,10 +310,11 @@ def single_gradient(args) -> dict:
         if i >= args.warmup:
             walls.append((time.perf_counter() - t0) * 1e3)
         log(f"gradient at {n:.3g} packets: {(time.perf_counter() - t0) * 1e3:.1f} ms")
+    g_used = [[rmc.ledger_dict(x)["generations"] for x in pair] for pair in gens]
     return {"metric": "wall time of one gradient (forward + residual + adjoint + gradient, N=16)",
             "value": min(walls), "unit": "ms", "higher_is_better": False, "n_gpus": 1,
-            "packets_forward": n, "packets_adjoint": n, "walls_ms": walls, "dtype": "f32", "data": "synthetic",
-            "config": {"workload": "disc256 gradient"}}
+            "packets_forward": n, "packets_adjoint": n, "walls_ms": walls, "generations_fwd_adj": g_used,
+            "dtype": "f32", "data": "synthetic", "config": {"workload": "disc256 gradient"}}
 
 
 def batch_workload(args) -> dict:
@@ -328,7 +400,7 @@ def pencil32(args) -> dict:
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         L = rmc.ledger_dict(led)
-        whole = 32 * 32 * (2 * N + 1) * 8 <= 144 * 1024 and n <= rmc.mc_get_tuning()["grid_max_packets"]
+        whole = 32 * 32 * (2 * N + 1) * 8 <= 144 * 1024 and n <= rmc.default_tuning()["grid_max_packets"]
         res[f"N{N}"] = {"packets_per_s": n / dt, "ms": dt * 1e3, "visits_per_packet": L["visits"] / n,
                         "mode": "whole-grid LDS tally" if whole else "tiled"}
         log(f"pencil32 N={N}: {n / dt:.3e} packets/s")
@@ -338,12 +410,14 @@ def pencil32(args) -> dict:
                       "packets": n}, "runs": res}
     if args.cpu_packets > 0:   # the oracle on the configuration's own 1e5 packets, N = 8
         import oracle as O
-        threads = min(16, os.cpu_count() or 1)
+        host = host_cpu()
+        threads = host["threads"]
         t0 = time.perf_counter()
         O.run_mc(O.medium_from(c.phantom), O.sources_from(c.sources), O.Run(100_000, 0, 8), n_threads=threads)
         dt = time.perf_counter() - t0
         out["cpu_baseline"] = {"value": 1e5 / dt, "unit": "packets/s", "cores": threads, "kind": "oracle",
-                               "sample": f"pencil32 forward, 100000 packets, N=8, FP64, {dt:.2f} s"}
+                               "sample": f"pencil32 forward, 100000 packets, N=8, FP64, {dt:.2f} s",
+                               "cpu_model": host["cpu_model"], "cores_visible": host["cores_visible"]}
     return out
 
 
@@ -353,12 +427,15 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--packets", type=float, default=1e8, help="packets per MC run (forward and adjoint each)")
-    ap.add_argument("--cpu-packets", type=int, default=60_000, help="oracle sample size (0: skip)")
+    ap.add_argument("--cpu-packets", type=int, default=250_000, help="oracle sample size (0: skip)")
     ap.add_argument("--hmeas-packets", type=float, default=2e7)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this size first (calibrates HBM counters)")
     ap.add_argument("--time-to-error", action="store_true",
-                    help="instead of the throughput line, measure the wall time to a gradient of fixed error")
+                    help="instead of the throughput line, measure only the wall time to a gradient of fixed error")
+    ap.add_argument("--no-time-to-error", action="store_true",
+                    help="leave the time-to-error measurement out of the throughput line")
+    ap.add_argument("--tte-seeds", type=int, default=4, help="seeds averaged per packet count in time to error")
     ap.add_argument("--ref-packets", type=float, default=1e9, help="packets of the reference gradient (each run)")
     ap.add_argument("--gradient", type=float, default=0,
                     help="time single gradients (forward + residual + adjoint + gradient) at this many packets "
@@ -384,7 +461,11 @@ def main() -> int:
 
     torch.cuda.set_device(0)
     if args.time_to_error:
-        print(json.dumps(time_to_error(args)), flush=True)
+        out = {"metric": "wall time to gradient at fixed rel. error (5% d eps/d mua, 20% d eps/d mus)",
+               "n_gpus": 1, "dtype": "f32", "data": "synthetic",
+               "config": {"workload": "disc256: forward + residual + adjoint + gradient, N = 16"}}
+        out.update(time_to_error(args, args.tte_seeds))
+        print(json.dumps(out), flush=True)
         return 0
     if args.batch:
         print(json.dumps(batch_workload(args)), flush=True)
@@ -413,19 +494,25 @@ def main() -> int:
     tmed = rmc.Medium.from_phantom(true, dev)
     ht, _ = rmc.mc_forward(tmed, c.sources, rmc.make_run(int(args.hmeas_packets), N, seed=1), ledger=False)
     hmeas = (tmed.mua.double() * ht[0]).contiguous()
-    ws_f = torch.empty(rmc.mc_workspace_bytes(med, c.sources, rmc.make_run(Np, N)) + 256, dtype=torch.uint8,
+    # one workspace for both runs (the adjoint's map source adds its CDF)
+    need = max(rmc.mc_workspace_bytes(med, c.sources, rmc.make_run(Np, N)),
+               rmc.mc_workspace_bytes(med, [P.SourceSpec("map", map=torch.zeros_like(hmeas))],
+                                      rmc.make_run(Np, N, stream_tag=1)))
+    ws_f = torch.empty(need + 256, dtype=torch.uint8,
                        device=dev)
     fwd = torch.empty((K, ph.nz, ph.nx), dtype=torch.float64, device=dev)
     adj = torch.empty_like(fwd)
     torch.cuda.synchronize()
 
     ledgers = []
+    timer = rmc.Timer()
 
     def step(i: int, keep: bool):
-        f, lf = rmc.mc_forward(med, c.sources, rmc.make_run(Np, N, seed=100 + i), out=fwd, workspace=ws_f)
+        tm = timer if keep else None
+        f, lf = rmc.mc_forward(med, c.sources, rmc.make_run(Np, N, seed=100 + i), out=fwd, workspace=ws_f, timer=tm)
         q, eps = rmc.mc_residual(med, f, hmeas)
         a, la = rmc.mc_adjoint(med, [P.SourceSpec("map", map=q)], rmc.make_run(Np, N, seed=100 + i, stream_tag=1),
-                               out=adj)
+                               out=adj, workspace=ws_f, timer=tm)
         g = rmc.mc_gradient(med, N, f, a, hmeas)
         if keep:
             ledgers.append((lf, la))
@@ -435,8 +522,6 @@ def main() -> int:
         log(f"warmup step {i}")
         step(i, False)
     torch.cuda.synchronize()
-    rmc.mc_profile_read(reset=True)
-    rmc.mc_profile_enable(True)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     e0.record()
@@ -445,24 +530,27 @@ def main() -> int:
     e1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    rmc.mc_profile_enable(False)
-    tr_ms, tr_launches = rmc.mc_profile_read(reset=True)
+    tr_ms, tr_launches = timer.read(reset=True)
     ms_total = e0.elapsed_time(e1)
     ms_step = ms_total / args.steps
     log(f"timed {args.steps} steps: {ms_step:.1f} ms/step (wall {wall:.2f} s)")
 
-    visits = segments = scatters = 0
+    visits = segments = scatters = packets = 0
+    gens = []
     for lf, la in ledgers:
         for l in (rmc.ledger_dict(lf), rmc.ledger_dict(la)):
             visits += l["visits"]
             segments += l["segments"]
             scatters += l["scatters"]
-    # algorithmic bytes per pixel visit: the K-channel FP64 tally update the
-    # method accumulates plus the two medium coefficients of the pixel
-    bytes_per_visit = K * 8 + 8
+            packets += l["packets"]
+            gens.append(l["generations"])
     avg_launch_ms = tr_ms / max(tr_launches, 1)
-    achieved = visits * bytes_per_visit / tr_launches / (avg_launch_ms * 1e-3) / 1e9 if tr_launches else 0.0
+    per_launch = lambda v: v / max(tr_launches, 1)
+    launch_s = avg_launch_ms * 1e-3
+    ops = algo_ops(segments, scatters, packets, N)
+    achieved = per_launch(ops) / launch_s if tr_launches else 0.0
     value = 2 * Np * args.steps / (ms_total * 1e-3)
+    kern = "k_transport_tile<16> + k_finish<16>"
     out = {
         "metric": "packets/s fwd+adj MC (N=16 harmonics)",
         "value": value,
@@ -480,39 +568,54 @@ def main() -> int:
                                "forward + adjoint + gradient",
                    "packets_forward": Np, "packets_adjoint": Np, "n_harm": N,
                    "tally": "64-bit fixed-point LDS tiles, FP64 map, packet migration"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_bytes_per_launch(),
-                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
-                     "kernel": "k_transport_tile<16> + k_finish<16>", "avg_launch_ms": avg_launch_ms,
-                     "launches": tr_launches, "algorithmic_bytes_per_launch": visits * bytes_per_visit / max(tr_launches, 1),
-                     "bytes_per_visit": bytes_per_visit,
+        # the method's arithmetic against the vector issue rate of the chip
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": ISSUE_PEAK_LANE_OPS, "unit": "lane-ops/s",
+                     "frac": achieved / ISSUE_PEAK_LANE_OPS, "traffic": None, "kernel": kern,
+                     "avg_launch_ms": avg_launch_ms, "launches": tr_launches,
+                     "algorithmic_ops_per_launch": per_launch(ops), "ops_per_visit": ops / max(visits, 1),
+                     "ops_per_segment": ALGO_OPS["segment_base"] + K, "ops_per_scatter": ALGO_OPS["scatter_base"] + 2 * N,
+                     "ops_per_launched_packet": ALGO_OPS["launch"],
+                     "peak_source": "157.3 TFLOP/s fp32 vector / (2 flops per FMA x 2 packed lanes)",
                      "visits_per_packet": visits / (2 * Np * args.steps),
                      "segments_per_packet": segments / (2 * Np * args.steps),
                      "scatters_per_packet": scatters / (2 * Np * args.steps),
+                     "generations_per_run": gens,
                      "transport_share_of_step": tr_ms / ms_total},
     }
+    # HBM: measured traffic of a transport launch (counters of this source) over its time
+    tb = traffic_bytes_per_launch()
+    out["roofline"]["traffic"] = tb
+    out["hbm"] = {"bound": "hbm", "achieved": tb / launch_s / 1e9 if (tb and tr_launches) else None,
+                  "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                  "frac": tb / launch_s / 1e9 / HBM_PEAK_GBS if (tb and tr_launches) else None,
+                  "traffic": tb, "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
+                  "tally_update_bytes_per_launch": per_launch(visits) * (K * 8 + 8), "kernel": kern}
     # the tally's own ceiling: K LDS atomic adds per visit against the device's
     # random-address 64-bit LDS add rate, measured in this run
     ceiling = lds_atomic_ceiling(dev)
-    lane_ops = visits * K / max(tr_launches, 1) / (avg_launch_ms * 1e-3) if tr_launches else 0.0
-    out["lds_roofline"] = {"bound": "lds_atomics", "achieved": lane_ops, "peak": ceiling, "unit": "lane-ops/s",
-                           "frac": lane_ops / ceiling, "kernel": "k_transport_tile<16> + k_finish<16>",
-                           "peak_source": "ds_add_u64 at random LDS addresses, mb_lds_atomics, this run"}
-    # the issue ceiling the loop actually meets: VALU wave-instructions (counted
-    # once per source by rocprofv3) per launch over the live launch time, against
-    # one wave64 VALU instruction per SIMD every 4 cycles at the 2.4 GHz peak clock
+    lane_ops = per_launch(visits) * K / launch_s if tr_launches else 0.0
+    out["lds_atomics"] = {"bound": "lds", "achieved": lane_ops, "peak": ceiling, "unit": "lane-ops/s",
+                          "frac": lane_ops / ceiling, "kernel": kern,
+                          "peak_source": "ds_add_u64 to all 33 slots of a random row, mb_lds_atomics, this run"}
+    # issue: VALU wave-instructions (counted once per source by rocprofv3) per
+    # launch over the live launch time, against one wave64 VALU instruction per
+    # SIMD every 4 cycles at the 2.4 GHz peak clock
     vpv = valu_per_visit()
     ncu = torch.cuda.get_device_properties(dev).multi_processor_count
     vpeak = ncu * 4 * 2.4e9 / 4
-    vach = vpv * visits / max(tr_launches, 1) / (avg_launch_ms * 1e-3) if (vpv and tr_launches) else None
-    out["valu_roofline"] = {"bound": "alu", "achieved": vach, "peak": vpeak, "unit": "wave64 VALU instructions/s",
-                            "frac": vach / vpeak if vach else None, "valu_per_visit": vpv,
-                            "kernel": "k_transport_tile<16> + k_finish<16>",
-                            "peak_source": f"{ncu} CUs x 4 SIMDs x 2.4 GHz / 4 cycles per wave64 instruction"}
+    vach = vpv * per_launch(visits) / launch_s if (vpv and tr_launches) else None
+    out["valu_issue"] = {"bound": "alu", "achieved": vach, "peak": vpeak, "unit": "wave64 VALU instructions/s",
+                         "frac": vach / vpeak if vach else None, "valu_per_visit": vpv,
+                         "method_share": (ops / max(visits, 1)) / (64 * vpv) if vpv else None, "kernel": kern,
+                         "peak_source": f"{ncu} CUs x 4 SIMDs x 2.4 GHz / 4 cycles per wave64 instruction"}
+    if not args.no_time_to_error:
+        out["time_to_error"] = time_to_error(args, args.tte_seeds)
     if args.cpu_packets > 0:
-        threads = min(16, os.cpu_count() or 1)
-        log(f"cpu baseline: oracle with {args.cpu_packets}+{args.cpu_packets} packets on {threads} threads")
-        out["cpu_baseline"] = cpu_baseline(args.cpu_packets, threads)
+        host = host_cpu()
+        threads = host["threads"]
+        log(f"cpu baseline: oracle with {args.cpu_packets}+{args.cpu_packets} packets on {threads} threads "
+            f"({host['cpu_model']})")
+        out["cpu_baseline"] = cpu_baseline(args.cpu_packets, threads, host)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -12,13 +12,20 @@
  *  - Every array argument whose name ends in _d is a DEVICE pointer owned by
  *    the caller; the library never allocates, frees or keeps it.  Host
  *    pointers end in _h.
- *  - Calls that take a stream only enqueue work on that stream and return;
- *    results are valid after the caller synchronises the stream.  Calls on
- *    different streams with different workspaces may run concurrently.
+ *  - Calls that take a stream only enqueue work on that stream and return:
+ *    none of them waits for the device, allocates device memory or keeps
+ *    state between calls (mc_trace, which is synchronous, is the one
+ *    exception and says so).  Results are valid after the caller
+ *    synchronises the stream.  Calls on different streams with different
+ *    workspaces may run concurrently.  The library holds no mutable global
+ *    state: tuning and timing are passed per call (mc_options).
  *  - Return value: MC_OK, or an error code; no call throws.  Invalid
  *    arguments are detected on the host before anything is enqueued.
  *    MC_ERR_DEVICE reports a failed launch; faults inside a kernel surface at
- *    the caller's next synchronisation.
+ *    the caller's next synchronisation.  What only the device can see -- a
+ *    NaN in a source map, a weight bound above 2^32 that only the map's
+ *    values reveal, a packet queue that overflowed (not reachable by
+ *    construction) -- turns the whole output of the run into NaN.
  *  - Maps are row-major [nz][nx]: x (lateral) is the column, z (depth) the
  *    row.  Pixel (ix,iz) covers [ix dx,(ix+1) dx) x [iz dx,(iz+1) dx).
  *  - Harmonic coefficient maps are planar [2N+1][nz][nx] FP64 in the order
@@ -112,16 +119,84 @@ typedef struct {
 /* Energy ledger of one run (device struct written by mc_forward/mc_adjoint).
  * Weight sums are raw packet-weight sums; multiply by `scale` (total source
  * measure / n_packets) for power.  launched + roulette_gain - roulette_loss
- * equals absorbed + escaped up to FP32 rounding. */
+ * equals absorbed + escaped up to FP32 rounding.  generations: tiled
+ * transport generations the run used before its tail went to the finisher
+ * (0 for the whole-grid transport). */
 typedef struct {
     double launched, absorbed, escaped, roulette_gain, roulette_loss;
     double scale;
-    uint64_t packets, segments, visits, scatters;
+    uint64_t packets, segments, visits, scatters, generations;
 } mc_ledger;
 
+/* Tuning of the tiled transport (grids whose tally exceeds one workgroup's
+ * LDS).  Results do not depend on these values (bitwise while the FP64 sums
+ * are exact, see mc_forward), except flush_track, which moves FP32 partial
+ * sums.  A zero field takes its default (mc_default_tuning).
+ *  live_packets   packets kept alive per generation, 1024 .. 2^26 (default 2^26)
+ *  job_packets    packets of one tile handed to one workgroup, 64 .. 2^20
+ *                 (a run or batch whose pool holds fewer than 2^23 live
+ *                 packets uses half that, to spread over more workgroups;
+ *                 default 4096)
+ *  max_visits     visits in one tile before a packet pauses until the next
+ *                 generation, >= 1 (default 64)
+ *  tile           tile side in pixels, 1 .. 256 (default, or a tile whose
+ *                 tally does not fit: the largest square tile that fits two
+ *                 workgroups per CU)
+ *  finish_packets once every packet is launched and at most this many remain
+ *                 they finish without migration (default: the smaller of
+ *                 2^17 and live_packets / 128)
+ *  grid_max_packets  a run whose tally fits one workgroup's LDS uses the
+ *                 whole-grid kernel only up to this many packets, larger runs
+ *                 the tiled transport (default 2^21)
+ *  flush_track    a pixel visit whose accumulated track length, in units of
+ *                 the run's weight bound, exceeds this many pixels is added
+ *                 to the tile tally in parts, 0 .. 65536 (default 65536)
+ *  tail_visits    once a job has handed out its last packet, its packets
+ *                 pause after this many more visits, 0 .. 2^30 (default 8)
+ *  max_generations  tiled generations enqueued per call, 1 .. 65536
+ *                 (default 0: 448 + 48 per pool of live_packets the run's
+ *                 packets fill).  The host enqueues this many without
+ *                 waiting; a generation that finds the finisher threshold
+ *                 reached does nothing.  Packets still in flight (or not yet
+ *                 launched) after the last one are moved to their end by the
+ *                 finisher, so the results never depend on it. */
+typedef struct {
+    uint64_t live_packets;
+    uint32_t job_packets;
+    uint32_t max_visits;
+    uint32_t tile;
+    uint32_t grid_max_packets;
+    uint64_t finish_packets;
+    float flush_track;
+    uint32_t tail_visits;
+    uint32_t max_generations;
+} mc_tuning;
+
+/* The built-in defaults, every field filled in. */
+mc_status mc_default_tuning(mc_tuning *tuning_h);
+
+/* Timing of transport kernel launches, owned by the caller: a run given a
+ * timer brackets each of its transport launches with two HIP events recorded
+ * on its stream.  mc_timer_read waits for the recorded events, adds their
+ * elapsed times to the timer's total and returns the total (ms) and the
+ * number of launches since the last reset.  A timer may serve several calls
+ * in turn; it is not shared with anything else. */
+typedef struct mc_timer mc_timer;
+mc_status mc_timer_create(mc_timer **timer_h);
+mc_status mc_timer_destroy(mc_timer *timer);
+mc_status mc_timer_read(mc_timer *timer, double *transport_ms, uint64_t *launches, int reset);
+
+/* Per-call options: either pointer may be NULL (defaults, no timing); opts
+ * itself may be NULL. */
+typedef struct {
+    const mc_tuning *tuning;
+    mc_timer *timer;
+} mc_options;
+
 /* Bytes of device workspace a forward/adjoint run needs (tallies, packet
- * counter, source tables).  0 on invalid arguments. */
-size_t mc_workspace_bytes(const mc_medium *medium, const mc_source *src, int n_src, const mc_run *run);
+ * queues, source tables).  0 on invalid arguments. */
+size_t mc_workspace_bytes(const mc_medium *medium, const mc_source *src, int n_src, const mc_run *run,
+                          const mc_options *opts);
 
 /* Forward radiance MC (Sec. 3, 3.1): launch, exponential free paths through
  * the pixels, continuous absorption weighting, roulette, 2D Henyey-Greenstein
@@ -144,8 +219,8 @@ size_t mc_workspace_bytes(const mc_medium *medium, const mc_source *src, int n_s
  * range (not reachable with physical media and the default tuning), the
  * whole output of the run is NaN rather than wrong. */
 mc_status mc_forward(const mc_medium *medium, const mc_source *src, int n_src, const mc_run *run,
-                     double *coeffs_d, mc_ledger *ledger_d, void *workspace_d, size_t workspace_bytes,
-                     void *stream);
+                     const mc_options *opts, double *coeffs_d, mc_ledger *ledger_d, void *workspace_d,
+                     size_t workspace_bytes, void *stream);
 
 /* Adjoint radiance MC (Sec. 4, eq. adjoint_RTE1; Sec. 6): solves the adjoint
  * RTE with source `src` (typically one MAP source q* from mc_residual).  The
@@ -154,8 +229,8 @@ mc_status mc_forward(const mc_medium *medium, const mc_source *src, int n_src, c
  * are mirrored on input and the output orders n >= 1 are multiplied by
  * (-1)^n, so coeffs_d holds the adjoint radiance phi*(x, s) itself. */
 mc_status mc_adjoint(const mc_medium *medium, const mc_source *src, int n_src, const mc_run *run,
-                     double *coeffs_d, mc_ledger *ledger_d, void *workspace_d, size_t workspace_bytes,
-                     void *stream);
+                     const mc_options *opts, double *coeffs_d, mc_ledger *ledger_d, void *workspace_d,
+                     size_t workspace_bytes, void *stream);
 
 /* One problem of a batch: a forward (adjoint = 0, as mc_forward) or adjoint
  * (adjoint = 1, as mc_adjoint) run with its own medium, sources, packet
@@ -175,7 +250,7 @@ typedef struct {
 #define MC_BATCH_MAX 4096
 
 /* Workspace bytes of mc_run_batch (0 on invalid arguments). */
-size_t mc_batch_workspace_bytes(const mc_problem *probs_h, int n_probs);
+size_t mc_batch_workspace_bytes(const mc_problem *probs_h, int n_probs, const mc_options *opts);
 
 /* Many problems (sources, wavelengths, grid sizes) in one packet pool: the
  * tiled transport's generations launch packets of every problem, sort all of
@@ -184,8 +259,8 @@ size_t mc_batch_workspace_bytes(const mc_problem *probs_h, int n_probs);
  * LDS.  Every problem's output equals what mc_forward / mc_adjoint gives for
  * it alone (the same packets and visit values; bitwise while the FP64 sums
  * are exact, see mc_forward).  probs_h: host array of n_probs (1 .. MC_BATCH_MAX) problems. */
-mc_status mc_run_batch(const mc_problem *probs_h, int n_probs, void *workspace_d, size_t workspace_bytes,
-                       void *stream);
+mc_status mc_run_batch(const mc_problem *probs_h, int n_probs, const mc_options *opts, void *workspace_d,
+                       size_t workspace_bytes, void *stream);
 
 /* Residual (Sec. 2 eq. error_function3, Sec. 6): H = mua a0 (Grueneisen 1),
  * r = hmeas - H, q* = mua r (per unit angle), eps = (dx^2 / 2) sum r^2.
@@ -276,55 +351,6 @@ mc_status mc_trace(const mc_medium *medium, const mc_source *src, int n_src, con
  * out_d[4i..4i+3] (device uint32).  Exposes the generator for checking. */
 mc_status mc_philox_fill(uint64_t seed, uint32_t tag, uint64_t pid0, uint64_t n, uint32_t j,
                          uint32_t *out_d, void *stream);
-
-/* Tuning of the tiled transport (grids whose tally exceeds one
- * workgroup's LDS).  Process-wide; a run uses the values current when its
- * layout is computed (mc_workspace_bytes, mc_forward, mc_adjoint), so call
- * mc_workspace_bytes again after a change (live_packets sizes the queues).
- * Results do not depend on these values (bitwise while the FP64 sums are
- * exact, see mc_forward), except flush_track, which moves FP32 partial sums.
- *  live_packets   packets kept alive per generation, 1024 .. 2^26 (default 2^26)
- *  job_packets    packets of one tile handed to one workgroup, 64 .. 2^20
- *                 (a run or batch whose pool holds fewer than 2^23 live
- *                 packets uses half that, to spread over more workgroups)
- *  max_visits     visits in one tile before a packet pauses until the next
- *                 generation, >= 1
- *  tile           tile side in pixels, 0 .. 256 (0, or a tile whose tally does
- *                 not fit: the largest square tile that fits two workgroups
- *                 per CU)
- *  finish_packets once every packet is launched and at most this many remain
- *                 they finish without migration (0: the smaller of 2^17
- *                 and live_packets / 128, whatever the run's own packet count)
- *  grid_max_packets  a run whose tally fits one workgroup's LDS uses the
- *                 whole-grid kernel only up to this many packets, larger runs
- *                 the tiled transport (0: 2^21)
- *  flush_track    a pixel visit whose accumulated track length, in units of
- *                 the run's weight bound, exceeds this many pixels is added
- *                 to the tile tally in parts, 0 .. 65536 (0: 65536)
- *  tail_visits    once a job has handed out its last packet, its packets
- *                 pause after this many more visits, 0 .. 2^30 (0: 8)
- * mc_set_tuning(NULL) restores the built-in defaults. */
-typedef struct {
-    uint64_t live_packets;
-    uint32_t job_packets;
-    uint32_t max_visits;
-    uint32_t tile;
-    uint32_t grid_max_packets;
-    uint64_t finish_packets;
-    float flush_track;
-    uint32_t tail_visits;
-} mc_tuning;
-mc_status mc_set_tuning(const mc_tuning *tuning_h);
-mc_status mc_get_tuning(mc_tuning *tuning_h);
-
-/* Timing of the transport kernel launches: when enabled, every transport
- * launch made by mc_forward / mc_adjoint is bracketed by two HIP events
- * recorded on the caller's stream.  mc_profile_read waits for the pending
- * events, adds their elapsed times to a running total and returns the total
- * time (ms) and the number of launches since the last reset.  Host-side
- * bookkeeping only; thread-safe. */
-void mc_profile_enable(int on);
-mc_status mc_profile_read(double *transport_ms, uint64_t *launches, int reset);
 
 const char *mc_status_string(mc_status s);
 /* Library build identifier (architecture and tally configuration). */

@@ -32,17 +32,22 @@ typedef enum {
     MB_LDS_ADD_F32 = 1,      /* one FP32 add (ds_add_f32) per lane at a random 4-byte slot */
     MB_LDS_ADD_U64 = 2,      /* one 64-bit integer add (ds_add_u64) per lane at a random slot */
     MB_LDS_ADD_U32 = 3,      /* one 32-bit integer add (ds_add_u32) per lane at a random slot */
-    MB_LDS_ADD_F64_ROW33 = 4 /* each lane picks a random row of 33 FP64 slots and adds to all 33:
-                                the pattern of a tally flush at N = 16 */
+    MB_LDS_ADD_F64_ROW33 = 4, /* each lane picks a random row of 33 FP64 slots and adds to all 33:
+                                 the pattern of a tally flush at N = 16 */
+    MB_LDS_ADD_U64_ROW33 = 5, /* the same with 64-bit integer adds (ds_add_u64): the fixed-point
+                                 tally flush; one address computation per 33 adds */
+    MB_LDS_ADD_U64_PRE = 6    /* each lane draws 8 random slots once and adds to each of them in
+                                 every iteration: 64-bit integer adds with no address arithmetic */
 } mb_lds_kind;
 
 /* LDS atomic throughput.  n_blocks workgroups of `block` threads (a multiple
  * of 64, at most 1024), each with lds_bytes of dynamic LDS (at least 1 KiB,
  * at most 160 KiB, a multiple of 8; for the row kind at least 33 x 8 bytes)
  * zeroed at start; each thread makes `iters` iterations of the kind's adds.
- * Lane-operations: n_blocks * block * iters (x 33 for the row kind).
- * sink_d: FP64 [n_blocks], the sum of each workgroup's LDS array after the
- * adds (each add is of 1, so it equals block * iters, x 33 for the row kind).
+ * Lane-operations: n_blocks * block * iters (x 33 for the row kinds, x 8 for
+ * MB_LDS_ADD_U64_PRE).  sink_d: FP64 [n_blocks], the sum of each workgroup's
+ * LDS array after the adds (each add is of 1, so it equals block * iters
+ * times that factor).
  * clk_d: NULL or uint64 [4]: workgroup 0 records the shader clock counter
  * (variable frequency) at its start and end in [0], [1] and the constant-rate
  * counter (mb_wall_clock_khz) in [2], [3], which gives the clock under load. */

@@ -19,12 +19,13 @@ MC_NHARM_MAX = 32
 
 # exported symbols declared in include/*.h
 SYMBOLS = ("mc_workspace_bytes", "mc_forward", "mc_adjoint", "mc_residual", "mc_gradient", "mc_absorbed",
-           "mc_adjoint_source", "mc_gradient_h", "mc_detect", "mc_trace", "mc_philox_fill", "mc_profile_enable",
-           "mc_profile_read", "mc_set_tuning", "mc_get_tuning", "mc_batch_workspace_bytes", "mc_run_batch",
+           "mc_adjoint_source", "mc_gradient_h", "mc_detect", "mc_trace", "mc_philox_fill", "mc_default_tuning",
+           "mc_timer_create", "mc_timer_destroy", "mc_timer_read", "mc_batch_workspace_bytes", "mc_run_batch",
            "mc_binned_workspace_bytes", "mc_run_binned",
            "mc_status_string", "mc_build_info", "dn_conv3x3_fwd", "dn_conv3x3_wgrad",
            "mb_lds_atomics", "mb_global_atomics_f64", "mb_copy", "mb_fma_f32", "mb_wall_clock_khz")
-MB_LDS_ADD_F64, MB_LDS_ADD_F32, MB_LDS_ADD_U64, MB_LDS_ADD_U32, MB_LDS_ADD_F64_ROW33 = range(5)
+(MB_LDS_ADD_F64, MB_LDS_ADD_F32, MB_LDS_ADD_U64, MB_LDS_ADD_U32, MB_LDS_ADD_F64_ROW33, MB_LDS_ADD_U64_ROW33,
+ MB_LDS_ADD_U64_PRE) = range(7)
 
 
 class mc_medium(C.Structure):
@@ -49,7 +50,7 @@ class mc_ledger(C.Structure):
     _fields_ = [("launched", C.c_double), ("absorbed", C.c_double), ("escaped", C.c_double),
                 ("roulette_gain", C.c_double), ("roulette_loss", C.c_double), ("scale", C.c_double),
                 ("packets", C.c_uint64), ("segments", C.c_uint64), ("visits", C.c_uint64),
-                ("scatters", C.c_uint64)]
+                ("scatters", C.c_uint64), ("generations", C.c_uint64)]
 
 
 class mc_event(C.Structure):
@@ -66,7 +67,11 @@ class mc_problem(C.Structure):
 class mc_tuning(C.Structure):
     _fields_ = [("live_packets", C.c_uint64), ("job_packets", C.c_uint32), ("max_visits", C.c_uint32),
                 ("tile", C.c_uint32), ("grid_max_packets", C.c_uint32), ("finish_packets", C.c_uint64),
-                ("flush_track", C.c_float), ("tail_visits", C.c_uint32)]
+                ("flush_track", C.c_float), ("tail_visits", C.c_uint32), ("max_generations", C.c_uint32)]
+
+
+class mc_options(C.Structure):
+    _fields_ = [("tuning", C.POINTER(mc_tuning)), ("timer", C.c_void_p)]
 
 
 _lib = None
@@ -81,11 +86,11 @@ def load() -> C.CDLL:
         raise ImportError(f"{LIB_PATH} is missing; build it with `python -m paper_1608_05238_amd.build`")
     lib = C.CDLL(LIB_PATH)
     P, V, St = C.POINTER, C.c_void_p, C.c_int
-    lib.mc_workspace_bytes.argtypes = [P(mc_medium), P(mc_source), C.c_int, P(mc_run)]
+    lib.mc_workspace_bytes.argtypes = [P(mc_medium), P(mc_source), C.c_int, P(mc_run), P(mc_options)]
     lib.mc_workspace_bytes.restype = C.c_size_t
     for name in ("mc_forward", "mc_adjoint"):
         f = getattr(lib, name)
-        f.argtypes = [P(mc_medium), P(mc_source), C.c_int, P(mc_run), V, V, V, C.c_size_t, V]
+        f.argtypes = [P(mc_medium), P(mc_source), C.c_int, P(mc_run), P(mc_options), V, V, V, C.c_size_t, V]
         f.restype = St
     lib.mc_residual.argtypes = [P(mc_medium), V, V, V, V, V]
     lib.mc_residual.restype = St
@@ -104,23 +109,23 @@ def load() -> C.CDLL:
     lib.mc_trace.restype = St
     lib.mc_philox_fill.argtypes = [C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint64, C.c_uint32, V, V]
     lib.mc_philox_fill.restype = St
-    lib.mc_profile_enable.argtypes = [C.c_int]
-    lib.mc_profile_enable.restype = None
-    lib.mc_profile_read.argtypes = [P(C.c_double), P(C.c_uint64), C.c_int]
-    lib.mc_profile_read.restype = St
-    lib.mc_batch_workspace_bytes.argtypes = [P(mc_problem), C.c_int]
+    lib.mc_timer_create.argtypes = [P(V)]
+    lib.mc_timer_create.restype = St
+    lib.mc_timer_destroy.argtypes = [V]
+    lib.mc_timer_destroy.restype = St
+    lib.mc_timer_read.argtypes = [V, P(C.c_double), P(C.c_uint64), C.c_int]
+    lib.mc_timer_read.restype = St
+    lib.mc_default_tuning.argtypes = [P(mc_tuning)]
+    lib.mc_default_tuning.restype = St
+    lib.mc_batch_workspace_bytes.argtypes = [P(mc_problem), C.c_int, P(mc_options)]
     lib.mc_batch_workspace_bytes.restype = C.c_size_t
-    lib.mc_run_batch.argtypes = [P(mc_problem), C.c_int, V, C.c_size_t, V]
+    lib.mc_run_batch.argtypes = [P(mc_problem), C.c_int, P(mc_options), V, C.c_size_t, V]
     lib.mc_run_batch.restype = St
     lib.mc_binned_workspace_bytes.argtypes = [P(mc_medium), P(mc_source), C.c_int, P(mc_run), C.c_int]
     lib.mc_binned_workspace_bytes.restype = C.c_size_t
     lib.mc_run_binned.argtypes = [P(mc_medium), P(mc_source), C.c_int, P(mc_run), C.c_int, C.c_int, V, V, V,
                                   C.c_size_t, V]
     lib.mc_run_binned.restype = St
-    lib.mc_set_tuning.argtypes = [P(mc_tuning)]
-    lib.mc_set_tuning.restype = St
-    lib.mc_get_tuning.argtypes = [P(mc_tuning)]
-    lib.mc_get_tuning.restype = St
     lib.dn_conv3x3_fwd.argtypes = [V, V, V, V, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, V]
     lib.dn_conv3x3_fwd.restype = St
     lib.dn_conv3x3_wgrad.argtypes = [V, V, V, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, V]

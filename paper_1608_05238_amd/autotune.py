@@ -1,15 +1,18 @@
-"""Autotuner of the tiled transport: live packets, job size, visits per stay
-and visits after a job's last packet (any other mc_tuning field, e.g. the
-tile side, can be searched through the `space` argument).
+"""Autotuner of the tiled transport: live packets, job size, visits per stay,
+visits after a job's last packet and the tile side (any other mc_tuning
+field can be searched through the `space` argument).
 
-`tune()` times short forward (or adjoint) runs of the caller's problem over a
-set of candidate tunings, keeps the fastest, applies it with mc_set_tuning
-and records it in an optional JSON cache keyed by grid size, harmonic order
-and run kind; `tune_batch()` does the same for a batch of problems
-(mc_run_batch) on a sample of it.  The tuning changes only the schedule
-(which packets move together, how often they are sorted); the result of a
-run is the same (bitwise while its FP64 sums are exact, see mc_forward in
-include/mcrad.h).
+`tune()` times short forward (or adjoint) runs of the caller's problem over
+candidate tunings and returns the fastest (record it in an optional JSON
+cache keyed by grid size, harmonic order and run kind); `tune_batch()` does
+the same for a batch of problems (mc_run_batch) on a sample of it.  The
+library keeps no tuning state: the caller passes the tuning it got to its
+runs (`tuning=` of mc_forward, mc_adjoint, mc_run_batch).  The default search
+is coordinate-wise: each knob in turn takes the candidate that runs fastest
+with the others held at the best values found so far (13 trials); `grid=True`
+tries every combination.  The tuning changes only the schedule (which packets
+move together, how often they are sorted); the result of a run is the same
+(bitwise while its FP64 sums are exact, see mc_forward in include/mcrad.h).
 
     python -m paper_1608_05238_amd.autotune      # tune the 256x256 disc workload
 """
@@ -19,7 +22,7 @@ import itertools
 import json
 import os
 import sys
-from typing import Iterable, Optional, Sequence
+from typing import Callable, Iterable, Optional, Sequence
 
 import torch
 
@@ -30,6 +33,7 @@ DEFAULT_CANDIDATES = {
     "job_packets": (2048, 4096, 8192),
     "max_visits": (32, 64, 128),
     "tail_visits": (4, 8, 16),
+    "tile": (12, 16),
 }
 
 
@@ -44,43 +48,58 @@ def _key(medium: rmc.Medium, n_harm: int, adjoint: bool) -> str:
     return f"{medium.nx}x{medium.nz}_N{n_harm}_{'adjoint' if adjoint else 'forward'}"
 
 
-def search(run, n_packets: int, space: Optional[dict] = None, log=None) -> dict:
-    """Time the zero-argument callable `run` (moving n_packets packets) under
-    every candidate tuning, apply the fastest and return it with the trials."""
-    base = rmc.mc_get_tuning()
+def _time(run: Callable[[dict], None], tuning: dict) -> float:
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    run(tuning)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) * 1e-3
+
+
+def search(run: Callable[[dict], None], n_packets: int, space: Optional[dict] = None, log=None,
+           grid: bool = False) -> dict:
+    """Time `run(tuning)` (moving n_packets packets) under candidate tunings
+    and return {"tuning": fastest, "packets_per_s": ..., "trials": [...]}."""
+    space = space or DEFAULT_CANDIDATES
+    base = rmc.default_tuning()
     trials = []
-    run()   # warm-up (code, caches)
-    for cand in candidates(space):
-        rmc.mc_set_tuning({**base, **cand})
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        run()
-        e1.record()
-        torch.cuda.synchronize()
-        t = e0.elapsed_time(e1) * 1e-3
+    run(base)   # warm-up (code, caches)
+
+    def trial(cand: dict) -> float:
+        t = _time(run, {**base, **cand})
         trials.append({"tuning": {**base, **cand}, "packets_per_s": n_packets / t})
         if log:
             log(f"{cand}: {n_packets / t:.4e} packets/s")
-    best = max(trials, key=lambda r: r["packets_per_s"])
-    rmc.mc_set_tuning(best["tuning"])
-    return {"tuning": best["tuning"], "packets_per_s": best["packets_per_s"], "trials": trials}
+        return n_packets / t
+
+    if grid:
+        for cand in candidates(space):
+            trial(cand)
+    else:
+        best: dict = {}
+        for k, vals in space.items():
+            rates = {v: trial({**best, k: v}) for v in vals}
+            best[k] = max(rates, key=rates.get)
+    top = max(trials, key=lambda r: r["packets_per_s"])
+    return {"tuning": top["tuning"], "packets_per_s": top["packets_per_s"], "trials": trials}
 
 
 def tune(medium: rmc.Medium, sources: Sequence, n_harm: int, trial_packets: int = 10_000_000,
-         adjoint: bool = False, space: Optional[dict] = None, cache_path: Optional[str] = None, log=None) -> dict:
-    """Pick the fastest tuning for this problem, apply it and return
-    {"tuning": ..., "packets_per_s": ..., "trials": [...]}."""
+         adjoint: bool = False, space: Optional[dict] = None, cache_path: Optional[str] = None, log=None,
+         grid: bool = False) -> dict:
+    """The fastest tuning for this problem: {"tuning": ..., "packets_per_s":
+    ..., "trials": [...]} (from the cache when it holds this problem's key)."""
     key = _key(medium, n_harm, adjoint)
     cache = {}
     if cache_path and os.path.exists(cache_path):
         with open(cache_path) as f:
             cache = json.load(f)
         if key in cache:
-            rmc.mc_set_tuning(cache[key]["tuning"])
             return cache[key]
     fn = rmc.mc_adjoint if adjoint else rmc.mc_forward
     run = rmc.make_run(trial_packets, n_harm, seed=1, stream_tag=1 if adjoint else 0)
-    out = search(lambda: fn(medium, sources, run, ledger=False), trial_packets, space, log)
+    out = search(lambda t: fn(medium, sources, run, ledger=False, tuning=t), trial_packets, space, log, grid)
     if cache_path:
         cache[key] = {"tuning": out["tuning"], "packets_per_s": out["packets_per_s"]}
         with open(cache_path, "w") as f:
@@ -89,7 +108,7 @@ def tune(medium: rmc.Medium, sources: Sequence, n_harm: int, trial_packets: int 
 
 
 def tune_batch(problems: Sequence[rmc.Problem], every: int = 4, scale: float = 0.25,
-               space: Optional[dict] = None, log=None) -> dict:
+               space: Optional[dict] = None, log=None, grid: bool = False) -> dict:
     """Tune for a batch on a sample of it: every `every`-th problem with its
     packet count scaled by `scale` (same grids, sources and seeds)."""
     sub = []
@@ -100,7 +119,7 @@ def tune_batch(problems: Sequence[rmc.Problem], every: int = 4, scale: float = 0
                                rmc.make_run(n, r.n_harm, r.seed, r.first_packet_id, r.stream_tag, r.w_threshold,
                                             r.roulette_m, r.flags), pr.adjoint))
     total = sum(p.run.n_packets for p in sub)
-    return search(lambda: rmc.mc_run_batch(sub, ledger=False), total, space, log)
+    return search(lambda t: rmc.mc_run_batch(sub, ledger=False, tuning=t), total, space, log, grid)
 
 
 def main(argv=None) -> int:

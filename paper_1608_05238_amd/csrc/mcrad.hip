@@ -20,9 +20,14 @@
 //      - whole-grid mode (small tallies): the whole grid's tally sits in each
 //        workgroup's LDS, added to the FP64 map when the workgroup ends;
 //      - tiled mode: square tiles of the grid, packets migrate between tiles
-//        in generations (launch, counting sort by tile, one workgroup job per
-//        tile batch, tile tally added to the FP64 map per job); a finisher
-//        kernel moves the last packets to their end without migration;
+//        in generations (launch and count, sort of record indices by tile,
+//        one workgroup job per tile batch, tile tally added to the FP64 map
+//        per job); a finisher kernel moves the last packets to their end
+//        without migration;
+//  * every value a kernel needs that depends on device data (the sum and
+//    maximum of a source map, the fixed-point scale, the normalisation) is
+//    computed on the device, and the tiled generations are steered by a
+//    device control block, so no entry point waits for the device;
 //  * each visit adds the same integer multiple of the run's resolution
 //    whichever kernel, tile or generation completes it, so the maps depend
 //    on the schedule only through FP64 additions, which are exact while a
@@ -38,6 +43,7 @@
 #include <cstring>
 #include <algorithm>
 #include <mutex>
+#include <new>
 #include <vector>
 
 #include "mcrad.h"
@@ -54,13 +60,13 @@ constexpr uint64_t kChunk = 1ull << 22;                // whole-grid mode: packe
 constexpr size_t kLdsGridMax = 144 * 1024;             // whole-grid mode: tally bytes in LDS
 constexpr size_t kLdsTileMax = 72 * 1024;              // tiled mode: tile tally + medium bytes (2 WGs/CU)
 constexpr uint32_t kInvalidTile = 0xFFFFFFFFu;
-constexpr uint32_t kSlice = 256;                       // queue slots a wave reserves at a time
+constexpr uint32_t kSlice = 256;                       // queue slots a wave reserves at a time (default)
 constexpr float kPi = 3.14159265358979323846f;
 constexpr uint32_t kMaxInteractions = 1u << 24;         // hard cap per packet (guards invalid media)
-// tiled mode: the LDS tile tally holds 64-bit fixed-point sums, value * 2^(32 - e)
-// where 2^e bounds the magnitude of any packet weight of the run (fixed_add)
+// the LDS tallies hold 64-bit fixed-point sums, value * 2^(32 - e) where 2^e
+// bounds the magnitude of any packet weight of the run (fixed_add)
 constexpr int kFixBits = 32;
-constexpr double kFlushTrackMax = 65536.0;             // see TileTuning::flush_track
+constexpr double kFlushTrackMax = 65536.0;             // see mc_tuning::flush_track
 
 enum : int { EV_LAUNCH = 0, EV_CROSS = 1, EV_SCATTER = 2, EV_ESCAPE = 3, EV_KILL = 4, EV_NONE = 5 };
 
@@ -71,21 +77,36 @@ struct SrcDev {
     double cum;                 // inclusive prefix of the sampling measure
 };
 
-// Per-problem values the tiled transport needs for a job: one entry per
-// problem of a batch (a single run is a batch of one).
+// One problem (a forward or adjoint run) in device memory.  The host fills
+// what it knows and hands the struct to k_prob_setup by value; that kernel
+// adds what depends on device data (the sum and maximum of a MAP source, the
+// fixed-point scale, the normalisation) and stores it.  Every transport
+// kernel reads its packets' problem from here.
 struct ProbDev {
-    int nx, nz, ntx, tile_base;   // grid, tiles across, first global tile index
+    int nx, nz, npix, ntx, tile_base, ntiles;   // grid; tiles across; first global tile; tiles
+    int nsrc, adjoint;
+    float dx;
     uint32_t tag, flags;
     uint64_t seed;
+    uint64_t pid0, npk;           // packet range of the run
+    uint64_t todo;                // packets to launch (0 for a source of no power)
     float wth, rm, inv_rm;
     float flush_at;               // scaled |a0 accumulator| at which a visit is flushed in parts
-    float fx;                     // fixed-point scale of the LDS tile tally (a power of two)
+    float fx;                     // fixed-point scale of the LDS tallies (a power of two)
     double fx_inv;                // its inverse
-    const float4 *med;
-    const float *g;
-    double *t64;
-    double *led;
-    unsigned long long *ledc;     // [4]: jobs whose tile tally may have left the fixed-point range
+    double wbound;                // host part of the bound on |packet weight|
+    double flush_track;
+    double total;                 // source measure (MAP: 2 pi sum |q| A, set on the device)
+    double inv_qbar;              // MAP: npix / sum |q| (equal-count launch)
+    double scale;                 // normalisation total / packets (0: no power; NaN: unusable map)
+    const float4 *med;            // {mua dx, mus dx, 1/(mus dx), g}
+    const double *map;            // MAP source values (sign)
+    const double *cdf;            // MAP: inclusive prefix of |map|, then max |map|
+    double *t64;                  // FP64 tally [npix][K]
+    double *led;                  // 5 doubles
+    unsigned long long *ledc;     // [0..3] counts, [4] jobs whose tile tally may have left the fixed-point range
+    SrcDev src[kMaxSrc];
+    float prof[kMaxProf];
 };
 
 // The values a step and a scatter read, uniform over a workgroup's job.
@@ -96,45 +117,9 @@ struct Hot {
     float wth, rm, inv_rm;
 };
 
-struct Params {
-    int nx, nz, npix, nsrc;
-    float dx;
-    int adjoint;
-    uint32_t tag, flags;
-    uint64_t seed, pid0, npk;   // packet range of this launch
-    float wth, rm, inv_rm;
-    double total;
-    double inv_qbar;            // MAP: npix / sum |q| (equal-count launch)
-    double wbound;              // bound on |packet weight| (launch weight, roulette gain)
-    float fx;                   // fixed-point scale of the visit sums (a power of two, fixed_add)
-    float flush_at;             // scaled |a0| of a visit at which it is flushed in parts
-    double fx_inv;              // 1 / fx
-    const float4 *med;          // {mua dx, mus dx, 1/(mua dx), 1/(mus dx)}
-    const float *g;
-    const double *map;          // MAP source values (sign)
-    const double *cdf;          // MAP: inclusive prefix of |map|
-    double *t64;                // FP64 tally [npix][K]
-    // tiled mode: packets migrate between square tiles whose tallies live in LDS
-    int tw, th, ntx, ntiles;
-    struct PacketRec *qa;       // unsorted records (appended by launches and leavers)
-    uint32_t *qtile;            // tile of each unsorted record (kInvalidTile: empty slot)
-    struct PacketRec *qb;       // records sorted by tile
-    uint32_t *qcnt;             // [0] raw records in qa, [1] records to scatter, [2] jobs, [3] job cursor,
-                                // [4] overflow flag, [5] finisher record cursor, [6] valid records
-                                // written by the last transport launch
-    uint32_t *tile_count, *tile_cursor;
-    uint4 *jobs;                // (tile, first record in qb, count, 0)
-    uint32_t cap_a, cap_b, job_size, max_visits, tail_visits;
-    const ProbDev *probs;       // batch: problem descriptors
-    const uint32_t *tile_prob;  // batch: problem of each global tile
-    int tile_base;              // this problem's first global tile
-    uint32_t prob;              // this problem's index in the batch
-    unsigned long long *counter;
-    double *led;                // 5 doubles
-    unsigned long long *ledc;   // 4 counters
-    SrcDev src[kMaxSrc];
-    float prof[kMaxProf];
-};
+__device__ __forceinline__ Hot hot_of(const ProbDev &S) {
+    return Hot{S.nx, S.nz, S.tag, S.flags, S.seed, S.wth, S.rm, S.inv_rm};
+}
 
 // ------------------------------------------------------------------ Philox
 // Philox4x32-10 (Salmon et al., SC'11): 10 rounds of two 32x32->64-bit
@@ -250,8 +235,8 @@ __device__ __forceinline__ void harmonics(float sx, float sz, float *h) {
 }
 
 // Angular profile p(t) = c0/2pi + (1/pi) sum (c_n cos nt + s_n sin nt).
-__device__ __forceinline__ float profile(const Params &P, const SrcDev &s, float sx, float sz) {
-    const float *c = P.prof + s.prof_off;
+__device__ __forceinline__ float profile(const ProbDev &S, const SrcDev &s, float sx, float sz) {
+    const float *c = S.prof + s.prof_off;
     float p = c[0] * (0.5f / kPi);
     float re = sz, im = sx;
     for (int n = 1; n <= s.n_prof; ++n) {
@@ -304,7 +289,7 @@ __device__ __forceinline__ void locate1(double a, int n, float s, int &i, float 
 
 // Launch (Sec. 3; Sec. 6 for the volumetric signed source).  Returns false
 // if the packet starts outside the grid (it then escapes at once).
-__device__ bool launch_state(const Params &P, uint64_t pid, Packet &p, LedgerRegs &L) {
+__device__ bool launch_state(const ProbDev &P, uint64_t pid, Packet &p, LedgerRegs &L) {
     const uint4 r = rng_block(P, pid, 0);
     const float u0 = u01(r.x), u1 = u01(r.y), u2 = u01(r.z), u3 = u01(r.w);
     int s = 0;
@@ -377,7 +362,7 @@ __device__ bool launch_state(const Params &P, uint64_t pid, Packet &p, LedgerReg
 }
 
 template <int NH>
-__device__ bool launch(const Params &P, uint64_t pid, Packet &p, float *h, LedgerRegs &L) {
+__device__ bool launch(const ProbDev &P, uint64_t pid, Packet &p, float *h, LedgerRegs &L) {
     if (!launch_state(P, pid, p, L)) return false;
     harmonics<NH>(p.sx, p.sz, h);
     return true;
@@ -526,8 +511,8 @@ __device__ __forceinline__ bool scatter_dir(const PP &P, Packet &p, const float 
     return !scatter_masked(P, p, true, g, L);
 }
 
-template <int NH>
-__device__ __forceinline__ bool scatter(const Params &P, Packet &p, const float g, float *h, LedgerRegs &L) {
+template <int NH, class PP>
+__device__ __forceinline__ bool scatter(const PP &P, Packet &p, const float g, float *h, LedgerRegs &L) {
     if (!scatter_dir(P, p, g, L)) return false;
     harmonics<NH>(p.sx, p.sz, h);
     return true;
@@ -636,16 +621,27 @@ __device__ __forceinline__ long long fixed_value(unsigned long long raw, uint32_
 // as 64-bit fixed-point sums (fixed_add), added to the HBM FP64 tally with
 // coalesced atomics at the end.  Persistent waves refill dead lanes from a
 // global packet counter with one wave-aggregated atomic.
+struct GridArgs {
+    const ProbDev *pd;
+    uint64_t pid0, npk;           // packet range of this launch
+    unsigned long long *counter;
+};
+
 template <int NH>
-__global__ void __launch_bounds__(grid_block(NH)) k_transport_grid(Params P) {
+__global__ void __launch_bounds__(grid_block(NH)) k_transport_grid(GridArgs A) {
     constexpr int K = 2 * NH + 1;
     extern __shared__ unsigned long long gfx[];   // [npix][K] fixed-point sums (fixed_add)
     __shared__ float s_mag;
+    const ProbDev &S = *A.pd;
+    if (S.todo == 0) return;   // a source of no power: nothing to transport
+    const Hot H = hot_of(S);
+    const int npix = S.npix;
+    const float4 *med = S.med;
     const int lane = __lane_id();
-    for (int i = threadIdx.x; i < P.npix * K; i += blockDim.x) gfx[i] = 0ull;
+    for (int i = threadIdx.x; i < npix * K; i += blockDim.x) gfx[i] = 0ull;
     if (threadIdx.x == 0) s_mag = 0.f;
     __syncthreads();
-    const float fx = P.fx, flush_at = P.flush_at;
+    const float fx = S.fx, flush_at = S.flush_at;
 
     Packet p;
     idle_packet(p, 0, 0);
@@ -664,12 +660,12 @@ __global__ void __launch_bounds__(grid_block(NH)) k_transport_grid(Params P) {
                 const int ndead = __popcll(dead);
                 const int leader = __ffsll((long long)dead) - 1;
                 unsigned long long base = 0;
-                if (lane == leader) base = atomicAdd(P.counter, (unsigned long long)ndead);
+                if (lane == leader) base = atomicAdd(A.counter, (unsigned long long)ndead);
                 base = __shfl(base, leader);
-                if (base + ndead >= P.npk) more = false;
+                if (base + ndead >= A.npk) more = false;
                 if (!p.alive) {
                     const unsigned long long my = base + __popcll(dead & lt_mask);
-                    if (my < P.npk) launch_state(P, P.pid0 + my, p, L);
+                    if (my < A.npk) launch_state(S, A.pid0 + my, p, L);
                 }
             }
         }
@@ -678,10 +674,10 @@ __global__ void __launch_bounds__(grid_block(NH)) k_transport_grid(Params P) {
         }
         // every lane steps and scatters (no branch); a free lane's results are discarded
         const bool live = p.alive;
-        const int pix = live ? p.iz * P.nx + p.ix : 0;
+        const int pix = live ? p.iz * H.nx + p.ix : 0;
         float T = 0.f, dw = 0.f;
-        const float4 mm = P.med[pix];
-        int ev = step(P, p, mm, T, dw);
+        const float4 mm = med[pix];
+        int ev = step(H, p, mm, T, dw);
         ev = live ? ev : EV_NONE;
         T = live ? T : 0.f;
         dw = live ? dw : 0.f;
@@ -689,7 +685,7 @@ __global__ void __launch_bounds__(grid_block(NH)) k_transport_grid(Params P) {
         L.segments += live ? 1u : 0u;
         deposit_harmonics<NH>(T * fx, p.sx, p.sz, keep, acc);   // direction of the segment, before any scatter
         const bool at = ev == EV_SCATTER;
-        const bool killed = scatter_masked(P, p, at, mm.w, L);
+        const bool killed = scatter_masked(H, p, at, mm.w, L);
         const bool vend = killed || (ev != EV_NONE && !at);   // the visit ends
         const bool flush = vend || fabsf(acc[0]) > flush_at;  // a long stay is flushed in parts
         if (ev == EV_ESCAPE) {
@@ -705,32 +701,77 @@ __global__ void __launch_bounds__(grid_block(NH)) k_transport_grid(Params P) {
         L.visits += vend ? 1u : 0u;
         keep = flush ? 0.f : 1.f;
     }
-    ledger_flush_block(P.led, P.ledc, L);
+    ledger_flush_block(S.led, S.ledc, L);
     float wm = mag;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) wm += __shfl_xor(wm, o);
     if (lane == 0) atomicAdd(&s_mag, wm);
     __syncthreads();
-    if (threadIdx.x == 0 && !(s_mag < 0x1p62f)) atomicAdd(P.ledc + 4, 1ull);   // see k_normalise
-    for (int i = threadIdx.x; i < P.npix * K; i += blockDim.x) {
-        const double v = (double)(long long)gfx[i] * P.fx_inv;
-        if (v != 0.0) unsafeAtomicAdd(P.t64 + i, v);
+    if (threadIdx.x == 0 && !(s_mag < 0x1p62f)) atomicAdd(S.ledc + 4, 1ull);   // see k_normalise
+    for (int i = threadIdx.x; i < npix * K; i += blockDim.x) {
+        const double v = (double)(long long)gfx[i] * S.fx_inv;
+        if (v != 0.0) unsafeAtomicAdd(S.t64 + i, v);
     }
 }
 
 // ------------------------------------------------------------------ tiled transport
 // Larger grids: the grid is cut into tw x th tiles whose tallies (64-bit
-// fixed-point sums, fixed_add) fit in LDS.  A run proceeds in generations.  Each generation, the live packets
-// (sorted by tile) are split into jobs of at most job_size packets of one
-// tile; a workgroup takes a job, keeps that tile's tally and medium in LDS,
-// and moves each packet until it leaves the tile, dies, or has made
-// max_visits visits there.  Packets that leave (or pause) are written back as
-// records and sorted by tile for the next generation; new packets are
-// launched to keep the population up.  Every tally update is an LDS atomic;
-// HBM sees one coalesced flush of the tile per job.
+// fixed-point sums, fixed_add) fit in LDS.  A run -- or a batch of runs
+// sharing one packet pool and one global tile index space -- proceeds in
+// generations.  Each generation: new packets are launched to keep the pool
+// at `live` packets and every record is counted by tile (k_gen_count, whose
+// last workgroup scans the counts into a job list); the record indices are
+// sorted by tile (k_gen_scatter); a workgroup takes a job (at most job_size
+// packets of one tile), keeps that tile's tally and medium in LDS, and moves
+// each packet until it leaves the tile, dies, or has made max_visits visits
+// there (k_transport_tile).  Records stay where they were written: two pools
+// alternate between generations, one read, the other receiving the packets
+// that leave.  Every tally update is an LDS atomic; HBM sees one coalesced
+// flush of the tile per job.  Once every packet is launched and at most
+// finish_at remain, the control block marks the run done: later generations
+// do nothing and the finisher (k_finish) moves the rest to their end.
 
-__device__ __forceinline__ uint32_t tile_of(const Params &P, int ix, int iz) {
-    return (uint32_t)((iz / P.th) * P.ntx + ix / P.tw);
+// Device control block of a tiled run (zeroed at set-up).
+struct GenCtl {
+    uint32_t done;                // the finisher threshold was met: later generations do nothing
+    uint32_t fin_pool, fin_nc, fin_nl;   // where the finisher finds the records when done
+    uint32_t gen_done;            // generations run before the threshold was met
+    uint32_t wg_done;             // workgroups of k_gen_count that finished (the last one scans)
+    uint32_t nc[2];               // carried-region slots reserved in pool p
+    uint32_t nvalid[2];           // valid records among them
+    uint32_t nl[2];               // launch-region records of pool p
+    uint32_t n_rec, n_jobs, job_cursor;
+    uint32_t overflow;            // a queue or the job list would have overflowed (output NaN)
+    uint32_t new_first_prob;      // first problem with packets left to launch
+    uint64_t launched_total, todo_total;
+};
+
+// Batch-wide parameters of the tiled kernels (by value).
+struct Gen {
+    int tw, th, ntiles, nprob;
+    uint32_t live;                // packets kept alive per generation
+    uint32_t cap_c, cap_l;        // slots of a pool's carried and launch regions
+    uint32_t job_size, max_visits, tail_visits, finish_at;
+    uint32_t slice;               // slots a wave reserves at a time in a carried region (64 .. 256)
+    const ProbDev *probs;
+    const uint32_t *tile_prob;    // problem of each global tile
+    struct PacketRec *pool[2];    // [cap_c + cap_l] records
+    uint32_t *ptile[2];           // tile of each slot (kInvalidTile: empty slot)
+    uint32_t *sidx;               // slots of the generation's records sorted by tile [live]
+    uint32_t *tile_count, *tile_cursor;
+    uint4 *jobs;                  // (tile, first position in sidx, count, problem)
+    uint32_t max_jobs;
+    GenCtl *ctl;
+    uint64_t *launched;           // packets of each problem launched so far
+    unsigned long long *fin_cur;  // finisher work cursors: [0] records, [1 + p] unlaunched packets of problem p
+};
+
+// The total of packets to launch: problems whose source has no power (or is
+// unusable) launch none, which only the device descriptors know.
+__global__ void k_ctl_init(Gen G) {
+    uint64_t t = 0;
+    for (int p = 0; p < G.nprob; ++p) t += G.probs[p].todo;
+    G.ctl->todo_total = t;
 }
 
 __device__ __forceinline__ void rec_store(PacketRec *r, const Packet &p, uint32_t tile, uint32_t prob) {
@@ -775,276 +816,367 @@ __device__ __forceinline__ uint32_t rec_load(const PacketRec *r, Packet &p) {
     return d.w;
 }
 
-// Wave-private slices of the unsorted queue: a wave reserves kSlice slots
-// with one atomic on the queue counter (shared by every wave of the device,
-// so it is touched rarely) and fills them; unused slots are marked invalid.
+__device__ __forceinline__ uint32_t tile_in(int tw, int th, int ntx, int ix, int iz) {
+    return (uint32_t)((iz / th) * ntx + ix / tw);
+}
+
+// Wave-private slices of a pool's carried region: a wave reserves G.slice
+// slots with one atomic on the region's counter (shared by every wave of the
+// device, so it is touched rarely) and fills them; unused slots are marked
+// invalid.
 struct QueueSlice {
-    uint32_t base = 0, used = kSlice, nput = 0;
+    uint32_t base = 0, used = 0, nput = 0;
     bool valid = false;
 };
 
-__device__ __forceinline__ void slice_close(const Params &P, QueueSlice &q) {
+__device__ __forceinline__ void slice_close(const Gen &G, int pool, QueueSlice &q) {
     if (!q.valid) return;
     const int lane = __lane_id();
-    for (uint32_t i = q.used + lane; i < kSlice; i += 64)
-        if (q.base + i < P.cap_a) P.qtile[q.base + i] = kInvalidTile;
+    for (uint32_t i = q.used + lane; i < G.slice; i += 64)
+        if (q.base + i < G.cap_c) G.ptile[pool][q.base + i] = kInvalidTile;
 }
 
-// Appends the packet of every lane with `put` set to the unsorted queue.
-__device__ __forceinline__ void slice_put(const Params &P, QueueSlice &q, bool put, const Packet &p, uint32_t tile,
-                                          uint32_t prob) {
+// Appends the packet of every lane with `put` set to the pool's carried region.
+__device__ __forceinline__ void slice_put(const Gen &G, int pool, QueueSlice &q, bool put, const Packet &p,
+                                          uint32_t tile, uint32_t prob) {
     const unsigned long long m = __ballot(put);
     if (!m) return;
     const int n = __popcll(m);
     const int lane = __lane_id();
-    if (q.used + n > kSlice) {
-        slice_close(P, q);
+    if (!q.valid || q.used + n > G.slice) {
+        slice_close(G, pool, q);
         uint32_t base = 0;
-        if (lane == 0) base = atomicAdd(P.qcnt, kSlice);
+        if (lane == 0) base = atomicAdd(&G.ctl->nc[pool], G.slice);
         q.base = __shfl(base, 0);
         q.used = 0;
         q.valid = true;
     }
     if (put) {
         const uint32_t pos = q.base + q.used + __popcll(m & ((1ull << lane) - 1ull));
-        if (pos < P.cap_a) {
-            rec_store(P.qa + pos, p, tile, prob);
-            P.qtile[pos] = tile;
+        if (pos < G.cap_c) {
+            rec_store(G.pool[pool] + pos, p, tile, prob);
+            G.ptile[pool][pos] = tile;
+        } else {
+            atomicOr(&G.ctl->overflow, 1u);   // never written; the run's output becomes NaN
         }
-        else atomicOr(P.qcnt + 4, 1u);   // overflow: reported to the host, never written
     }
     q.used += n;
     q.nput += n;
 }
 
 // End of a wave's appends: pad its last slice and count its records.
-__device__ __forceinline__ void slice_finish(const Params &P, QueueSlice &q) {
-    slice_close(P, q);
-    if (q.nput && __lane_id() == 0) atomicAdd(P.qcnt + 6, q.nput);
+__device__ __forceinline__ void slice_finish(const Gen &G, int pool, QueueSlice &q) {
+    slice_close(G, pool, q);
+    if (q.nput && __lane_id() == 0) atomicAdd(&G.ctl->nvalid[pool], q.nput);
 }
 
-// Launch n_new packets (ids pid_base..) and append those inside the grid.
-// A grid-stride loop over few workgroups: each iteration reserves queue slots
-// with one atomic per workgroup, and the energy ledger is reduced over the
-// workgroup before its single set of atomics (the ledger and queue counters
-// are single addresses shared by the whole device).
-__global__ void __launch_bounds__(256) k_tile_launch(Params P, uint64_t pid_base, uint32_t n_new) {
-    __shared__ uint32_t s_cnt[4];
-    __shared__ uint32_t s_base;
-    const int lane = __lane_id(), wave = threadIdx.x >> 6;
-    LedgerRegs L;
-    for (uint32_t b0 = blockIdx.x * blockDim.x; b0 < n_new; b0 += gridDim.x * blockDim.x) {
-        const uint32_t i = b0 + threadIdx.x;
-        Packet p;
-        p.alive = false;
-        if (i < n_new) launch_state(P, pid_base + i, p, L);
-        const unsigned long long m = __ballot(p.alive);
-        if (lane == 0) s_cnt[wave] = (uint32_t)__popcll(m);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            const uint32_t tot = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
-            s_base = tot ? atomicAdd(P.qcnt, tot) : 0u;
-        }
-        __syncthreads();
-        if (p.alive) {
-            uint32_t pos = s_base + __popcll(m & ((1ull << lane) - 1ull));
-            for (int w = 0; w < wave; ++w) pos += s_cnt[w];
-            if (pos < P.cap_a) {
-                const uint32_t t = (uint32_t)P.tile_base + tile_of(P, p.ix, p.iz);
-                rec_store(P.qa + pos, p, t, P.prob);
-                P.qtile[pos] = t;
-            } else {
-                atomicOr(P.qcnt + 4, 1u);
-            }
-        }
-        __syncthreads();
+// ---- generation step 1: launch and count (the last workgroup scans)
+constexpr int kGenBlock = 1024;
+constexpr int kHistTiles = 4096;   // tiles histogrammed in LDS; beyond, wave-aggregated global atomics
+constexpr int kMaxAlloc = 256;     // problems that receive new packets in one generation
+
+// Counts one record of tile t (LDS histogram, or the global count directly).
+__device__ __forceinline__ void count_tile(const Gen &G, uint32_t *hist, bool local, uint32_t t, bool valid) {
+    if (local) {
+        if (valid) atomicAdd(hist + t, 1u);
+        return;
     }
-    ledger_flush_block(P.led, P.ledc, L);
-}
-
-// Counting sort of the unsorted queue by tile: counts.  Up to kHistTiles
-// tiles a workgroup histograms its share in LDS and adds each non-zero bin
-// to the global count once; beyond that, wave-aggregated global atomics.
-constexpr int kHistTiles = 4096;
-
-__global__ void __launch_bounds__(256) k_bin_count(Params P) {
-    __shared__ uint32_t hist[kHistTiles];
-    const uint32_t n = P.qcnt[0] < P.cap_a ? P.qcnt[0] : P.cap_a;
     const int lane = __lane_id();
-    const bool local = P.ntiles <= kHistTiles;
-    if (local) {
-        for (int i = threadIdx.x; i < P.ntiles; i += blockDim.x) hist[i] = 0u;
-        __syncthreads();
-    }
-    for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
-        const uint32_t i = base + threadIdx.x;
-        const uint32_t t = i < n ? P.qtile[i] : kInvalidTile;
-        if (local) {
-            if (t != kInvalidTile) atomicAdd(hist + t, 1u);
-            continue;
-        }
-        bool pend = t != kInvalidTile;
-        for (;;) {
-            const unsigned long long m = __ballot(pend);
-            if (!m) break;
-            const int leader = __ffsll((long long)m) - 1;
-            const uint32_t t0 = __shfl(t, leader);
-            const unsigned long long same = __ballot(pend && t == t0);
-            if (lane == leader) atomicAdd(P.tile_count + t0, (uint32_t)__popcll(same));
-            if (pend && t == t0) pend = false;
-        }
-    }
-    if (local) {
-        __syncthreads();
-        for (int i = threadIdx.x; i < P.ntiles; i += blockDim.x)
-            if (hist[i]) atomicAdd(P.tile_count + i, hist[i]);
+    bool pend = valid;
+    for (;;) {
+        const unsigned long long m = __ballot(pend);
+        if (!m) break;
+        const int leader = __ffsll((long long)m) - 1;
+        const uint32_t t0 = __shfl(t, leader);
+        const unsigned long long same = __ballot(pend && t == t0);
+        if (lane == leader) atomicAdd(G.tile_count + t0, (uint32_t)__popcll(same));
+        if (pend && t == t0) pend = false;
     }
 }
 
-// Single block: exclusive scan of the tile counts, job list, counters for the
-// next phase.  Tile counts are reset for the next generation.
-__global__ void __launch_bounds__(1024) k_bin_scan(Params P) {
-    __shared__ uint32_t s_rec[1024], s_job[1024];
+// The scan of a generation, by the last workgroup of k_gen_count: exclusive
+// scan of the tile counts into cursors and a job list; bookkeeping of the
+// launches; the finisher decision; reset of the other pool's counters.
+__device__ void gen_scan(const Gen &G, int g, uint32_t *buf, int np, const uint32_t *a_prob, const uint32_t *a_new) {
+    GenCtl *C = G.ctl;
+    const int cur = g & 1;
     const int t = threadIdx.x;
-    const int per = (P.ntiles + 1023) / 1024;
-    const int a = t * per, b = min(P.ntiles, a + per);
+    uint32_t *s_rec = buf, *s_job = buf + kGenBlock;
+    const int per = (G.ntiles + kGenBlock - 1) / kGenBlock;
+    const int a = t * per, b = min(G.ntiles, a + per);
     uint32_t nrec = 0, njob = 0;
     for (int i = a; i < b; ++i) {
-        const uint32_t c = P.tile_count[i];
+        const uint32_t c = G.tile_count[i];
         nrec += c;
-        njob += (c + P.job_size - 1) / P.job_size;
+        njob += (c + G.job_size - 1) / G.job_size;
     }
     s_rec[t] = nrec;
     s_job[t] = njob;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {   // inclusive Hillis-Steele scan
+    for (int off = 1; off < kGenBlock; off <<= 1) {   // inclusive Hillis-Steele scan
         const uint32_t vr = t >= off ? s_rec[t - off] : 0u, vj = t >= off ? s_job[t - off] : 0u;
         __syncthreads();
         s_rec[t] += vr;
         s_job[t] += vj;
         __syncthreads();
     }
-    const bool fits = s_rec[1023] <= P.cap_b;   // holds by construction; checked so nothing is written past it
+    const uint32_t total = s_rec[kGenBlock - 1], total_jobs = s_job[kGenBlock - 1];
+    const bool fits = total <= G.live && total_jobs <= G.max_jobs;   // hold by construction
     uint32_t roff = s_rec[t] - nrec, joff = s_job[t] - njob;
     for (int i = a; i < b; ++i) {
-        const uint32_t c = P.tile_count[i];
-        P.tile_cursor[i] = roff;
+        const uint32_t c = G.tile_count[i];
+        G.tile_cursor[i] = roff;
         if (fits)
-            for (uint32_t s0 = 0; s0 < c; s0 += P.job_size)
-                P.jobs[joff++] = make_uint4((uint32_t)i, roff + s0, min(P.job_size, c - s0), P.tile_prob[i]);
+            for (uint32_t s0 = 0; s0 < c; s0 += G.job_size)
+                G.jobs[joff++] = make_uint4((uint32_t)i, roff + s0, min(G.job_size, c - s0), G.tile_prob[i]);
         roff += c;
-        P.tile_count[i] = 0;
+        G.tile_count[i] = 0;
     }
     __syncthreads();
-    if (t == 1023) {
-        P.qcnt[1] = P.qcnt[0] < P.cap_a ? P.qcnt[0] : P.cap_a;
-        P.qcnt[0] = 0;
-        P.qcnt[2] = fits ? s_job[1023] : 0u;
-        P.qcnt[3] = 0;
-        P.qcnt[6] = 0;
-        if (!fits) P.qcnt[4] = 1u;
+    if (t == 0) {
+        uint64_t lt = C->launched_total;
+        for (int k = 0; k < np; ++k) {
+            G.launched[a_prob[k]] += a_new[k];
+            lt += a_new[k];
+        }
+        C->launched_total = lt;
+        uint32_t p = C->new_first_prob;
+        while (p < (uint32_t)G.nprob && G.launched[p] >= G.probs[p].todo) ++p;
+        C->new_first_prob = p;
+        C->n_rec = total;
+        C->n_jobs = fits ? total_jobs : 0u;
+        C->job_cursor = 0;
+        if (!fits) C->overflow = 1u;
+        // the packets left fit the finisher: this generation moves nothing
+        if (lt >= C->todo_total && total <= G.finish_at) {
+            C->done = 1u;
+            C->fin_pool = (uint32_t)cur;
+            C->fin_nc = min(C->nc[cur], G.cap_c);
+            C->fin_nl = min(C->nl[cur], G.cap_l);
+            C->gen_done = (uint32_t)g;
+            C->n_jobs = 0;
+        }
+        // the other pool receives this generation's leavers, then the next one's launches
+        C->nc[cur ^ 1] = 0;
+        C->nvalid[cur ^ 1] = 0;
+        C->nl[cur ^ 1] = 0;
+        C->wg_done = 0;
     }
 }
 
-// Counting sort: scatter records to their tile's range of the sorted queue.
-// A workgroup takes chunks of kScatterChunk records.  Up to kHistTiles tiles,
-// each record gets its rank among the chunk's records of its tile from an LDS
-// atomic, the workgroup reserves one range per tile it holds with a single
-// global atomic, and every record lands at range start + rank; beyond that,
-// ranks come from wave-aggregated global atomics.  The 64-byte records are
-// moved by four lanes each, so every load and store instruction covers
-// sixteen whole records.
+__global__ void __launch_bounds__(kGenBlock) k_gen_count(Gen G, int g) {
+    GenCtl *C = G.ctl;
+    __shared__ uint32_t hist[kHistTiles];
+    __shared__ uint32_t a_prob[kMaxAlloc], a_new[kMaxAlloc], a_pre[kMaxAlloc + 1];
+    __shared__ uint64_t a_base[kMaxAlloc];
+    __shared__ uint32_t w_cnt[kGenBlock / 64];
+    __shared__ uint32_t s_base;
+    __shared__ int s_np, s_last;
+    if (C->done) return;   // uniform: written by an earlier kernel
+    const int cur = g & 1;
+    const int lane = __lane_id(), wave = threadIdx.x >> 6;
+    const bool local = G.ntiles <= kHistTiles;
+    if (local)
+        for (int i = threadIdx.x; i < G.ntiles; i += kGenBlock) hist[i] = 0u;
+    if (threadIdx.x == 0) {
+        // new packets fill the pool up to `live`, problem after problem; each
+        // problem's share occupies a range of the launch index space rounded
+        // up to whole workgroups, so an iteration below serves one problem
+        uint64_t room = C->nvalid[cur] < G.live ? G.live - C->nvalid[cur] : 0;
+        int m = 0;
+        uint32_t pre = 0;
+        for (int p = (int)C->new_first_prob; p < G.nprob && room > 0 && m < kMaxAlloc; ++p) {
+            const uint64_t left = G.probs[p].todo - G.launched[p];
+            if (!left) continue;
+            const uint32_t k = (uint32_t)min<uint64_t>(left, room);
+            a_prob[m] = (uint32_t)p;
+            a_base[m] = G.launched[p];
+            a_new[m] = k;
+            a_pre[m] = pre;
+            pre += (k + kGenBlock - 1) / kGenBlock * kGenBlock;
+            room -= k;
+            ++m;
+        }
+        a_pre[m] = pre;
+        s_np = m;
+    }
+    __syncthreads();
+    const int np = s_np;
+    const uint32_t n_new = a_pre[np];
+    LedgerRegs L;
+    int lk = -1;   // allocation entry whose problem the ledger L holds (workgroup-uniform)
+    for (uint32_t b0 = blockIdx.x * kGenBlock; b0 < n_new; b0 += gridDim.x * kGenBlock) {
+        int lo = 0, hi = np - 1;   // the entry whose range holds b0
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (a_pre[mid] <= b0) lo = mid; else hi = mid - 1;
+        }
+        if (lo != lk) {
+            if (lk >= 0) {
+                const ProbDev &q = G.probs[a_prob[lk]];
+                ledger_flush_block(q.led, q.ledc, L);
+                L = LedgerRegs();
+            }
+            lk = lo;
+        }
+        const uint32_t prob = a_prob[lo];
+        const ProbDev &S = G.probs[prob];
+        const uint32_t i = b0 - a_pre[lo] + threadIdx.x;
+        Packet p;
+        p.alive = false;
+        if (i < a_new[lo]) launch_state(S, S.pid0 + a_base[lo] + i, p, L);
+        const unsigned long long m = __ballot(p.alive);
+        if (lane == 0) w_cnt[wave] = (uint32_t)__popcll(m);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t tot = 0;
+            for (int w = 0; w < kGenBlock / 64; ++w) tot += w_cnt[w];
+            s_base = tot ? atomicAdd(&C->nl[cur], tot) : 0u;
+        }
+        __syncthreads();
+        uint32_t tile = kInvalidTile;
+        if (p.alive) {
+            uint32_t pos = s_base + __popcll(m & ((1ull << lane) - 1ull));
+            for (int w = 0; w < wave; ++w) pos += w_cnt[w];
+            tile = (uint32_t)S.tile_base + tile_in(G.tw, G.th, S.ntx, p.ix, p.iz);
+            if (pos < G.cap_l) {
+                rec_store(G.pool[cur] + G.cap_c + pos, p, tile, prob);
+                G.ptile[cur][G.cap_c + pos] = tile;
+            } else {
+                atomicOr(&C->overflow, 1u);
+                tile = kInvalidTile;
+            }
+        }
+        count_tile(G, hist, local, tile, tile != kInvalidTile);
+        __syncthreads();   // w_cnt and s_base are reused
+    }
+    if (lk >= 0) {
+        const ProbDev &q = G.probs[a_prob[lk]];
+        ledger_flush_block(q.led, q.ledc, L);
+    }
+    // the records carried over from the last generation
+    const uint32_t nc = min(C->nc[cur], G.cap_c);
+    for (uint32_t b0 = blockIdx.x * kGenBlock; b0 < nc; b0 += gridDim.x * kGenBlock) {
+        const uint32_t i = b0 + threadIdx.x;
+        const uint32_t t = i < nc ? G.ptile[cur][i] : kInvalidTile;
+        count_tile(G, hist, local, t, t != kInvalidTile);
+    }
+    __syncthreads();
+    if (local)
+        for (int i = threadIdx.x; i < G.ntiles; i += kGenBlock)
+            if (hist[i]) atomicAdd(G.tile_count + i, hist[i]);
+    // the last workgroup to finish sees every count and scans them
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        s_last = atomicAdd(&C->wg_done, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    gen_scan(G, g, hist, np, a_prob, a_new);
+}
+
+// ---- generation step 2: sort the record indices by tile
+// A workgroup takes chunks of kScatterChunk records of the generation (the
+// pool's carried region, then its launch region); each record gets its rank
+// among the chunk's records of its tile from an LDS atomic, the workgroup
+// reserves one range per tile it holds with a single global atomic, and the
+// record's slot index lands at range start + rank.  Beyond kHistTiles tiles,
+// ranks come from wave-aggregated global atomics.
 constexpr int kScatterPer = 8;                              // records per thread and chunk
 constexpr uint32_t kScatterChunk = 256u * kScatterPer;
 
-__device__ __forceinline__ void move_records(const Params &P, uint32_t wave_first, uint32_t pos) {
-    const int lane = __lane_id();
-    const int part = lane & 3;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int r = q * 16 + (lane >> 2);   // record of the wave this lane helps move
-        const uint32_t dst = __shfl(pos, r);
-        if (dst < P.cap_b) {
-            const uint4 *src = reinterpret_cast<const uint4 *>(P.qa + wave_first + r);
-            reinterpret_cast<uint4 *>(P.qb + dst)[part] = src[part];
-        }
-    }
+__device__ __forceinline__ uint32_t gen_slot(const Gen &G, uint32_t u, uint32_t nc) {
+    return u < nc ? u : G.cap_c + (u - nc);
 }
 
-__global__ void __launch_bounds__(256) k_bin_scatter(Params P) {
+__global__ void __launch_bounds__(256) k_gen_scatter(Gen G, int g) {
     __shared__ uint32_t cnt[kHistTiles];
     __shared__ uint32_t start[kHistTiles];
-    const uint32_t n = P.qcnt[1];
+    GenCtl *C = G.ctl;
+    if (C->done) return;
+    const int cur = g & 1;
+    const uint32_t nc = min(C->nc[cur], G.cap_c), nl = min(C->nl[cur], G.cap_l);
+    const uint32_t n = nc + nl;
+    const uint32_t *pt = G.ptile[cur];
     const int lane = __lane_id();
-    if (P.ntiles <= kHistTiles) {
+    if (G.ntiles <= kHistTiles) {
         for (uint32_t c0 = blockIdx.x * kScatterChunk; c0 < n; c0 += gridDim.x * kScatterChunk) {
-            for (int i = threadIdx.x; i < P.ntiles; i += blockDim.x) cnt[i] = 0u;
+            for (int i = threadIdx.x; i < G.ntiles; i += blockDim.x) cnt[i] = 0u;
             __syncthreads();
             uint32_t t[kScatterPer], rank[kScatterPer];
 #pragma unroll
             for (int r = 0; r < kScatterPer; ++r) {
-                const uint32_t i = c0 + r * 256u + threadIdx.x;
-                t[r] = i < n ? P.qtile[i] : kInvalidTile;
+                const uint32_t u = c0 + r * 256u + threadIdx.x;
+                t[r] = u < n ? pt[gen_slot(G, u, nc)] : kInvalidTile;
                 rank[r] = t[r] != kInvalidTile ? atomicAdd(cnt + t[r], 1u) : 0u;
             }
             __syncthreads();
-            for (int i = threadIdx.x; i < P.ntiles; i += blockDim.x)
-                start[i] = cnt[i] ? atomicAdd(P.tile_cursor + i, cnt[i]) : 0u;
+            for (int i = threadIdx.x; i < G.ntiles; i += blockDim.x)
+                start[i] = cnt[i] ? atomicAdd(G.tile_cursor + i, cnt[i]) : 0u;
             __syncthreads();
 #pragma unroll
             for (int r = 0; r < kScatterPer; ++r) {
-                const uint32_t pos = t[r] != kInvalidTile ? start[t[r]] + rank[r] : 0xFFFFFFFFu;
-                move_records(P, c0 + r * 256u + threadIdx.x - (uint32_t)lane, pos);
+                if (t[r] == kInvalidTile) continue;
+                const uint32_t pos = start[t[r]] + rank[r];
+                if (pos < G.live) G.sidx[pos] = gen_slot(G, c0 + r * 256u + threadIdx.x, nc);
             }
             __syncthreads();
         }
         return;
     }
-    for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
-        const uint32_t i = base + threadIdx.x;
-        const uint32_t t = i < n ? P.qtile[i] : kInvalidTile;
+    for (uint32_t b0 = blockIdx.x * blockDim.x; b0 < n; b0 += gridDim.x * blockDim.x) {
+        const uint32_t u = b0 + threadIdx.x;
+        const uint32_t t = u < n ? pt[gen_slot(G, u, nc)] : kInvalidTile;
         bool pend = t != kInvalidTile;
-        uint32_t pos = 0xFFFFFFFFu;
         for (;;) {
             const unsigned long long m = __ballot(pend);
             if (!m) break;
             const int leader = __ffsll((long long)m) - 1;
             const uint32_t t0 = __shfl(t, leader);
             const unsigned long long same = __ballot(pend && t == t0);
-            uint32_t b0 = 0;
-            if (lane == leader) b0 = atomicAdd(P.tile_cursor + t0, (uint32_t)__popcll(same));
-            b0 = __shfl(b0, leader);
+            uint32_t b = 0;
+            if (lane == leader) b = atomicAdd(G.tile_cursor + t0, (uint32_t)__popcll(same));
+            b = __shfl(b, leader);
             if (pend && t == t0) {
-                pos = b0 + __popcll(same & ((1ull << lane) - 1ull));
+                const uint32_t pos = b + __popcll(same & ((1ull << lane) - 1ull));
+                if (pos < G.live) G.sidx[pos] = gen_slot(G, u, nc);
                 pend = false;
             }
         }
-        move_records(P, i - (uint32_t)lane, pos);
     }
 }
 
+// ---- generation step 3: move the packets tile by tile
 template <int NH>
-__global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu(NH <= 16 ? 4 : 2))) k_transport_tile(Params P) {
+__global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu(NH <= 16 ? 4 : 2)))
+k_transport_tile(Gen G, int g) {
     constexpr int K = 2 * NH + 1;
     // [tw*th][K] fixed-point sums: value * fx of the job's problem (fixed_add)
     extern __shared__ unsigned long long fxt[];
-    float4 *smed = reinterpret_cast<float4 *>(fxt + (((size_t)P.tw * P.th * K + 1) & ~size_t(1)));
-    uint32_t *sadds = reinterpret_cast<uint32_t *>(smed + P.tw * P.th);   // fixed_add_raw adds per pixel
+    float4 *smed = reinterpret_cast<float4 *>(fxt + (((size_t)G.tw * G.th * K + 1) & ~size_t(1)));
+    uint32_t *sadds = reinterpret_cast<uint32_t *>(smed + G.tw * G.th);   // fixed_add_raw adds per pixel
     __shared__ uint32_t s_job[5];
     __shared__ uint32_t s_next;
     __shared__ float s_mag;
+    GenCtl *C = G.ctl;
+    if (C->done) return;
+    const int cur = g & 1, nxt = cur ^ 1;
+    const PacketRec *in = G.pool[cur];
     const int lane = __lane_id();
-    const int ntp = P.tw * P.th;
+    const int ntp = G.tw * G.th;
     const unsigned long long lt_mask = (1ull << lane) - 1ull;
+    constexpr uint32_t kNone = 0xFFFFFFFFu;
     LedgerTile L;
     QueueSlice q;
-    int cur = -1;   // problem whose ledger L holds
+    int cur_prob = -1;   // problem whose ledger L holds
 
     for (;;) {
         if (threadIdx.x == 0) {
-            const uint32_t j = atomicAdd(P.qcnt + 3, 1u);
-            const bool ok = j < P.qcnt[2];
-            const uint4 jb = ok ? P.jobs[j] : make_uint4(0u, 0u, 0u, 0u);
+            const uint32_t j = atomicAdd(&C->job_cursor, 1u);
+            const bool ok = j < C->n_jobs;
+            const uint4 jb = ok ? G.jobs[j] : make_uint4(0u, 0u, 0u, 0u);
             s_job[0] = ok ? 1u : 0u;
             s_job[1] = jb.x;
             s_job[2] = jb.y;
@@ -1056,27 +1188,27 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
         __syncthreads();
         if (!s_job[0]) break;
         const uint32_t tile = s_job[1], first = s_job[2], cnt = s_job[3], prob = s_job[4];
-        const ProbDev &pd = P.probs[prob];
-        if ((int)prob != cur) {   // the ledger follows the problem (uniform in the workgroup)
-            if (cur >= 0) {
-                ledger_flush_tile(P.probs[cur].led, P.probs[cur].ledc, L);
+        const ProbDev &pd = G.probs[prob];
+        if ((int)prob != cur_prob) {   // the ledger follows the problem (uniform in the workgroup)
+            if (cur_prob >= 0) {
+                ledger_flush_tile(G.probs[cur_prob].led, G.probs[cur_prob].ledc, L);
                 L = LedgerTile();
             }
-            cur = (int)prob;
+            cur_prob = (int)prob;
         }
-        const Hot H{pd.nx, pd.nz, pd.tag, pd.flags, pd.seed, pd.wth, pd.rm, pd.inv_rm};
+        const Hot H = hot_of(pd);
         const int ntx = pd.ntx, local = (int)tile - pd.tile_base;
         const float4 *gmed = pd.med;
         double *t64 = pd.t64;
         const float fx = pd.fx;   // power of two: the scaled FP32 sums round exactly as unscaled ones
         const float flush_at = pd.flush_at;
-        const int tx0 = (local % ntx) * P.tw, tz0 = (local / ntx) * P.th;
+        const int tx0 = (local % ntx) * G.tw, tz0 = (local / ntx) * G.th;
         for (int i = threadIdx.x; i < ntp * K; i += blockDim.x) fxt[i] = 0ull;
         for (int i = threadIdx.x; i < ntp; i += blockDim.x) sadds[i] = 0u;
         for (int i = threadIdx.x; i < ntp; i += blockDim.x) {
-            const int gx = tx0 + i % P.tw, gz = tz0 + i / P.tw;
-            const bool in = gx < H.nx && gz < H.nz;
-            smed[i] = in ? gmed[gz * H.nx + gx] : make_float4(0.f, 0.f, 0.f, 0.f);
+            const int gx = tx0 + i % G.tw, gz = tz0 + i / G.tw;
+            const bool in_grid = gx < H.nx && gz < H.nz;
+            smed[i] = in_grid ? gmed[gz * H.nx + gx] : make_float4(0.f, 0.f, 0.f, 0.f);
         }
         __syncthreads();
 
@@ -1088,8 +1220,11 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
 #pragma unroll
         for (int j = 0; j < K; ++j) acc[j] = 0.f;
         // Each lane holds the record of its next packet in registers, loaded
-        // one whole stay ahead, so a refill never waits for memory.
+        // one whole stay ahead, and the pool slot of the packet after it,
+        // claimed one more stay ahead, so neither a refill nor the record
+        // load waits for memory.
         bool more = true, has_next = false;
+        uint32_t nslot = kNone;   // claimed slot whose record is not loaded yet
         uint32_t tail_nvis = 0;   // visits of the current stay when the job ran out of packets
         // (the last word is the packet id alone: a load whose destination
         // registers are partly dead lets them be reused, and the reuse must then
@@ -1108,11 +1243,22 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
             // so its LDS latency overlaps with that work
             const bool live = p.alive;
             // 24-bit products (full-rate v_mad_i32_i24): tile sizes and offsets are small
-            const int lp = live ? __mul24(p.iz - tz0, P.tw) + (p.ix - tx0) : 0;
+            const int lp = live ? __mul24(p.iz - tz0, G.tw) + (p.ix - tx0) : 0;
             const float4 mm = smed[lp];
-            // lanes without a prefetched record claim the next ones of the job
+            // free record registers take the record of the slot claimed earlier
+            if (!has_next && nslot != kNone) {
+                const uint4 *r = reinterpret_cast<const uint4 *>(in + nslot);
+                nr0 = r[0];
+                nr1 = r[1];
+                nr2 = r[2];
+                const uint64_t id = in[nslot].pid;
+                nr3 = make_uint2((uint32_t)id, (uint32_t)(id >> 32));
+                has_next = true;
+                nslot = kNone;
+            }
+            // lanes without a claimed slot claim the next ones of the job
             if (more) {
-                const unsigned long long want = __ballot(!has_next);
+                const unsigned long long want = __ballot(nslot == kNone);
                 if (want) {
                     const int nw = __popcll(want);
                     const int leader = __ffsll((long long)want) - 1;
@@ -1123,22 +1269,17 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
                         more = false;
                         tail_nvis = nvis;
                     }
-                    if (!has_next) {
+                    if (nslot == kNone) {
                         const uint32_t my = base + __popcll(want & lt_mask);
                         if (my < cnt) {
-                            const uint4 *r = reinterpret_cast<const uint4 *>(P.qb + first + my);
-                            nr0 = r[0];
-                            nr1 = r[1];
-                            nr2 = r[2];
-                            const uint64_t id = P.qb[first + my].pid;
-                            nr3 = make_uint2((uint32_t)id, (uint32_t)(id >> 32));
-                            has_next = true;
+                            const uint32_t sl = G.sidx[first + my];
+                            nslot = sl < G.cap_c + G.cap_l ? sl : kNone;   // always true; guards the load below
                         }
                     }
                 }
             }
             if (!__ballot(p.alive)) {
-                if (!more && !__ballot(has_next)) break;
+                if (!more && !__ballot(has_next || nslot != kNone)) break;
             }
             // every lane steps (no branch); a free lane's result is discarded
             float T = 0.f, dw = 0.f;
@@ -1176,18 +1317,18 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
                 L.visits += 1;
                 nvis += 1;
                 if (ev == EV_CROSS) {
-                    const int ox = p.ix < tx0 ? -1 : (p.ix >= tx0 + P.tw ? 1 : 0);
-                    const int oz = p.iz < tz0 ? -1 : (p.iz >= tz0 + P.th ? 1 : 0);
+                    const int ox = p.ix < tx0 ? -1 : (p.ix >= tx0 + G.tw ? 1 : 0);
+                    const int oz = p.iz < tz0 ? -1 : (p.iz >= tz0 + G.th ? 1 : 0);
                     const bool out = (ox | oz) != 0;
                     dest = (uint32_t)((int)tile + __mul24(oz, ntx) + ox);   // a crossing moves one pixel: a neighbour tile
                     // once the job has no packets left to hand out, a packet pauses
                     // after tail_visits more visits so the workgroup is not held by
                     // its longest stay (it resumes next generation)
-                    leave = out || nvis >= (more ? P.max_visits : min(P.max_visits, tail_nvis + P.tail_visits));
+                    leave = out || nvis >= (more ? G.max_visits : min(G.max_visits, tail_nvis + G.tail_visits));
                 }
             }
             keep = flush ? 0.f : 1.f;
-            slice_put(P, q, leave, p, dest, prob);
+            slice_put(G, nxt, q, leave, p, dest, prob);
             if (leave) {
                 p.alive = false;
                 nvis = 0;
@@ -1205,28 +1346,32 @@ __global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu
         for (int i = threadIdx.x; i < ntp * K; i += blockDim.x) {
             const int lp = i / K, c = i - lp * K;
             const double v = (double)fixed_value(fxt[i], sadds[lp]) * pd.fx_inv;
-            const int gx = tx0 + lp % P.tw, gz = tz0 + lp / P.tw;
+            const int gx = tx0 + lp % G.tw, gz = tz0 + lp / G.tw;
             if (v != 0.0 && gx < H.nx && gz < H.nz) unsafeAtomicAdd(t64 + (size_t)(gz * H.nx + gx) * K + c, v);
         }
         __syncthreads();
     }
-    slice_finish(P, q);
-    if (cur >= 0) ledger_flush_tile(P.probs[cur].led, P.probs[cur].ledc, L);   // cur is uniform
+    slice_finish(G, nxt, q);
+    if (cur_prob >= 0) ledger_flush_tile(G.probs[cur_prob].led, G.probs[cur_prob].ledc, L);   // uniform
 }
 
 // ------------------------------------------------------------------ tail finisher
-// When few packets remain after the last launch, the generations would be
-// dominated by the longest-lived packets.  The finisher moves each remaining
-// packet to its end without migration; a wave stages the K-vectors of the
-// visits it completes in LDS and adds them to the HBM FP64 tally as
-// contiguous runs of atomics.
+// When few packets remain, the generations would be dominated by the
+// longest-lived packets.  The finisher moves each remaining packet to its end
+// without migration, whatever problem it belongs to: first the records the
+// last generation left (the pool of the generation that found the threshold
+// met, or the pool after the last enqueued generation), then -- only if the
+// generations ran out before every packet was launched -- the packets of
+// each problem not launched yet (one launch per problem, `prob_only`).  A
+// wave stages the K-vectors of the visits it completes in LDS and adds them
+// to the HBM FP64 tallies as contiguous runs of atomics.
 constexpr int kBlockFinish = 256;
 
-// Adds a wave's staged visit sums (n visits of K values) to the HBM tally:
+// Adds a wave's staged visit sums (n visits of K values) to the HBM tallies:
 // consecutive lanes take consecutive values, so each pixel's K channels go
 // out as one contiguous run of atomics.
-__device__ __forceinline__ void finish_flush_stage(const Params &P, const float *stage, const int *stage_pix, int n,
-                                                   int K, double fx_inv) {
+__device__ __forceinline__ void finish_flush_stage(const Gen &G, const float *stage, const int *stage_pix,
+                                                   const int *stage_prob, int n, int K) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -1234,12 +1379,50 @@ __device__ __forceinline__ void finish_flush_stage(const Params &P, const float 
     for (int e = __lane_id(); e < total; e += 64) {
         const int v = e / K;
         const float val = stage[e];
-        if (val != 0.f)
-            unsafeAtomicAdd(P.t64 + (size_t)stage_pix[v] * K + (e - v * K), __builtin_rint((double)val) * fx_inv);
+        if (val != 0.f) {
+            const ProbDev &S = G.probs[stage_prob[v]];
+            unsafeAtomicAdd(S.t64 + (size_t)stage_pix[v] * K + (e - v * K), __builtin_rint((double)val) * S.fx_inv);
+        }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Ledger of lanes that may hold different problems (prob < 0: nothing held):
+// the lanes of each problem in turn are summed over the wave and one lane
+// adds the sums to that problem's ledger.
+__device__ __forceinline__ void ledger_flush_lanes(const Gen &G, int prob, const LedgerRegs &L) {
+    const int lane = __lane_id();
+    int pend = prob;
+    for (;;) {
+        const unsigned long long m = __ballot(pend >= 0);
+        if (!m) break;
+        const int leader = __ffsll((long long)m) - 1;
+        const int p0 = __shfl(pend, leader);
+        const bool mine = pend == p0;
+        double v[5] = {L.launched, L.absorbed, L.escaped, L.gain, L.loss};
+        unsigned long long c[4] = {L.packets, L.segments, L.visits, L.scatters};
+#pragma unroll
+        for (int i = 0; i < 5; ++i) v[i] = mine ? v[i] : 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) c[i] = mine ? c[i] : 0ull;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+            for (int i = 0; i < 5; ++i) v[i] += __shfl_xor(v[i], off);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) c[i] += __shfl_xor(c[i], off);
+        }
+        if (lane == leader) {
+            const ProbDev &S = G.probs[p0];
+            for (int i = 0; i < 5; ++i)
+                if (v[i] != 0.0) atomicAdd(S.led + i, v[i]);
+            for (int i = 0; i < 4; ++i)
+                if (c[i]) atomicAdd(S.ledc + i, c[i]);
+        }
+        if (mine) pend = -1;
+    }
 }
 
 // Few packets per lane and long histories make this kernel latency-bound, so
@@ -1247,27 +1430,51 @@ __device__ __forceinline__ void finish_flush_stage(const Params &P, const float 
 // medium of the pixel a packet enters is loaded one iteration ahead of its
 // use, and a wave gathers the sums of up to 64 completed visits in LDS before
 // it adds them to the tally (the wait for those atomics then comes once per
-// buffer, not once per visit).
+// buffer, not once per visit).  Lanes branch (a lone packet in a wave pays
+// only for what it does).
 template <int NH>
-__global__ void __launch_bounds__(kBlockFinish) k_finish(Params P, uint32_t n_rec) {
+__global__ void __launch_bounds__(kBlockFinish) k_finish(Gen G, int g_last, int prob_only) {
     constexpr int K = 2 * NH + 1;
     extern __shared__ float stage_all[];
+    GenCtl *C = G.ctl;
     const int lane = __lane_id();
     const int wave = threadIdx.x >> 6;
     float *stage = stage_all + wave * 64 * K;
     int *stage_pix = reinterpret_cast<int *>(stage_all + (kBlockFinish / 64) * 64 * K) + wave * 64;
+    int *stage_prob = stage_pix + (kBlockFinish / 64) * 64;
     const unsigned long long lt_mask = (1ull << lane) - 1ull;
+    // the work: records of a pool (prob_only < 0) or the unlaunched packets of one problem
+    uint32_t pool = 0, nc = 0, nl = 0;
+    uint64_t n_work = 0, pid_first = 0;
+    unsigned long long *cursor = G.fin_cur + (prob_only < 0 ? 0 : 1 + prob_only);
+    if (prob_only < 0) {
+        if (C->done) {
+            pool = C->fin_pool;
+            nc = C->fin_nc;
+            nl = C->fin_nl;
+        } else {   // the generations ran out: the leavers of the last one
+            pool = (uint32_t)(g_last & 1);
+            nc = min(C->nc[pool], G.cap_c);
+        }
+        n_work = (uint64_t)nc + nl;
+    } else {
+        const ProbDev &S = G.probs[prob_only];
+        pid_first = G.launched[prob_only];
+        n_work = S.todo > pid_first ? S.todo - pid_first : 0;
+        if (!n_work) return;
+    }
     LedgerRegs L;
+    int lprob = -1;   // problem of the ledger L
     Packet p;
     idle_packet(p, 0, 0);
+    int prob = -1;    // problem of the lane's packet
+    Hot H{};
+    const float4 *med = nullptr;
+    float fx = 0.f, flush_at = 0.f;
     float4 mm = make_float4(0.f, 0.f, 0.f, 0.f);   // medium of the packet's pixel
     float acc[K], keep = 1.f;   // keep = 0 after a flush: the next deposit restarts the sums
 #pragma unroll
     for (int j = 0; j < K; ++j) acc[j] = 0.f;
-    // visit sums are scaled and rounded as in the LDS tallies (fixed_add), so a
-    // visit adds the same value whichever kernel completes it
-    const float fx = P.fx, flush_at = P.flush_at;
-    const double fx_inv = P.fx_inv;
     bool more = true;
     int used = 0;   // visits staged in this wave's buffer (wave-uniform)
     for (;;) {
@@ -1276,15 +1483,48 @@ __global__ void __launch_bounds__(kBlockFinish) k_finish(Params P, uint32_t n_re
             if (dead) {
                 const int ndead = __popcll(dead);
                 const int leader = __ffsll((long long)dead) - 1;
-                uint32_t base = 0;
-                if (lane == leader) base = atomicAdd(P.qcnt + 5, (uint32_t)ndead);
+                unsigned long long base = 0;
+                if (lane == leader) base = atomicAdd(cursor, (unsigned long long)ndead);
                 base = __shfl(base, leader);
-                if (base + ndead >= n_rec) more = false;
+                if (base + ndead >= n_work) more = false;
                 if (!p.alive) {
-                    const uint32_t my = base + __popcll(dead & lt_mask);
-                    if (my < n_rec && P.qtile[my] != kInvalidTile && P.qa[my].prob == P.prob) {
-                        rec_load(P.qa + my, p);   // a queued packet is inside the grid
-                        mm = P.med[p.iz * P.nx + p.ix];
+                    const uint64_t my = base + __popcll(dead & lt_mask);
+                    int np_ = -1;
+                    Packet q;
+                    q.alive = false;
+                    if (my < n_work) {
+                        if (prob_only < 0) {
+                            const uint32_t slot = my < nc ? (uint32_t)my : G.cap_c + (uint32_t)(my - nc);
+                            if (G.ptile[pool][slot] != kInvalidTile) np_ = (int)rec_load(G.pool[pool] + slot, q);
+                        } else {
+                            np_ = prob_only;
+                        }
+                    }
+                    if (np_ >= 0) {
+                        if (np_ != lprob) {   // a lane changes problem: its ledger goes out first (rare)
+                            if (lprob >= 0) {
+                                const ProbDev &O = G.probs[lprob];
+                                double v[5] = {L.launched, L.absorbed, L.escaped, L.gain, L.loss};
+                                unsigned long long c[4] = {L.packets, L.segments, L.visits, L.scatters};
+                                for (int i = 0; i < 5; ++i)
+                                    if (v[i] != 0.0) atomicAdd(O.led + i, v[i]);
+                                for (int i = 0; i < 4; ++i)
+                                    if (c[i]) atomicAdd(O.ledc + i, c[i]);
+                                L = LedgerRegs();
+                            }
+                            lprob = np_;
+                        }
+                        const ProbDev &S = G.probs[np_];
+                        if (prob_only >= 0) launch_state(S, S.pid0 + pid_first + my, q, L);
+                        if (q.alive) {
+                            p = q;
+                            prob = np_;
+                            H = hot_of(S);
+                            med = S.med;
+                            fx = S.fx;
+                            flush_at = S.flush_at;
+                            mm = med[p.iz * H.nx + p.ix];   // a queued or launched packet is inside the grid
+                        }
                     }
                 }
             }
@@ -1293,36 +1533,36 @@ __global__ void __launch_bounds__(kBlockFinish) k_finish(Params P, uint32_t n_re
             if (!more) break;
         }
         int ev = EV_NONE, pix = 0;
-        float T = 0.f, dw = 0.f;
-        const float g = mm.w;   // read before mm is reloaded: the scatter need not wait for that load
+        float T = 0.f;
+        bool vend = false;
         if (p.alive) {
-            pix = p.iz * P.nx + p.ix;
-            ev = step(P, p, mm, T, dw);
+            const float g = mm.w;   // read before mm is reloaded: the scatter need not wait for that load
+            float dw = 0.f;
+            pix = p.iz * H.nx + p.ix;
+            ev = step(H, p, mm, T, dw);
             L.absorbed += (double)dw;
             L.segments += 1;
-        }
-        // the medium of the pixel the next step starts in (a crossing's new
-        // pixel, else the same one), loaded by every lane outside any branch so
-        // the load lands in mm directly and is waited for only at that step
-        mm = P.med[ev == EV_CROSS ? p.iz * P.nx + p.ix : pix];
-        deposit_harmonics<NH>(T * fx, p.sx, p.sz, keep, acc);   // direction of the segment, before any scatter
-        bool vend = false;
-        if (ev == EV_SCATTER) {
-            if (!scatter_dir(P, p, g, L)) vend = true;   // the pixel of the step
-        } else if (ev != EV_NONE) {
-            vend = true;
-            if (ev == EV_ESCAPE) {
-                L.escaped += p.w;
-                p.alive = false;
+            // the medium of the pixel the next step starts in (a crossing's new
+            // pixel, else the same one)
+            if (ev == EV_CROSS) mm = med[p.iz * H.nx + p.ix];
+            deposit_harmonics<NH>(T * fx, p.sx, p.sz, keep, acc);   // direction of the segment, before any scatter
+            if (ev == EV_SCATTER) {
+                if (!scatter_dir(H, p, g, L)) vend = true;   // killed by roulette: the visit ends
+            } else {
+                vend = true;
+                if (ev == EV_ESCAPE) {
+                    L.escaped += p.w;
+                    p.alive = false;
+                }
             }
         }
-        const bool flush = vend || fabsf(acc[0]) > flush_at;
+        const bool flush = vend || (ev != EV_NONE && fabsf(acc[0]) > flush_at);
         L.visits += vend ? 1u : 0u;
         const unsigned long long fm = __ballot(flush);
         if (fm) {
             const int nf = __popcll(fm);
             if (used + nf > 64) {   // no room: the staged visits go to the tally first
-                finish_flush_stage(P, stage, stage_pix, used, K, fx_inv);
+                finish_flush_stage(G, stage, stage_pix, stage_prob, used, K);
                 used = 0;
             }
             if (flush) {
@@ -1331,13 +1571,14 @@ __global__ void __launch_bounds__(kBlockFinish) k_finish(Params P, uint32_t n_re
 #pragma unroll
                 for (int j = 0; j < K; ++j) st[j] = acc[j];
                 stage_pix[slot] = pix;
+                stage_prob[slot] = prob;
             }
             used += nf;
         }
-        keep = flush ? 0.f : 1.f;
+        if (ev != EV_NONE) keep = flush ? 0.f : 1.f;
     }
-    if (used) finish_flush_stage(P, stage, stage_pix, used, K, fx_inv);
-    ledger_flush_block(P.led, P.ledc, L);
+    if (used) finish_flush_stage(G, stage, stage_pix, stage_prob, used, K);
+    ledger_flush_lanes(G, lprob, L);
 }
 
 // ------------------------------------------------------------------ discrete-ordinates tally
@@ -1347,7 +1588,10 @@ __global__ void __launch_bounds__(kBlockFinish) k_finish(Params P, uint32_t n_re
 // direction's angular bin with one FP64 device atomic.
 constexpr int kBinnedMax = 4096;
 
-__global__ void __launch_bounds__(256) k_transport_binned(Params P, int n_bins, double *raw) {
+__global__ void __launch_bounds__(256) k_transport_binned(GridArgs A, int n_bins, double *raw) {
+    const ProbDev &S = *A.pd;
+    if (S.todo == 0) return;
+    const Hot H = hot_of(S);
     const int lane = __lane_id();
     Packet p;
     idle_packet(p, 0, 0);
@@ -1362,12 +1606,12 @@ __global__ void __launch_bounds__(256) k_transport_binned(Params P, int n_bins, 
                 const int ndead = __popcll(dead);
                 const int leader = __ffsll((long long)dead) - 1;
                 unsigned long long base = 0;
-                if (lane == leader) base = atomicAdd(P.counter, (unsigned long long)ndead);
+                if (lane == leader) base = atomicAdd(A.counter, (unsigned long long)ndead);
                 base = __shfl(base, leader);
-                if (base + ndead >= P.npk) more = false;
+                if (base + ndead >= A.npk) more = false;
                 if (!p.alive) {
                     const unsigned long long my = base + __popcll(dead & lt_mask);
-                    if (my < P.npk) launch_state(P, P.pid0 + my, p, L);
+                    if (my < A.npk) launch_state(S, A.pid0 + my, p, L);
                 }
             }
         }
@@ -1375,10 +1619,10 @@ __global__ void __launch_bounds__(256) k_transport_binned(Params P, int n_bins, 
             if (!more) break;
         }
         const bool live = p.alive;
-        const int pix = live ? p.iz * P.nx + p.ix : 0;
+        const int pix = live ? p.iz * H.nx + p.ix : 0;
         float T = 0.f, dw = 0.f;
-        const float4 mm = P.med[pix];
-        int ev = step(P, p, mm, T, dw);
+        const float4 mm = S.med[pix];
+        int ev = step(H, p, mm, T, dw);
         ev = live ? ev : EV_NONE;
         dw = live ? dw : 0.f;
         L.absorbed += (double)dw;
@@ -1386,38 +1630,42 @@ __global__ void __launch_bounds__(256) k_transport_binned(Params P, int n_bins, 
         if (live && T != 0.f) {   // direction of the segment, before any scatter
             const double th = atan2((double)p.sx, (double)p.sz);
             const int b = min(n_bins - 1, max(0, (int)floor((th + M_PI) * per_rad)));
-            unsafeAtomicAdd(raw + (size_t)b * P.npix + pix, (double)T);
+            unsafeAtomicAdd(raw + (size_t)b * S.npix + pix, (double)T);
         }
         const bool at = ev == EV_SCATTER;
-        const bool killed = scatter_masked(P, p, at, mm.w, L);
+        const bool killed = scatter_masked(H, p, at, mm.w, L);
         if (ev == EV_ESCAPE) {
             L.escaped += p.w;
             p.alive = false;
         }
         L.visits += (killed || (ev != EV_NONE && !at)) ? 1u : 0u;
     }
-    ledger_flush_block(P.led, P.ledc, L);
+    ledger_flush_block(S.led, S.ledc, L);
 }
 
 // binned[b][i] = raw[b'][i] * scale, b' = b (forward) or b + n_bins/2 (adjoint:
-// the mirrored direction)
-__global__ void k_binned_normalise(int npix, int n_bins, int adjoint, double scale, const double *raw, double *out) {
+// the mirrored direction); scale = the run's normalisation / (dx w), w the bin width
+__global__ void k_binned_normalise(const ProbDev *pd, int n_bins, double bw, const double *raw, double *out) {
+    const int npix = pd->npix;
     const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
     if (i >= (size_t)npix * n_bins) return;
     const int b = (int)(i / npix);
     const size_t px = i - (size_t)b * npix;
-    const int src = adjoint ? (b + n_bins / 2) % n_bins : b;
+    const int src = pd->adjoint ? (b + n_bins / 2) % n_bins : b;
+    const double scale = pd->scale / ((double)pd->dx * bw);
     out[i] = raw[(size_t)src * npix + px] * scale;
 }
 
 // ------------------------------------------------------------------ trace kernel
 // Runs the listed packets one after the other through the same device
-// functions as k_transport and records every event.
+// functions as the transport kernels and records every event.
 template <int NH>
-__global__ void k_trace(Params P, const uint64_t *pids, int n_pids, mc_event *ev, size_t cap,
+__global__ void k_trace(const ProbDev *pd, const uint64_t *pids, int n_pids, mc_event *ev, size_t cap,
                         unsigned long long *n_ev) {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
     constexpr int K = 2 * NH + 1;
+    const ProbDev &P = *pd;
+    const Hot H = hot_of(P);
     float h[K];
     LedgerRegs L;
     size_t n = 0;
@@ -1451,9 +1699,10 @@ __global__ void k_trace(Params P, const uint64_t *pids, int n_pids, mc_event *ev
             const int ix = p.ix, iz = p.iz, k = (int)p.k;
             float T, dw;
             const int pix = p.iz * P.nx + p.ix;
-            const int e = step(P, p, P.med[pix], T, dw);
+            const float4 mm = P.med[pix];
+            const int e = step(H, p, mm, T, dw);
             if (e == EV_SCATTER) {
-                if (scatter<NH>(P, p, P.g[pix], h, L)) rec(p, EV_SCATTER, k, ix, iz, p.w, T);
+                if (scatter<NH>(H, p, mm.w, h, L)) rec(p, EV_SCATTER, k, ix, iz, p.w, T);
                 else rec(p, EV_KILL, k, ix, iz, p.w, T);
             } else if (e == EV_ESCAPE) {
                 p.alive = false;
@@ -1483,7 +1732,8 @@ __global__ void k_fill_zero(uint32_t *p, size_t n) {
 }
 
 // Single-block inclusive scan of |map| in FP64 (fixed order: each thread a
-// contiguous run, then a sequential pass over the 1024 run totals).
+// contiguous run, then a sequential pass over the 1024 run totals); the
+// maximum of |map| is stored after the scan.
 __global__ void __launch_bounds__(1024) k_map_cdf(int n, const double *map, double *cdf) {
     __shared__ double part[1024], pmax[1024];
     const int t = threadIdx.x;
@@ -1515,37 +1765,80 @@ __global__ void __launch_bounds__(1024) k_map_cdf(int n, const double *map, doub
     }
 }
 
+// Completes a problem from the host's part (by value) with what depends on
+// device data, and stores it.  The MAP source's measure is 2 pi sum |q| A; an
+// all-zero map launches nothing and normalises to zero; a NaN anywhere in
+// the map, or a weight bound above 2^32 once the equal-count launch's factor
+// max |q| / mean |q| is known, launches nothing and normalises to NaN.
+// Fixed-point scale fx = 2^(32 - e) with 2^e above the weight bound, so a
+// segment adds at most sqrt 2 * 2^32 in scaled units; a visit is flushed in
+// parts at flush_track * 2^32 <= 2^48, inside fixed_add's 2^51.  Every thread
+// also fills the problem's entries of the tile-to-problem table.
+__global__ void k_prob_setup(ProbDev h, ProbDev *out, uint32_t *tile_prob, uint32_t index) {
+    for (int k = threadIdx.x; k < h.ntiles; k += blockDim.x)
+        if (tile_prob) tile_prob[h.tile_base + k] = index;
+    if (threadIdx.x != 0) return;
+    bool usable = true;
+    double wb = h.wbound;
+    if (h.map) {
+        const double sum = h.cdf[h.npix - 1], mx = h.cdf[h.npix];
+        h.total = 2.0 * M_PI * sum * (double)h.dx * (double)h.dx;
+        h.src[0].cum = h.total;
+        h.inv_qbar = sum > 0.0 ? (double)h.npix / sum : 0.0;
+        if (h.flags & MC_FLAG_EQUAL_COUNT) wb *= mx * h.inv_qbar;
+        if (sum == 0.0) h.todo = 0;                    // a source of no power: the field is zero
+        else if (!(sum > 0.0) || !(mx < INFINITY)) usable = false;   // NaN or infinity in the map
+    }
+    if (!(wb <= 0x1p32)) usable = false;
+    int e = 0;
+    frexp(fmax(wb, 1.0), &e);   // 2^e > wb
+    h.fx = (float)ldexp(1.0, kFixBits - e);
+    h.fx_inv = ldexp(1.0, e - kFixBits);
+    h.flush_at = (float)ldexp(h.flush_track, kFixBits);
+    if (!usable) {
+        h.todo = 0;
+        h.scale = __builtin_nan("");
+    } else {
+        h.scale = h.todo ? h.total / (double)h.npk : 0.0;
+    }
+    *out = h;
+}
+
 // Normalise (Sec. 6: divide by the packet count; times the source measure and
 // the track-length-to-fluence factor 1/(dx Np) in pixel units) and transpose
 // [npix][K] -> [K][npix]; the adjoint output reads the mirrored direction,
-// (-1)^n on orders n >= 1.
-// A nonzero *range_errors (tiled mode: a job whose fixed-point tile tally may
-// have wrapped) turns the whole output into NaN.
-__global__ void k_normalise(int npix, int N, int adjoint, double scale, const double *t64,
-                            const unsigned long long *range_errors, double *out) {
+// (-1)^n on orders n >= 1.  A job whose fixed-point tile tally may have
+// wrapped (ledc[4]) or an overflowed queue turns the whole output into NaN.
+__global__ void k_normalise(const ProbDev *pd, int N, const GenCtl *ctl, double *out) {
+    const int npix = pd->npix;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= npix) return;
     const int K = 2 * N + 1;
-    const bool bad = range_errors && *range_errors;
+    const bool bad = pd->ledc[4] != 0 || (ctl && ctl->overflow);
+    const double scale = pd->scale / (double)pd->dx;
+    const double *t64 = pd->t64;
     for (int c = 0; c < K; ++c) {
         const int n = c <= N ? c : c - N;
-        const double f = (adjoint && (n & 1)) ? -scale : scale;
+        const double f = (pd->adjoint && (n & 1)) ? -scale : scale;
         out[(size_t)c * npix + i] = bad ? __builtin_nan("") : t64[(size_t)i * K + c] * f;
     }
 }
 
-__global__ void k_ledger_out(const double *led, const unsigned long long *ledc, double scale, mc_ledger *out) {
+__global__ void k_ledger_out(const ProbDev *pd, const GenCtl *ctl, uint32_t generations, mc_ledger *out) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double *led = pd->led;
+    const unsigned long long *ledc = pd->ledc;
     out->launched = led[0];
     out->absorbed = led[1];
     out->escaped = led[2];
     out->roulette_gain = led[3];
     out->roulette_loss = led[4];
-    out->scale = scale;
+    out->scale = pd->scale;
     out->packets = ledc[0];
     out->segments = ledc[1];
     out->visits = ledc[2];
     out->scatters = ledc[3];
+    out->generations = ctl ? (ctl->done ? ctl->gen_done : generations) : 0;
 }
 
 // Residual (Sec. 2, Sec. 6) with a deterministic single-block reduction of eps.
@@ -1639,13 +1932,14 @@ __global__ void k_philox_fill(uint64_t seed, uint32_t tag, uint64_t pid0, uint64
 }
 
 // ------------------------------------------------------------------ dispatch tables
-using TransportFn = void (*)(Params);
-using TraceFn = void (*)(Params, const uint64_t *, int, mc_event *, size_t, unsigned long long *);
-using FinishFn = void (*)(Params, uint32_t);
+using GridFn = void (*)(GridArgs);
+using TileFn = void (*)(Gen, int);
+using TraceFn = void (*)(const ProbDev *, const uint64_t *, int, mc_event *, size_t, unsigned long long *);
+using FinishFn = void (*)(Gen, int, int);
 
 template <int NH>
 struct Table {
-    static void fill(TransportFn *grid, TransportFn *tile, TraceFn *tr, FinishFn *fin) {
+    static void fill(GridFn *grid, TileFn *tile, TraceFn *tr, FinishFn *fin) {
         grid[NH] = k_transport_grid<NH>;
         tile[NH] = k_transport_tile<NH>;
         tr[NH] = k_trace<NH>;
@@ -1654,41 +1948,27 @@ struct Table {
     }
 };
 
+// Kernel entry points by harmonic order (filled once; never changed after).
 struct Kernels {
-    TransportFn grid[MC_NHARM_MAX + 1], tile[MC_NHARM_MAX + 1];
+    GridFn grid[MC_NHARM_MAX + 1];
+    TileFn tile[MC_NHARM_MAX + 1];
     TraceFn tr[MC_NHARM_MAX + 1];
     FinishFn fin[MC_NHARM_MAX + 1];
     Kernels() { Table<MC_NHARM_MAX>::fill(grid, tile, tr, fin); }
 };
 
 const Kernels &kernels() {
-    static Kernels k;
+    static const Kernels k;
     return k;
 }
 
 // ------------------------------------------------------------------ host helpers
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
-// Optional timing of the transport launches with HIP events recorded on the
-// launch stream (enabled by mc_profile_enable; read by mc_profile_read).
-struct Profile {
-    std::mutex mu;
-    bool on = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
-    double ms = 0;
-    uint64_t launches = 0;
-};
-Profile &profile_state() {
-    static Profile p;
-    return p;
-}
-
-// Tiled-mode sizing.  Tiles are square, as large as lets two workgroups of a
-// CU hold their tile's tally, medium and flush counts in LDS.
-// live packets per generation (on the 10^8-packet disc256 gradient 2^25
-// against 2^24: -1.8% time, 2^26 against 2^25: -1.1%; small runs unchanged
-// once the finisher threshold below is kept at 2^17).  The queues then take
-// ~13 GB of HBM.
+// Defaults of the tiled transport.  Live packets per generation: on the
+// 1e8-packet disc256 gradient 2^25 against 2^24: -1.8% time, 2^26 against
+// 2^25: -1.1%; small runs unchanged once the finisher threshold is kept at
+// 2^17.
 constexpr uint64_t kLiveMax = 1ull << 26;
 constexpr uint64_t kFinishMax = 1ull << 17;   // default finisher threshold: min(this, live / 128)
 constexpr uint64_t kGridMaxPackets = 1ull << 21;   // larger runs take the tiled transport
@@ -1699,61 +1979,75 @@ constexpr uint32_t kMaxVisitsPerStay = 64;    // a packet pauses after this many
 // more visits, so a wave does not idle behind its longest stay (measured on
 // the 256x256 disc: 8 beats 2, 4, 16 and no limit by 7-9%)
 constexpr uint32_t kTailVisits = 8;
+// generations enqueued per call unless the caller says: a base for the drain
+// of the longest histories plus a share per pool turnover (measured on the
+// disc256 workload: ~210 generations for 2.8e6 packets, ~390 for 1e8 at 2^26
+// live packets, ~720 for 1e9)
+constexpr uint32_t kGenBase = 448, kGenPerPool = 48;
 constexpr int kTileWavesMax = 256 * 16;       // bound on resident waves of the tiled kernel
 
-// Tuning knobs of the tiled mode.  Process-wide; set through mc_set_tuning()
-// (the autotuner) and initialised from the environment (RMC_LIVE, RMC_JOB,
-// RMC_MAXVIS, RMC_TAILVIS, RMC_TILE, RMC_FINISH) for measurement sweeps.  A
-// run takes one snapshot when its layout is computed.
+// The tuning a call runs with: the caller's fields, defaults where zero.
 struct TileTuning {
     uint64_t live = kLiveMax;
     uint32_t job = kJobSize, maxvis = kMaxVisitsPerStay, tailvis = kTailVisits;
     uint64_t finish = 0;   // 0: min(2^17, live / 128)
-    int tile = 0;   // 0: largest square tile for two workgroups per CU
-    uint64_t grid_max = kGridMaxPackets;   // whole-grid kernel only up to this many packets
-    // a visit whose accumulated track length times |weight| reaches flush_track
-    // pixels (in units of the run's weight bound) is flushed to the tile tally
-    // in parts; at most 2^16, which keeps every flush inside fixed_add's range
+    int tile = 0;          // 0: largest square tile for two workgroups per CU
+    uint64_t grid_max = kGridMaxPackets;
     double flush_track = kFlushTrackMax;
+    uint32_t max_gen = 0;      // 0: kGenBase + kGenPerPool per pool of live packets the run holds
+    uint32_t slice = kSlice;   // not a caller knob
 };
-TileTuning tuning_from_env() {
-    TileTuning v;
-    auto get = [](const char *n, uint64_t lo, uint64_t hi, uint64_t def) {
-        const char *e = std::getenv(n);
-        if (!e) return def;
-        const unsigned long long x = std::strtoull(e, nullptr, 10);
-        return (x >= lo && x <= hi) ? (uint64_t)x : def;
-    };
-    v.live = get("RMC_LIVE", 1024, 1ull << 26, v.live);
-    v.job = (uint32_t)get("RMC_JOB", 64, 1u << 20, v.job);
-    v.maxvis = (uint32_t)get("RMC_MAXVIS", 1, 1u << 30, v.maxvis);
-    v.tailvis = (uint32_t)get("RMC_TAILVIS", 1, 1u << 30, v.tailvis);
-    v.tile = (int)get("RMC_TILE", 1, 256, 0);
-    v.finish = get("RMC_FINISH", 1, 1ull << 26, 0);
-    return v;
-}
-struct TuningState {
-    std::mutex mu;
-    TileTuning t = tuning_from_env();
-};
-TuningState &tuning_state() {
-    static TuningState s;
-    return s;
-}
-TileTuning tuning_snapshot() {
-    TuningState &s = tuning_state();
-    std::lock_guard<std::mutex> g(s.mu);
-    return s.t;
+
+bool tuning_from(const mc_options *o, TileTuning &v) {
+    v = TileTuning();
+    if (!o || !o->tuning) return true;
+    const mc_tuning &t = *o->tuning;
+    if (t.live_packets && (t.live_packets < 1024 || t.live_packets > kLiveMax)) return false;
+    if (t.job_packets && (t.job_packets < 64 || t.job_packets > (1u << 20))) return false;
+    if (t.tile > 256 || t.finish_packets > kLiveMax || t.tail_visits > (1u << 30) || t.max_generations > 65536)
+        return false;
+    if (!(t.flush_track >= 0.f && t.flush_track <= (float)kFlushTrackMax)) return false;
+    if (t.live_packets) v.live = t.live_packets;
+    if (t.job_packets) v.job = t.job_packets;
+    if (t.max_visits) v.maxvis = t.max_visits;
+    if (t.tile) v.tile = (int)t.tile;
+    if (t.finish_packets) v.finish = t.finish_packets;
+    if (t.grid_max_packets) v.grid_max = t.grid_max_packets;
+    if (t.flush_track > 0.f) v.flush_track = (double)t.flush_track;
+    if (t.tail_visits) v.tailvis = t.tail_visits;
+    if (t.max_generations) v.max_gen = t.max_generations;
+    return true;
 }
 
-struct Layout {
-    size_t med, cdf, t64, led, ledc, counters, qa, qtile, qb, tcount, tcursor, jobs, qcnt, total;
-    uint64_t n_chunks;
-    bool tiled;
-    int tw, th, ntx, ntz, ntiles;
-    uint64_t live, cap_a, max_jobs;
-    size_t tile_lds;
-    TileTuning tt;   // the tuning this layout was computed with
+}  // namespace
+
+// Caller-owned timer of transport launches (see mc_timer_create).
+struct mc_timer {
+    std::mutex mu;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+    double ms = 0;
+    uint64_t launches = 0;
+};
+
+namespace {
+
+// Records HIP events around a transport launch when the call has a timer.
+struct LaunchTimer {
+    mc_timer *tm;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    explicit LaunchTimer(mc_timer *t) : tm(t) {}
+    mc_status begin(hipStream_t s) {
+        if (!tm) return MC_OK;
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return MC_ERR_DEVICE;
+        return hipEventRecord(e0, s) == hipSuccess ? MC_OK : MC_ERR_DEVICE;
+    }
+    mc_status end(hipStream_t s) {
+        if (!tm) return MC_OK;
+        if (hipEventRecord(e1, s) != hipSuccess) return MC_ERR_DEVICE;
+        std::lock_guard<std::mutex> g(tm->mu);
+        tm->pending.emplace_back(e0, e1);
+        return MC_OK;
+    }
 };
 
 // tile LDS: fixed-point sums [tw*th][K], medium [tw*th], flush counts [tw*th]
@@ -1762,22 +2056,28 @@ size_t tile_lds_bytes(int tw, int th, int K) {
     return tal + (size_t)tw * th * (sizeof(float4) + sizeof(uint32_t));
 }
 
-// Tiled transport unless the whole tally (8 bytes per value) fits one workgroup's LDS and the
-// run is small (the tiled mode's per-generation overhead is ~10 ms; measured
-// on a 32x32 pencil beam, the tiled mode overtakes the whole-grid kernel near
-// 2e6 packets and is 5x faster at 1e8).
+// Tiled transport unless the whole tally (8 bytes per value) fits one
+// workgroup's LDS and the run is small (the tiled mode's per-generation
+// overhead is ~10 ms; measured on a 32x32 pencil beam, the tiled mode
+// overtakes the whole-grid kernel near 2e6 packets and is 5x faster at 1e8).
 bool is_tiled(const mc_medium *m, const mc_run *run, const TileTuning &tt) {
     if ((size_t)m->nx * m->nz * (2 * run->n_harm + 1) * sizeof(double) > kLdsGridMax) return true;
     return run->n_packets > tt.grid_max;
 }
 
-// Whole-grid mode: medium, CDF, tally, ledger and per-chunk counters.
+// Whole-grid mode workspace: problem, medium, CDF, tally, ledger, per-chunk counters.
+struct Layout {
+    size_t pd, med, cdf, t64, led, ledc, counters, total;
+    uint64_t n_chunks;
+};
+
 Layout layout(const mc_medium *m, const mc_source *src, const mc_run *run) {
     Layout L{};
     const size_t npix = (size_t)m->nx * m->nz;
     const int K = 2 * run->n_harm + 1;
-    L.tiled = is_tiled(m, run, tuning_snapshot());
     size_t off = 0;
+    L.pd = off;
+    off = align_up(off + sizeof(ProbDev));
     L.med = off;
     off = align_up(off + npix * sizeof(float4));
     L.cdf = off;
@@ -1807,22 +2107,24 @@ struct BatchProblem {
 };
 
 // Tiled mode for a batch of problems sharing the harmonic order: per-problem
-// medium, CDF, tally and ledger; one packet pool, one set of queues and one
-// global tile index space (problem p owns tiles tile_base[p] ..).
+// descriptor, medium, CDF, tally and ledger; one packet pool (two alternating
+// record pools), one set of counters and one global tile index space (problem
+// p owns tiles tile_base[p] ..).
 struct BatchLayout {
     TileTuning tt;
     int N = 0, K = 0, t = 0, ntiles = 0;
     size_t tile_lds = 0;
-    uint64_t live = 0, cap_a = 0, max_jobs = 0, total_packets = 0;
+    uint64_t live = 0, cap_c = 0, cap_l = 0, max_jobs = 0, total_packets = 0;
     uint32_t job = 0;   // packets per job: the tuning's, halved for small pools
     std::vector<size_t> med, cdf, t64, led, ledc;
     std::vector<int> ntx, ntz, tile_base;
-    size_t probs = 0, tile_prob = 0, qcnt = 0, tcount = 0, tcursor = 0, jobs = 0, qa = 0, qtile = 0, qb = 0, total = 0;
+    size_t probs = 0, tile_prob = 0, ctl = 0, launched = 0, fin_cur = 0, tcount = 0, tcursor = 0, jobs = 0,
+           sidx = 0, pool[2] = {0, 0}, ptile[2] = {0, 0}, total = 0;
 };
 
-BatchLayout batch_layout(const BatchProblem *pb, int n) {
+BatchLayout batch_layout(const BatchProblem *pb, int n, const TileTuning &tt) {
     BatchLayout B;
-    B.tt = tuning_snapshot();
+    B.tt = tt;
     B.N = pb[0].run->n_harm;
     B.K = 2 * B.N + 1;
     int t = 1;
@@ -1852,30 +2154,43 @@ BatchLayout batch_layout(const BatchProblem *pb, int n) {
         B.total_packets += pb[i].run->n_packets;
     }
     B.live = std::min<uint64_t>(B.total_packets, B.tt.live);
-    B.cap_a = 2 * B.live + (uint64_t)kSlice * kTileWavesMax + 64ull * 64;
+    // carried region: every packet a generation moves may leave, plus the
+    // padding of the wave slices still open when it ends; launch region: at
+    // most `live` new packets per generation
+    B.cap_c = B.live + (uint64_t)B.tt.slice * kTileWavesMax + 64ull * 64;
+    B.cap_l = B.live;
     // a pool below 2^23 live packets spreads over too few jobs of the tuned
     // size to fill the device: half-size jobs (measured on 1e6- and 4e6-packet
     // disc256 gradients: -7%; 4096 stays better for full pools)
     B.job = (B.live < kSmallPool && B.tt.job >= 128) ? B.tt.job / 2 : B.tt.job;
     B.max_jobs = (uint64_t)B.ntiles + B.live / B.job + 2;
+    if (!B.tt.max_gen)
+        B.tt.max_gen = (uint32_t)std::min<uint64_t>(65536, kGenBase + kGenPerPool * ((B.total_packets + B.live - 1) / B.live));
     B.probs = off;
     off = align_up(off + (size_t)n * sizeof(ProbDev));
     B.tile_prob = off;
     off = align_up(off + (size_t)B.ntiles * sizeof(uint32_t));
-    B.qcnt = off;
-    off = align_up(off + 8 * sizeof(uint32_t));
+    // everything from ctl to the end of the cursors is zeroed at set-up
+    B.ctl = off;
+    off = align_up(off + sizeof(GenCtl));
+    B.launched = off;
+    off = align_up(off + (size_t)n * sizeof(uint64_t));
+    B.fin_cur = off;
+    off = align_up(off + (size_t)(n + 1) * sizeof(unsigned long long));
     B.tcount = off;
     off = align_up(off + (size_t)B.ntiles * sizeof(uint32_t));
     B.tcursor = off;
     off = align_up(off + (size_t)B.ntiles * sizeof(uint32_t));
     B.jobs = off;
     off = align_up(off + B.max_jobs * sizeof(uint4));
-    B.qa = off;
-    off = align_up(off + B.cap_a * sizeof(PacketRec));
-    B.qtile = off;
-    off = align_up(off + B.cap_a * sizeof(uint32_t));
-    B.qb = off;
-    off = align_up(off + B.live * sizeof(PacketRec));
+    B.sidx = off;
+    off = align_up(off + B.live * sizeof(uint32_t));
+    for (int p = 0; p < 2; ++p) {
+        B.pool[p] = off;
+        off = align_up(off + (B.cap_c + B.cap_l) * sizeof(PacketRec));
+        B.ptile[p] = off;
+        off = align_up(off + (B.cap_c + B.cap_l) * sizeof(uint32_t));
+    }
     B.total = off;
     return B;
 }
@@ -1884,8 +2199,8 @@ BatchLayout batch_layout(const BatchProblem *pb, int n) {
 // p = c0/2pi + (1/pi) sum (c_n cos nt + s_n sin nt) is at most
 // |c0| + 2 sum (|c_n| + |s_n|) (1 without a profile, and for pencils and
 // lines); a roulette survivor gains at most the factor m W_th.  The
-// equal-count map launch multiplies by q_i / mean |q|, bounded once max |q|
-// is known on the device.
+// equal-count map launch multiplies by q_i / mean |q|, bounded on the device
+// once max |q| is known (k_prob_setup).
 double weight_bound(const mc_source *src, int n_src, const mc_run *run) {
     double wb = 0.0;
     for (int s = 0; s < n_src; ++s) {
@@ -1936,15 +2251,14 @@ mc_status validate(const mc_medium *m, const mc_source *src, int n_src, const mc
         }
     }
     if (prof_total > kMaxProf) return MC_ERR_UNSUPPORTED;
-    // the fixed-point tile tally resolves weights up to 2^32 (see fixed_add)
+    // the fixed-point tallies resolve weights up to 2^32 (see fixed_add)
     if (!(weight_bound(src, n_src, run) <= 0x1p32)) return MC_ERR_UNSUPPORTED;
     return MC_OK;
 }
 
-// Build kernel parameters.  map_total: sum |map| (MAP source) computed on
-// the host for the normalisation; the device CDF is built separately.
-void fill_params(Params &P, const mc_medium *m, const mc_source *src, int n_src, const mc_run *run, int adjoint,
-                 double map_abs_sum) {
+// The host's part of a problem descriptor (k_prob_setup adds the rest).
+void fill_problem(ProbDev &P, const mc_medium *m, const mc_source *src, int n_src, const mc_run *run, int adjoint,
+                  double flush_track) {
     std::memset(&P, 0, sizeof(P));
     P.nx = m->nx;
     P.nz = m->nz;
@@ -1955,14 +2269,16 @@ void fill_params(Params &P, const mc_medium *m, const mc_source *src, int n_src,
     P.tag = run->stream_tag;
     P.flags = run->flags;
     P.seed = run->seed;
+    P.pid0 = run->first_packet_id;
+    P.npk = run->n_packets;
+    P.todo = run->n_packets;
     P.wth = run->w_threshold;
     P.rm = run->roulette_m;
     P.inv_rm = 1.f / run->roulette_m;
     P.wbound = weight_bound(src, n_src, run);
-    P.g = m->g_d;
+    P.flush_track = flush_track;
     double total = 0;
     int poff = 0;
-    const double A = (double)m->dx * m->dx;
     for (int s = 0; s < n_src; ++s) {
         const mc_source &q = src[s];
         SrcDev &d = P.src[s];
@@ -1987,37 +2303,16 @@ void fill_params(Params &P, const mc_medium *m, const mc_source *src, int n_src,
                 P.prof[poff++] = 1.f;
             }
         }
-        total += q.kind == MC_SRC_MAP ? 2.0 * M_PI * map_abs_sum * A : q.power;
+        if (q.kind != MC_SRC_MAP) total += q.power;   // a MAP source's measure is set on the device
         d.cum = total;
     }
     P.total = total;
-    if (n_src == 1 && src[0].kind == MC_SRC_MAP) {
-        P.map = src[0].map_d;
-        P.inv_qbar = map_abs_sum > 0 ? (double)P.npix / map_abs_sum : 0.0;
-    }
-}
-
-// Fixed-point scale of the visit sums (fixed_add): fx = 2^(32 - e) with 2^e
-// above the run's weight bound (times max |q| / mean |q| for the equal-count
-// map launch), so a segment adds at most sqrt 2 * 2^32 in scaled units; a
-// visit is flushed in parts at flush_track * 2^32 <= 2^48, inside 2^51.
-mc_status fixed_point(Params &P, double map_abs_max, double flush_track) {
-    double wb = P.wbound;
-    if ((P.flags & MC_FLAG_EQUAL_COUNT) && P.map) wb *= map_abs_max * P.inv_qbar;
-    if (!(wb <= 0x1p32)) return MC_ERR_UNSUPPORTED;
-    int e = 0;
-    std::frexp(std::max(wb, 1.0), &e);   // 2^e > wb
-    P.fx = (float)std::ldexp(1.0, kFixBits - e);
-    P.fx_inv = std::ldexp(1.0, e - kFixBits);
-    P.flush_at = (float)std::ldexp(flush_track, kFixBits);
-    return MC_OK;
+    if (n_src == 1 && src[0].kind == MC_SRC_MAP) P.map = src[0].map_d;
 }
 
 int occupancy_blocks(const void *fn, int block, size_t lds) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, block, lds) != hipSuccess ||
-        nb < 1)
-        nb = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, block, lds) != hipSuccess || nb < 1) nb = 1;
     return nb;
 }
 
@@ -2036,41 +2331,28 @@ mc_status launch_zero(void *p, size_t bytes, hipStream_t st) {
     return hipGetLastError() == hipSuccess ? MC_OK : MC_ERR_DEVICE;
 }
 
-// Record HIP events around a transport launch when timing is on.
-struct LaunchTimer {
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    bool on = false;
-    mc_status begin(hipStream_t s) {
-        Profile &pr = profile_state();
-        {
-            std::lock_guard<std::mutex> g(pr.mu);
-            on = pr.on;
-        }
-        if (!on) return MC_OK;
-        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return MC_ERR_DEVICE;
-        return hipEventRecord(e0, s) == hipSuccess ? MC_OK : MC_ERR_DEVICE;
-    }
-    mc_status end(hipStream_t s) {
-        if (!on) return MC_OK;
-        if (hipEventRecord(e1, s) != hipSuccess) return MC_ERR_DEVICE;
-        Profile &pr = profile_state();
-        std::lock_guard<std::mutex> g(pr.mu);
-        pr.pending.emplace_back(e0, e1);
-        return MC_OK;
-    }
-};
-
 mc_status set_lds_limit(const void *fn, size_t lds) {
     if (lds <= 64 * 1024) return MC_OK;
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess ? MC_OK
                                                                                                     : MC_ERR_DEVICE;
 }
 
+// Medium table, CDF of a MAP source, then the problem descriptor.
+mc_status setup_problem(const ProbDev &host, ProbDev *pd_d, uint32_t *tile_prob, uint32_t index, const float *mua,
+                        const float *mus, const float *g, hipStream_t s) {
+    hipLaunchKernelGGL(k_setup_medium, dim3((host.npix + 255) / 256), dim3(256), 0, s, host.npix, host.dx, mua, mus, g,
+                       const_cast<float4 *>(host.med));
+    if (host.map)
+        hipLaunchKernelGGL(k_map_cdf, dim3(1), dim3(1024), 0, s, host.npix, host.map, const_cast<double *>(host.cdf));
+    hipLaunchKernelGGL(k_prob_setup, dim3(1), dim3(256), 0, s, host, pd_d, tile_prob, index);
+    return hipGetLastError() == hipSuccess ? MC_OK : MC_ERR_DEVICE;
+}
+
 // Whole-grid mode: persistent launches over chunks of packets.
-mc_status run_grid(Params &P, const Layout &L, const mc_run *run, char *base, hipStream_t s) {
-    const int N = run->n_harm, K = 2 * N + 1;
-    const TransportFn fn = kernels().grid[N];
-    const size_t lds = (size_t)P.npix * K * sizeof(double);
+mc_status run_grid(const ProbDev *pd, const Layout &L, const mc_run *run, mc_timer *timer, char *base,
+                   size_t lds, hipStream_t s) {
+    const int N = run->n_harm;
+    const GridFn fn = kernels().grid[N];
     mc_status st = set_lds_limit(reinterpret_cast<const void *>(fn), lds);
     if (st != MC_OK) return st;
     const int block = grid_block(N);
@@ -2079,313 +2361,174 @@ mc_status run_grid(Params &P, const Layout &L, const mc_run *run, char *base, hi
     for (uint64_t c = 0; c < L.n_chunks; ++c) {
         const uint64_t a = c * kChunk;
         const uint64_t n = std::min<uint64_t>(kChunk, run->n_packets - a);
-        P.pid0 = run->first_packet_id + a;
-        P.npk = n;
-        P.counter = reinterpret_cast<unsigned long long *>(base + L.counters) + c;
+        GridArgs A{pd, run->first_packet_id + a, n, reinterpret_cast<unsigned long long *>(base + L.counters) + c};
         const uint64_t want = (n + block - 1) / block;
         const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)cus * occ));
-        LaunchTimer tm;
+        LaunchTimer tm(timer);
         if ((st = tm.begin(s)) != MC_OK) return st;
-        hipLaunchKernelGGL(fn, dim3(grid), dim3(block), lds, s, P);
+        hipLaunchKernelGGL(fn, dim3(grid), dim3(block), lds, s, A);
         if ((st = tm.end(s)) != MC_OK) return st;
         if (hipGetLastError() != hipSuccess) return MC_ERR_DEVICE;
     }
     return MC_OK;
 }
 
-// Tiled mode: host-driven generations over one packet pool shared by every
-// problem of the batch (launch, sort by tile, transport), one stream
-// synchronisation per generation to read the queue length.
-mc_status run_batch(const BatchProblem *pb, int n, void *ws, size_t ws_bytes, hipStream_t s) {
+// Tiled mode: every problem of the batch in one packet pool.  The host
+// enqueues the set-up, max_generations generations (each: launch and count,
+// sort, transport -- steered by the device control block, see GenCtl), the
+// finisher, and the normalisation, and returns without waiting.
+mc_status run_batch(const BatchProblem *pb, int n, const TileTuning &tt, mc_timer *timer, void *ws, size_t ws_bytes,
+                    hipStream_t s) {
     for (int i = 0; i < n; ++i) {
         mc_status st = validate(pb[i].m, pb[i].src, pb[i].n_src, pb[i].run);
         if (st != MC_OK) return st;
         if (!pb[i].coeffs || pb[i].run->n_harm != pb[0].run->n_harm) return MC_ERR_INVALID_ARG;
     }
-    const BatchLayout B = batch_layout(pb, n);
+    const BatchLayout B = batch_layout(pb, n, tt);
     if (!ws || ws_bytes < B.total || (reinterpret_cast<uintptr_t>(ws) & 255)) return MC_ERR_WORKSPACE;
-    if (B.tile_lds > kLdsTileMax || B.live > 0xFFFFFFFFull / 4) return MC_ERR_UNSUPPORTED;
+    if (B.tile_lds > kLdsTileMax || B.cap_c + B.cap_l > 0xFFFFFFF0ull) return MC_ERR_UNSUPPORTED;
     char *base = static_cast<char *>(ws);
     const int N = B.N;
     mc_status st;
-    // per problem: zero tally and ledger, medium table, CDF of a map source
-    std::vector<Params> PP(n);
-    std::vector<ProbDev> PD(n);
-    std::vector<uint32_t> tile_prob(B.ntiles);
-    std::vector<uint64_t> todo(n), launched(n, 0);
+    ProbDev *probs_d = reinterpret_cast<ProbDev *>(base + B.probs);
+    uint32_t *tile_prob = reinterpret_cast<uint32_t *>(base + B.tile_prob);
+    GenCtl *ctl = reinterpret_cast<GenCtl *>(base + B.ctl);
+    // counters, cursors and tile counts start at zero; the control block knows the total to launch
+    if ((st = launch_zero(base + B.ctl, B.tcursor - B.ctl, s)) != MC_OK) return st;
     for (int i = 0; i < n; ++i) {
         const mc_medium *m = pb[i].m;
         const int npix = m->nx * m->nz;
         if ((st = launch_zero(base + B.t64[i], (size_t)npix * B.K * sizeof(double), s)) != MC_OK) return st;
         if ((st = launch_zero(base + B.led[i], B.ledc[i] + 8 * sizeof(unsigned long long) - B.led[i], s)) != MC_OK)
             return st;
-        hipLaunchKernelGGL(k_setup_medium, dim3((npix + 255) / 256), dim3(256), 0, s, npix, m->dx, m->mua_d,
-                           m->mus_d, m->g_d, reinterpret_cast<float4 *>(base + B.med[i]));
-        double map_abs_sum = 0, map_abs_max = 0;
-        todo[i] = pb[i].run->n_packets;
-        if (pb[i].src[0].kind == MC_SRC_MAP) {
-            double *cdf = reinterpret_cast<double *>(base + B.cdf[i]);
-            hipLaunchKernelGGL(k_map_cdf, dim3(1), dim3(1024), 0, s, npix, pb[i].src[0].map_d, cdf);
-            // the normalisation needs sum |q| (the last CDF entry), the weight bound max |q|
-            double h2[2];
-            if (hipMemcpyAsync(h2, cdf + npix - 1, 2 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
-                hipStreamSynchronize(s) != hipSuccess)
-                return MC_ERR_DEVICE;
-            map_abs_sum = h2[0];
-            map_abs_max = h2[1];
-            if (map_abs_sum == 0.0) todo[i] = 0;   // an all-zero source: the field is zero
-            else if (!(map_abs_sum > 0)) return MC_ERR_INVALID_ARG;   // NaN in the map
-        }
-        Params &P = PP[i];
-        fill_params(P, m, pb[i].src, pb[i].n_src, pb[i].run, pb[i].adjoint, map_abs_sum);
-        if ((st = fixed_point(P, map_abs_max, B.tt.flush_track)) != MC_OK) return st;
+        ProbDev P;
+        fill_problem(P, m, pb[i].src, pb[i].n_src, pb[i].run, pb[i].adjoint, tt.flush_track);
+        P.ntx = B.ntx[i];
+        P.tile_base = B.tile_base[i];
+        P.ntiles = B.ntx[i] * B.ntz[i];
         P.med = reinterpret_cast<const float4 *>(base + B.med[i]);
+        P.cdf = reinterpret_cast<const double *>(base + B.cdf[i]);
         P.t64 = reinterpret_cast<double *>(base + B.t64[i]);
         P.led = reinterpret_cast<double *>(base + B.led[i]);
         P.ledc = reinterpret_cast<unsigned long long *>(base + B.ledc[i]);
-        P.cdf = reinterpret_cast<const double *>(base + B.cdf[i]);
-        P.tw = P.th = B.t;
-        P.ntx = B.ntx[i];
-        P.ntiles = B.ntiles;
-        P.tile_base = B.tile_base[i];
-        P.prob = (uint32_t)i;
-        P.qa = reinterpret_cast<PacketRec *>(base + B.qa);
-        P.qtile = reinterpret_cast<uint32_t *>(base + B.qtile);
-        P.qb = reinterpret_cast<PacketRec *>(base + B.qb);
-        P.qcnt = reinterpret_cast<uint32_t *>(base + B.qcnt);
-        P.tile_count = reinterpret_cast<uint32_t *>(base + B.tcount);
-        P.tile_cursor = reinterpret_cast<uint32_t *>(base + B.tcursor);
-        P.jobs = reinterpret_cast<uint4 *>(base + B.jobs);
-        P.probs = reinterpret_cast<const ProbDev *>(base + B.probs);
-        P.tile_prob = reinterpret_cast<const uint32_t *>(base + B.tile_prob);
-        P.cap_a = (uint32_t)B.cap_a;
-        P.cap_b = (uint32_t)B.live;
-        P.job_size = B.job;
-        P.max_visits = B.tt.maxvis;
-        P.tail_visits = B.tt.tailvis;
-        ProbDev &d = PD[i];
-        d.nx = m->nx;
-        d.nz = m->nz;
-        d.ntx = B.ntx[i];
-        d.tile_base = B.tile_base[i];
-        d.tag = P.tag;
-        d.flags = P.flags;
-        d.seed = P.seed;
-        d.wth = P.wth;
-        d.rm = P.rm;
-        d.inv_rm = P.inv_rm;
-        d.flush_at = P.flush_at;
-        d.fx = P.fx;
-        d.fx_inv = P.fx_inv;
-        d.med = P.med;
-        d.g = P.g;
-        d.t64 = P.t64;
-        d.led = P.led;
-        d.ledc = P.ledc;
-        for (int k = 0; k < B.ntx[i] * B.ntz[i]; ++k) tile_prob[B.tile_base[i] + k] = (uint32_t)i;
+        if ((st = setup_problem(P, probs_d + i, tile_prob, (uint32_t)i, m->mua_d, m->mus_d, m->g_d, s)) != MC_OK)
+            return st;
     }
-    if ((st = launch_zero(base + B.qcnt, 8 * sizeof(uint32_t), s)) != MC_OK) return st;
-    if ((st = launch_zero(base + B.tcount, (size_t)B.ntiles * sizeof(uint32_t), s)) != MC_OK) return st;
-    if (hipMemcpyAsync(base + B.probs, PD.data(), (size_t)n * sizeof(ProbDev), hipMemcpyHostToDevice, s) !=
-            hipSuccess ||
-        hipMemcpyAsync(base + B.tile_prob, tile_prob.data(), (size_t)B.ntiles * sizeof(uint32_t),
-                       hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)   // the host arrays go out of scope below
-        return MC_ERR_DEVICE;
-    if (hipGetLastError() != hipSuccess) return MC_ERR_DEVICE;
+    // total packets to launch (problems whose map has no power launch none:
+    // the control block learns this from the descriptors on the device)
+    Gen G{};
+    G.tw = G.th = B.t;
+    G.ntiles = B.ntiles;
+    G.nprob = n;
+    G.live = (uint32_t)B.live;
+    G.cap_c = (uint32_t)B.cap_c;
+    G.cap_l = (uint32_t)B.cap_l;
+    G.job_size = B.job;
+    G.max_visits = B.tt.maxvis;
+    G.tail_visits = B.tt.tailvis;
+    G.finish_at = (uint32_t)(B.tt.finish ? B.tt.finish : std::min<uint64_t>(kFinishMax, B.tt.live / 128));
+    G.slice = B.tt.slice;
+    G.probs = probs_d;
+    G.tile_prob = tile_prob;
+    for (int p = 0; p < 2; ++p) {
+        G.pool[p] = reinterpret_cast<PacketRec *>(base + B.pool[p]);
+        G.ptile[p] = reinterpret_cast<uint32_t *>(base + B.ptile[p]);
+    }
+    G.sidx = reinterpret_cast<uint32_t *>(base + B.sidx);
+    G.tile_count = reinterpret_cast<uint32_t *>(base + B.tcount);
+    G.tile_cursor = reinterpret_cast<uint32_t *>(base + B.tcursor);
+    G.jobs = reinterpret_cast<uint4 *>(base + B.jobs);
+    G.max_jobs = (uint32_t)B.max_jobs;
+    G.ctl = ctl;
+    G.launched = reinterpret_cast<uint64_t *>(base + B.launched);
+    G.fin_cur = reinterpret_cast<unsigned long long *>(base + B.fin_cur);
+    hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(1), 0, s, G);
 
-    const TransportFn fn = kernels().tile[N];
+    const TileFn fn = kernels().tile[N];
     if ((st = set_lds_limit(reinterpret_cast<const void *>(fn), B.tile_lds)) != MC_OK) return st;
     const int occ = occupancy_blocks(reinterpret_cast<const void *>(fn), kBlockTile, B.tile_lds);
     const int cus = device_cus();
     const unsigned tgrid = (unsigned)std::max(1, std::min(cus * occ, kTileWavesMax / (kBlockTile / 64)));
-    const unsigned bgrid = (unsigned)std::min<uint64_t>((B.cap_a + 255) / 256, 4096);
-    const unsigned cgrid = (unsigned)std::min<uint64_t>((B.cap_a + 255) / 256, 4 * (uint64_t)cus);
-    const Params &P0 = PP[0];   // the sort and transport kernels read only batch-wide fields
-    static thread_local uint32_t *host_cnt = nullptr;   // two slots of the 8 queue counters
-    if (!host_cnt && hipHostMalloc(reinterpret_cast<void **>(&host_cnt), 16 * sizeof(uint32_t)) != hipSuccess)
-        return MC_ERR_DEVICE;
-    struct CountEvents {   // one event per counter slot, on the device of this call
-        hipEvent_t e[2] = {nullptr, nullptr};
-        ~CountEvents() {
-            for (hipEvent_t x : e)
-                if (x) (void)hipEventDestroy(x);
-        }
-    } cev;
-    for (hipEvent_t &x : cev.e)
-        if (hipEventCreateWithFlags(&x, hipEventDisableTiming) != hipSuccess) return MC_ERR_DEVICE;
-    // the tail is handed to the finisher at a fixed count (the tuning's pool
-    // size / 128, 131072 by default) whatever the run's size: a small run whose
-    // pool is small would otherwise spend hundreds of latency-bound
-    // generations on its last few thousand packets (measured: a 1e6-packet
-    // disc256 gradient 241 -> 173 ms)
-    const uint64_t finish_at = B.tt.finish ? B.tt.finish : std::min<uint64_t>(kFinishMax, B.tt.live / 128);
-    uint64_t total_todo = 0, total_launched = 0, carried = 0;
-    uint32_t n_rec = 0;   // records in the unsorted queue after the last generation read
-    for (int i = 0; i < n; ++i) total_todo += todo[i];
-    // one generation: sort the queue by tile, transport, then the queue
-    // counters are copied to host slot `slot` and its event recorded
-    auto enqueue_gen = [&](int slot) -> mc_status {
-        hipLaunchKernelGGL(k_bin_count, dim3(cgrid), dim3(256), 0, s, P0);
-        hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, s, P0);
-        hipLaunchKernelGGL(k_bin_scatter, dim3(bgrid), dim3(256), 0, s, P0);
-        LaunchTimer tm;
-        mc_status r;
-        if ((r = tm.begin(s)) != MC_OK) return r;
-        hipLaunchKernelGGL(fn, dim3(tgrid), dim3(kBlockTile), B.tile_lds, s, P0);
-        if ((r = tm.end(s)) != MC_OK) return r;
+    const unsigned cgrid = (unsigned)std::max(1, cus);
+    const unsigned sgrid = (unsigned)std::max(1, 4 * cus);
+    for (uint32_t g = 0; g < B.tt.max_gen; ++g) {
+        hipLaunchKernelGGL(k_gen_count, dim3(cgrid), dim3(kGenBlock), 0, s, G, (int)g);
+        hipLaunchKernelGGL(k_gen_scatter, dim3(sgrid), dim3(256), 0, s, G, (int)g);
+        LaunchTimer tm(timer);
+        if ((st = tm.begin(s)) != MC_OK) return st;
+        hipLaunchKernelGGL(fn, dim3(tgrid), dim3(kBlockTile), B.tile_lds, s, G, (int)g);
+        if ((st = tm.end(s)) != MC_OK) return st;
         if (hipGetLastError() != hipSuccess) return MC_ERR_DEVICE;
-        if (hipMemcpyAsync(host_cnt + 8 * slot, P0.qcnt, 8 * sizeof(uint32_t), hipMemcpyDeviceToHost, s) !=
-                hipSuccess ||
-            hipEventRecord(cev.e[slot], s) != hipSuccess)
-            return MC_ERR_DEVICE;
-        return MC_OK;
-    };
-    auto read_gen = [&](int slot) -> mc_status {
-        if (hipEventSynchronize(cev.e[slot]) != hipSuccess) return MC_ERR_DEVICE;
-        const uint32_t *c = host_cnt + 8 * slot;
-        if (c[4]) return MC_ERR_DEVICE;   // queue overflow (not expected by construction)
-        carried = c[6];   // valid records; qa also holds the padding of partly used slices
-        n_rec = (uint32_t)std::min<uint64_t>(c[0], B.cap_a);
-        return MC_OK;
-    };
-    // Refill phase: one generation at a time, each refill sized by the count
-    // the previous generation left.
-    for (uint64_t gen = 0; total_launched < total_todo; ++gen) {
-        if (gen > (1ull << 32)) return MC_ERR_DEVICE;
-        uint64_t budget = carried < B.live ? B.live - carried : 0;
-        for (int i = 0; i < n && budget; ++i) {   // refill the pool, problems in order
-            const uint64_t n_new = std::min<uint64_t>(budget, todo[i] - launched[i]);
-            if (!n_new) continue;
-            const unsigned lgrid = (unsigned)std::min<uint64_t>((n_new + 255) / 256, 8 * (uint64_t)cus);
-            hipLaunchKernelGGL(k_tile_launch, dim3(lgrid), dim3(256), 0, s, PP[i],
-                               pb[i].run->first_packet_id + launched[i], (uint32_t)n_new);
-            launched[i] += n_new;
-            total_launched += n_new;
-            budget -= n_new;
-        }
-        if (total_launched == total_todo) break;   // this generation is the drain's first
-        if ((st = enqueue_gen(0)) != MC_OK || (st = read_gen(0)) != MC_OK) return st;
     }
-    // Drain phase (every packet launched): generations run back to back, the
-    // host reading one generation's counters while the next already runs on
-    // its output, so the device does not wait for the host in between.  Once
-    // at most finish_at packets remain, the generation in flight completes and
-    // the finisher takes what it leaves.
-    if (total_todo > 0) {
-        int inflight = 0, head = 0;   // generations enqueued and not yet read; slot of the oldest
-        for (uint64_t gen = 0;; ++gen) {
-            if (gen > (1ull << 32)) return MC_ERR_DEVICE;
-            while (inflight < 2) {
-                if ((st = enqueue_gen((head + inflight) & 1)) != MC_OK) return st;
-                ++inflight;
-            }
-            if ((st = read_gen(head)) != MC_OK) return st;
-            head ^= 1;
-            --inflight;
-            if (carried <= finish_at) {
-                if ((st = read_gen(head)) != MC_OK) return st;
-                break;
-            }
-        }
+    // the finisher: the records left, then any packets the generations did not launch
+    const FinishFn ff = kernels().fin[N];
+    const size_t flds = (size_t)(kBlockFinish / 64) * 64 * (2 * N + 1) * sizeof(float) +
+                        2 * (kBlockFinish / 64) * 64 * sizeof(int);
+    if ((st = set_lds_limit(reinterpret_cast<const void *>(ff), flds)) != MC_OK) return st;
+    const int focc = occupancy_blocks(reinterpret_cast<const void *>(ff), kBlockFinish, flds);
+    const unsigned fgrid = (unsigned)std::max<uint64_t>(
+        1, std::min<uint64_t>((G.finish_at + kBlockFinish - 1) / kBlockFinish + 1, (uint64_t)cus * focc));
+    {
+        LaunchTimer tf(timer);
+        if ((st = tf.begin(s)) != MC_OK) return st;
+        hipLaunchKernelGGL(ff, dim3(fgrid), dim3(kBlockFinish), flds, s, G, (int)B.tt.max_gen, -1);
+        if ((st = tf.end(s)) != MC_OK) return st;
     }
-    if (carried > 0) {
-        // finish the remaining packets without migration, one launch per
-        // problem (each takes only its own records; qcnt[5]: record cursor)
-        const FinishFn ff = kernels().fin[N];
-        const size_t flds = (size_t)(kBlockFinish / 64) * 64 * (2 * N + 1) * sizeof(float) +
-                            (kBlockFinish / 64) * 64 * sizeof(int);
-        if ((st = set_lds_limit(reinterpret_cast<const void *>(ff), flds)) != MC_OK) return st;
-        const int focc = occupancy_blocks(reinterpret_cast<const void *>(ff), kBlockFinish, flds);
-        const unsigned fgrid = (unsigned)std::max<uint64_t>(
-            1, std::min<uint64_t>((carried + kBlockFinish - 1) / kBlockFinish, (uint64_t)cus * focc));
-        for (int i = 0; i < n; ++i) {
-            if (!todo[i]) continue;
-            if ((st = launch_zero(PP[i].qcnt + 5, sizeof(uint32_t), s)) != MC_OK) return st;
-            LaunchTimer tf;
-            if ((st = tf.begin(s)) != MC_OK) return st;
-            hipLaunchKernelGGL(ff, dim3(fgrid), dim3(kBlockFinish), flds, s, PP[i], n_rec);
-            if ((st = tf.end(s)) != MC_OK) return st;
-            if (hipGetLastError() != hipSuccess) return MC_ERR_DEVICE;
-        }
-    }
+    const unsigned fgrid_all = (unsigned)std::max(1, cus * focc);
+    for (int i = 0; i < n; ++i)
+        hipLaunchKernelGGL(ff, dim3(fgrid_all), dim3(kBlockFinish), flds, s, G, (int)B.tt.max_gen, i);
     // normalisation and ledgers
     for (int i = 0; i < n; ++i) {
-        const mc_medium *m = pb[i].m;
-        const int npix = m->nx * m->nz;
-        const double scale = PP[i].total / ((double)pb[i].run->n_packets);
-        hipLaunchKernelGGL(k_normalise, dim3((npix + 255) / 256), dim3(256), 0, s, npix, N, pb[i].adjoint,
-                           todo[i] ? scale / (double)m->dx : 0.0, PP[i].t64, PP[i].ledc + 4, pb[i].coeffs);
+        const int npix = pb[i].m->nx * pb[i].m->nz;
+        hipLaunchKernelGGL(k_normalise, dim3((npix + 255) / 256), dim3(256), 0, s, probs_d + i, N,
+                           (const GenCtl *)ctl, pb[i].coeffs);
         if (pb[i].ledger)
-            hipLaunchKernelGGL(k_ledger_out, dim3(1), dim3(1), 0, s, PP[i].led, PP[i].ledc, todo[i] ? scale : 0.0,
-                               pb[i].ledger);
+            hipLaunchKernelGGL(k_ledger_out, dim3(1), dim3(1), 0, s, (const ProbDev *)(probs_d + i), (const GenCtl *)ctl,
+                               B.tt.max_gen, pb[i].ledger);
     }
     return hipGetLastError() == hipSuccess ? MC_OK : MC_ERR_DEVICE;
 }
 
-mc_status run_mc(const mc_medium *m, const mc_source *src, int n_src, const mc_run *run, double *coeffs,
-                 mc_ledger *ledger, void *ws, size_t ws_bytes, void *stream, int adjoint) {
+mc_status run_mc(const mc_medium *m, const mc_source *src, int n_src, const mc_run *run, const TileTuning &tt,
+                 mc_timer *timer, double *coeffs, mc_ledger *ledger, void *ws, size_t ws_bytes, hipStream_t s,
+                 int adjoint) {
     mc_status st = validate(m, src, n_src, run);
     if (st != MC_OK) return st;
     if (!coeffs) return MC_ERR_INVALID_ARG;
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    if (is_tiled(m, run, tuning_snapshot())) {
+    if (is_tiled(m, run, tt)) {
         const BatchProblem one{m, src, n_src, run, adjoint, coeffs, ledger};
-        return run_batch(&one, 1, ws, ws_bytes, s);
+        return run_batch(&one, 1, tt, timer, ws, ws_bytes, s);
     }
     const Layout L = layout(m, src, run);
     if (!ws || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255)) return MC_ERR_WORKSPACE;
     char *base = static_cast<char *>(ws);
     const int npix = m->nx * m->nz;
     const int N = run->n_harm;
-
     // zero the tally, ledger and chunk counters
     if ((st = launch_zero(base + L.t64, L.counters + L.n_chunks * sizeof(unsigned long long) - L.t64, s)) != MC_OK)
         return st;
-    hipLaunchKernelGGL(k_setup_medium, dim3((npix + 255) / 256), dim3(256), 0, s, npix, m->dx, m->mua_d, m->mus_d, m->g_d,
-                       reinterpret_cast<float4 *>(base + L.med));
-    double map_abs_sum = 0, map_abs_max = 0;
-    if (src[0].kind == MC_SRC_MAP) {
-        double *cdf = reinterpret_cast<double *>(base + L.cdf);
-        hipLaunchKernelGGL(k_map_cdf, dim3(1), dim3(1024), 0, s, npix, src[0].map_d, cdf);
-        // the normalisation needs sum |q| (the last CDF entry), the weight bound max |q|
-        double h2[2];
-        if (hipMemcpyAsync(h2, cdf + npix - 1, 2 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess)
-            return MC_ERR_DEVICE;
-        map_abs_sum = h2[0];
-        map_abs_max = h2[1];
-        if (map_abs_sum == 0.0) {   // an all-zero source: the field is zero
-            st = launch_zero(coeffs, (size_t)npix * (2 * N + 1) * sizeof(double), s);
-            if (st == MC_OK && ledger) st = launch_zero(ledger, sizeof(mc_ledger), s);
-            return st;
-        }
-        if (!(map_abs_sum > 0)) return MC_ERR_INVALID_ARG;   // NaN in the map
-    }
-    if (hipGetLastError() != hipSuccess) return MC_ERR_DEVICE;
-    Params P;
-    fill_params(P, m, src, n_src, run, adjoint, map_abs_sum);
-    if ((st = fixed_point(P, map_abs_max, tuning_snapshot().flush_track)) != MC_OK) return st;
+    ProbDev P;
+    fill_problem(P, m, src, n_src, run, adjoint, tt.flush_track);
     P.med = reinterpret_cast<const float4 *>(base + L.med);
+    P.cdf = reinterpret_cast<const double *>(base + L.cdf);
     P.t64 = reinterpret_cast<double *>(base + L.t64);
     P.led = reinterpret_cast<double *>(base + L.led);
     P.ledc = reinterpret_cast<unsigned long long *>(base + L.ledc);
-    P.cdf = reinterpret_cast<const double *>(base + L.cdf);
-
-    st = run_grid(P, L, run, base, s);
-    if (st != MC_OK) return st;
-    const double scale = P.total / ((double)run->n_packets);
-    hipLaunchKernelGGL(k_normalise, dim3((npix + 255) / 256), dim3(256), 0, s, npix, N, adjoint,
-                       scale / (double)m->dx, P.t64, P.ledc + 4, coeffs);
+    ProbDev *pd = reinterpret_cast<ProbDev *>(base + L.pd);
+    if ((st = setup_problem(P, pd, nullptr, 0, m->mua_d, m->mus_d, m->g_d, s)) != MC_OK) return st;
+    const size_t lds = (size_t)npix * (2 * N + 1) * sizeof(double);
+    if ((st = run_grid(pd, L, run, timer, base, lds, s)) != MC_OK) return st;
+    hipLaunchKernelGGL(k_normalise, dim3((npix + 255) / 256), dim3(256), 0, s, (const ProbDev *)pd, N,
+                       (const GenCtl *)nullptr, coeffs);
     if (ledger)
-        hipLaunchKernelGGL(k_ledger_out, dim3(1), dim3(1), 0, s, P.led, P.ledc, scale, ledger);
+        hipLaunchKernelGGL(k_ledger_out, dim3(1), dim3(1), 0, s, (const ProbDev *)pd, (const GenCtl *)nullptr, 0u, ledger);
     return hipGetLastError() == hipSuccess ? MC_OK : MC_ERR_DEVICE;
 }
 
-// Discrete-ordinates runs (mc_run_binned): medium, CDF of a map source, raw
-// bins [n_bins][npix], ledger and per-chunk packet counters.
+// Discrete-ordinates runs (mc_run_binned): problem, medium, CDF of a map
+// source, raw bins [n_bins][npix], ledger and per-chunk packet counters.
 struct BinnedLayout {
-    size_t med, cdf, raw, led, ledc, counters, total;
+    size_t pd, med, cdf, raw, led, ledc, counters, total;
     uint64_t n_chunks;
 };
 
@@ -2393,6 +2536,8 @@ BinnedLayout binned_layout(const mc_medium *m, const mc_source *src, const mc_ru
     BinnedLayout L{};
     const size_t npix = (size_t)m->nx * m->nz;
     size_t off = 0;
+    L.pd = off;
+    off = align_up(off + sizeof(ProbDev));
     L.med = off;
     off = align_up(off + npix * sizeof(float4));
     L.cdf = off;
@@ -2423,48 +2568,29 @@ mc_status run_binned(const mc_medium *m, const mc_source *src, int n_src, const 
     const int npix = m->nx * m->nz;
     const size_t nout = (size_t)npix * n_bins;
     if ((st = launch_zero(base + L.raw, L.total - L.raw, s)) != MC_OK) return st;   // bins, ledger, counters
-    hipLaunchKernelGGL(k_setup_medium, dim3((npix + 255) / 256), dim3(256), 0, s, npix, m->dx, m->mua_d, m->mus_d,
-                       m->g_d, reinterpret_cast<float4 *>(base + L.med));
-    double map_abs_sum = 0;
-    if (src[0].kind == MC_SRC_MAP) {
-        double *cdf = reinterpret_cast<double *>(base + L.cdf);
-        hipLaunchKernelGGL(k_map_cdf, dim3(1), dim3(1024), 0, s, npix, src[0].map_d, cdf);
-        if (hipMemcpyAsync(&map_abs_sum, cdf + npix - 1, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess)
-            return MC_ERR_DEVICE;
-        if (map_abs_sum == 0.0) {   // an all-zero source: the field is zero
-            st = launch_zero(out, nout * sizeof(double), s);
-            if (st == MC_OK && ledger) st = launch_zero(ledger, sizeof(mc_ledger), s);
-            return st;
-        }
-        if (!(map_abs_sum > 0)) return MC_ERR_INVALID_ARG;   // NaN in the map
-    }
-    Params P;
-    fill_params(P, m, src, n_src, run, adjoint, map_abs_sum);
+    ProbDev P;
+    fill_problem(P, m, src, n_src, run, adjoint, kFlushTrackMax);
     P.med = reinterpret_cast<const float4 *>(base + L.med);
+    P.cdf = reinterpret_cast<const double *>(base + L.cdf);
     P.led = reinterpret_cast<double *>(base + L.led);
     P.ledc = reinterpret_cast<unsigned long long *>(base + L.ledc);
-    P.cdf = reinterpret_cast<const double *>(base + L.cdf);
+    ProbDev *pd = reinterpret_cast<ProbDev *>(base + L.pd);
+    if ((st = setup_problem(P, pd, nullptr, 0, m->mua_d, m->mus_d, m->g_d, s)) != MC_OK) return st;
     double *raw = reinterpret_cast<double *>(base + L.raw);
     const int cus = device_cus();
     const int occ = occupancy_blocks(reinterpret_cast<const void *>(&k_transport_binned), 256, 0);
     for (uint64_t c = 0; c < L.n_chunks; ++c) {
         const uint64_t a = c * kChunk;
         const uint64_t n = std::min<uint64_t>(kChunk, run->n_packets - a);
-        P.pid0 = run->first_packet_id + a;
-        P.npk = n;
-        P.counter = reinterpret_cast<unsigned long long *>(base + L.counters) + c;
+        GridArgs A{pd, run->first_packet_id + a, n, reinterpret_cast<unsigned long long *>(base + L.counters) + c};
         const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((n + 255) / 256, (uint64_t)cus * occ));
-        hipLaunchKernelGGL(k_transport_binned, dim3(grid), dim3(256), 0, s, P, n_bins, raw);
+        hipLaunchKernelGGL(k_transport_binned, dim3(grid), dim3(256), 0, s, A, n_bins, raw);
         if (hipGetLastError() != hipSuccess) return MC_ERR_DEVICE;
     }
-    // as the coefficients (source measure / packets, track length in pixel
-    // units over the pixel area), per unit angle of the bin
-    const double scale = P.total / (double)run->n_packets;
-    const double bw = 2.0 * M_PI / n_bins;
-    hipLaunchKernelGGL(k_binned_normalise, dim3((unsigned)((nout + 255) / 256)), dim3(256), 0, s, npix, n_bins, adjoint,
-                       scale / (double)m->dx / bw, raw, out);
-    if (ledger) hipLaunchKernelGGL(k_ledger_out, dim3(1), dim3(1), 0, s, P.led, P.ledc, scale, ledger);
+    hipLaunchKernelGGL(k_binned_normalise, dim3((unsigned)((nout + 255) / 256)), dim3(256), 0, s, (const ProbDev *)pd,
+                       n_bins, 2.0 * M_PI / n_bins, (const double *)raw, out);
+    if (ledger)
+        hipLaunchKernelGGL(k_ledger_out, dim3(1), dim3(1), 0, s, (const ProbDev *)pd, (const GenCtl *)nullptr, 0u, ledger);
     return hipGetLastError() == hipSuccess ? MC_OK : MC_ERR_DEVICE;
 }
 
@@ -2485,45 +2611,61 @@ mc_status mc_run_binned(const mc_medium *medium, const mc_source *src, int n_src
                       reinterpret_cast<hipStream_t>(stream));
 }
 
-size_t mc_workspace_bytes(const mc_medium *medium, const mc_source *src, int n_src, const mc_run *run) {
+size_t mc_workspace_bytes(const mc_medium *medium, const mc_source *src, int n_src, const mc_run *run,
+                          const mc_options *opts) {
     if (validate(medium, src, n_src, run) != MC_OK) return 0;
-    if (is_tiled(medium, run, tuning_snapshot())) {
+    TileTuning tt;
+    if (!tuning_from(opts, tt)) return 0;
+    if (is_tiled(medium, run, tt)) {
         const BatchProblem one{medium, src, n_src, run, 0, nullptr, nullptr};
-        return batch_layout(&one, 1).total;
+        return batch_layout(&one, 1, tt).total;
     }
     return layout(medium, src, run).total;
 }
 
-size_t mc_batch_workspace_bytes(const mc_problem *probs, int n_probs) {
+size_t mc_batch_workspace_bytes(const mc_problem *probs, int n_probs, const mc_options *opts) {
     if (!probs || n_probs < 1 || n_probs > MC_BATCH_MAX) return 0;
+    TileTuning tt;
+    if (!tuning_from(opts, tt)) return 0;
     std::vector<BatchProblem> pb(n_probs);
     for (int i = 0; i < n_probs; ++i) {
         const mc_problem &q = probs[i];
         if (validate(&q.medium, q.src, q.n_src, &q.run) != MC_OK || q.run.n_harm != probs[0].run.n_harm) return 0;
         pb[i] = BatchProblem{&q.medium, q.src, q.n_src, &q.run, q.adjoint ? 1 : 0, q.coeffs_d, q.ledger_d};
     }
-    return batch_layout(pb.data(), n_probs).total;
+    return batch_layout(pb.data(), n_probs, tt).total;
 }
 
-mc_status mc_run_batch(const mc_problem *probs, int n_probs, void *workspace_d, size_t workspace_bytes,
-                       void *stream) {
+mc_status mc_run_batch(const mc_problem *probs, int n_probs, const mc_options *opts, void *workspace_d,
+                       size_t workspace_bytes, void *stream) {
     if (!probs || n_probs < 1 || n_probs > MC_BATCH_MAX) return MC_ERR_INVALID_ARG;
     std::vector<BatchProblem> pb(n_probs);
     for (int i = 0; i < n_probs; ++i) {
         const mc_problem &q = probs[i];
         pb[i] = BatchProblem{&q.medium, q.src, q.n_src, &q.run, q.adjoint ? 1 : 0, q.coeffs_d, q.ledger_d};
     }
-    return run_batch(pb.data(), n_probs, workspace_d, workspace_bytes, reinterpret_cast<hipStream_t>(stream));
+    TileTuning tt;
+    if (!tuning_from(opts, tt)) return MC_ERR_INVALID_ARG;
+    return run_batch(pb.data(), n_probs, tt, opts ? opts->timer : nullptr, workspace_d, workspace_bytes,
+                     reinterpret_cast<hipStream_t>(stream));
 }
 
-mc_status mc_forward(const mc_medium *medium, const mc_source *src, int n_src, const mc_run *run, double *coeffs_d,
-                     mc_ledger *ledger_d, void *workspace_d, size_t workspace_bytes, void *stream) {
-    return run_mc(medium, src, n_src, run, coeffs_d, ledger_d, workspace_d, workspace_bytes, stream, 0);
+mc_status mc_forward(const mc_medium *medium, const mc_source *src, int n_src, const mc_run *run,
+                     const mc_options *opts, double *coeffs_d, mc_ledger *ledger_d, void *workspace_d,
+                     size_t workspace_bytes, void *stream) {
+    TileTuning tt;
+    if (!tuning_from(opts, tt)) return MC_ERR_INVALID_ARG;
+    return run_mc(medium, src, n_src, run, tt, opts ? opts->timer : nullptr, coeffs_d, ledger_d, workspace_d,
+                  workspace_bytes, reinterpret_cast<hipStream_t>(stream), 0);
 }
 
-mc_status mc_adjoint(const mc_medium *medium, const mc_source *src, int n_src, const mc_run *run, double *coeffs_d,
-                     mc_ledger *ledger_d, void *workspace_d, size_t workspace_bytes, void *stream) {
-    return run_mc(medium, src, n_src, run, coeffs_d, ledger_d, workspace_d, workspace_bytes, stream, 1);
+mc_status mc_adjoint(const mc_medium *medium, const mc_source *src, int n_src, const mc_run *run,
+                     const mc_options *opts, double *coeffs_d, mc_ledger *ledger_d, void *workspace_d,
+                     size_t workspace_bytes, void *stream) {
+    TileTuning tt;
+    if (!tuning_from(opts, tt)) return MC_ERR_INVALID_ARG;
+    return run_mc(medium, src, n_src, run, tt, opts ? opts->timer : nullptr, coeffs_d, ledger_d, workspace_d,
+                  workspace_bytes, reinterpret_cast<hipStream_t>(stream), 1);
 }
 
 mc_status mc_residual(const mc_medium *m, const double *coeffs_d, const double *hmeas_d, double *q_star_d,
@@ -2591,7 +2733,6 @@ mc_status mc_trace(const mc_medium *m, const mc_source *src, int n_src, const mc
     mc_status st = validate(m, src, n_src, run);
     if (st != MC_OK) return st;
     if (!pids_h || n_pids < 0 || (!events_h && cap) || !n_events_h) return MC_ERR_INVALID_ARG;
-    const int npix = m->nx * m->nz;
     const Layout L = layout(m, src, run);
     void *ws = nullptr, *d_pids = nullptr, *d_ev = nullptr, *d_n = nullptr;
     auto cleanup = [&]() {
@@ -2607,27 +2748,18 @@ mc_status mc_trace(const mc_medium *m, const mc_source *src, int n_src, const mc
         return MC_ERR_DEVICE;
     }
     char *base = static_cast<char *>(ws);
-    Params P;
-    double map_abs_sum = 0;
-    hipLaunchKernelGGL(k_setup_medium, dim3((npix + 255) / 256), dim3(256), 0, 0, npix, m->dx, m->mua_d, m->mus_d, m->g_d,
-                       reinterpret_cast<float4 *>(base + L.med));
-    if (src[0].kind == MC_SRC_MAP) {
-        double *cdf = reinterpret_cast<double *>(base + L.cdf);
-        hipLaunchKernelGGL(k_map_cdf, dim3(1), dim3(1024), 0, 0, npix, src[0].map_d, cdf);
-        if (hipMemcpy(&map_abs_sum, cdf + npix - 1, sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
-            cleanup();
-            return MC_ERR_DEVICE;
-        }
-    }
-    fill_params(P, m, src, n_src, run, adjoint, map_abs_sum);
+    ProbDev P;
+    fill_problem(P, m, src, n_src, run, adjoint, kFlushTrackMax);
     P.med = reinterpret_cast<const float4 *>(base + L.med);
     P.cdf = reinterpret_cast<const double *>(base + L.cdf);
-    if (hipMemcpy(d_pids, pids_h, sizeof(uint64_t) * n_pids, hipMemcpyHostToDevice) != hipSuccess) {
+    ProbDev *pd = reinterpret_cast<ProbDev *>(base + L.pd);
+    if (setup_problem(P, pd, nullptr, 0, m->mua_d, m->mus_d, m->g_d, 0) != MC_OK ||
+        hipMemcpy(d_pids, pids_h, sizeof(uint64_t) * n_pids, hipMemcpyHostToDevice) != hipSuccess) {
         cleanup();
         return MC_ERR_DEVICE;
     }
-    hipLaunchKernelGGL(kernels().tr[run->n_harm], dim3(1), dim3(64), 0, 0, P, (const uint64_t *)d_pids, n_pids,
-                       (mc_event *)d_ev, cap, (unsigned long long *)d_n);
+    hipLaunchKernelGGL(kernels().tr[run->n_harm], dim3(1), dim3(64), 0, 0, (const ProbDev *)pd,
+                       (const uint64_t *)d_pids, n_pids, (mc_event *)d_ev, cap, (unsigned long long *)d_n);
     unsigned long long n = 0;
     if (hipGetLastError() != hipSuccess || hipMemcpy(&n, d_n, sizeof(n), hipMemcpyDeviceToHost) != hipSuccess) {
         cleanup();
@@ -2661,74 +2793,64 @@ const char *mc_status_string(mc_status s) {
     return "unknown status";
 }
 
-void mc_profile_enable(int on) {
-    Profile &pr = profile_state();
-    std::lock_guard<std::mutex> g(pr.mu);
-    pr.on = on != 0;
-}
-
-mc_status mc_set_tuning(const mc_tuning *t) {
-    TileTuning v;   // defaults
-    if (t) {
-        if (t->live_packets < 1024 || t->live_packets > (1ull << 26) || t->job_packets < 64 ||
-            t->job_packets > (1u << 20) || t->max_visits < 1 || t->tile > 256 || t->finish_packets > (1ull << 26) ||
-            !(t->flush_track >= 0.f && t->flush_track <= (float)kFlushTrackMax) || t->tail_visits > (1u << 30))
-            return MC_ERR_INVALID_ARG;
-        v.live = t->live_packets;
-        v.grid_max = t->grid_max_packets ? t->grid_max_packets : kGridMaxPackets;
-        v.job = t->job_packets;
-        v.maxvis = t->max_visits;
-        v.tile = (int)t->tile;
-        v.finish = t->finish_packets;
-        v.flush_track = t->flush_track > 0.f ? (double)t->flush_track : kFlushTrackMax;
-        v.tailvis = t->tail_visits ? t->tail_visits : kTailVisits;
-    }
-    TuningState &s = tuning_state();
-    std::lock_guard<std::mutex> g(s.mu);
-    s.t = v;
-    return MC_OK;
-}
-
-mc_status mc_get_tuning(mc_tuning *t) {
+mc_status mc_default_tuning(mc_tuning *t) {
     if (!t) return MC_ERR_INVALID_ARG;
-    const TileTuning v = tuning_snapshot();
+    const TileTuning v;
     t->live_packets = v.live;
     t->job_packets = v.job;
     t->max_visits = v.maxvis;
-    t->tile = (uint32_t)v.tile;
-    t->finish_packets = v.finish;
-    t->grid_max_packets = (uint32_t)std::min<uint64_t>(v.grid_max, 0xFFFFFFFFull);
+    t->tile = 0;
+    t->finish_packets = std::min<uint64_t>(kFinishMax, v.live / 128);
+    t->grid_max_packets = (uint32_t)v.grid_max;
     t->flush_track = (float)v.flush_track;
     t->tail_visits = v.tailvis;
+    t->max_generations = 0;   // chosen per run from its packet count and pool
     return MC_OK;
 }
 
-mc_status mc_profile_read(double *transport_ms, uint64_t *launches, int reset) {
-    Profile &pr = profile_state();
-    std::lock_guard<std::mutex> g(pr.mu);
-    mc_status st = MC_OK;
-    for (auto &ev : pr.pending) {
-        float ms = 0.f;
-        if (hipEventSynchronize(ev.second) != hipSuccess || hipEventElapsedTime(&ms, ev.first, ev.second) != hipSuccess)
-            st = MC_ERR_DEVICE;
-        pr.ms += ms;
-        pr.launches += 1;
+mc_status mc_timer_create(mc_timer **timer) {
+    if (!timer) return MC_ERR_INVALID_ARG;
+    *timer = new (std::nothrow) mc_timer();
+    return *timer ? MC_OK : MC_ERR_DEVICE;
+}
+
+mc_status mc_timer_destroy(mc_timer *timer) {
+    if (!timer) return MC_ERR_INVALID_ARG;
+    for (auto &ev : timer->pending) {
+        (void)hipEventSynchronize(ev.second);
         (void)hipEventDestroy(ev.first);
         (void)hipEventDestroy(ev.second);
     }
-    pr.pending.clear();
-    if (transport_ms) *transport_ms = pr.ms;
-    if (launches) *launches = pr.launches;
+    delete timer;
+    return MC_OK;
+}
+
+mc_status mc_timer_read(mc_timer *timer, double *transport_ms, uint64_t *launches, int reset) {
+    if (!timer) return MC_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> g(timer->mu);
+    mc_status st = MC_OK;
+    for (auto &ev : timer->pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(ev.second) != hipSuccess || hipEventElapsedTime(&ms, ev.first, ev.second) != hipSuccess)
+            st = MC_ERR_DEVICE;
+        timer->ms += ms;
+        timer->launches += 1;
+        (void)hipEventDestroy(ev.first);
+        (void)hipEventDestroy(ev.second);
+    }
+    timer->pending.clear();
+    if (transport_ms) *transport_ms = timer->ms;
+    if (launches) *launches = timer->launches;
     if (reset) {
-        pr.ms = 0;
-        pr.launches = 0;
+        timer->ms = 0;
+        timer->launches = 0;
     }
     return st;
 }
 
 const char *mc_build_info(void) {
     return "librmc gfx950: FP32 transport; 64-bit fixed-point tally in LDS (whole grid when it fits, else square "
-           "tiles with packet migration between tiles), added to an FP64 HBM map";
+           "tiles with packet migration between tiles, generations steered on the device), added to an FP64 HBM map";
 }
 
 }  // extern "C"

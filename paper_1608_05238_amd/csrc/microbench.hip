@@ -41,6 +41,9 @@ __global__ void __launch_bounds__(1024) k_lds_atomics(uint32_t lds_bytes, uint32
     __syncthreads();
     const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t h = mb_hash(gid ^ (seed * 0x9e3779b9u));
+    uint32_t pre[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) pre[c] = mb_pick(mb_hash(h + 0x632be5abu * (c + 1)), lds_bytes / 8u);
     for (uint32_t it = 0; it < iters; ++it) {
         h = h * 1664525u + 1013904223u;
         const uint32_t r = mb_hash(h);
@@ -52,10 +55,20 @@ __global__ void __launch_bounds__(1024) k_lds_atomics(uint32_t lds_bytes, uint32
             atomicAdd(reinterpret_cast<unsigned long long *>(lds) + mb_pick(r, lds_bytes / 8u), 1ull);
         } else if constexpr (KIND == MB_LDS_ADD_U32) {
             atomicAdd(reinterpret_cast<uint32_t *>(lds) + mb_pick(r, lds_bytes / 4u), 1u);
-        } else {
+        } else if constexpr (KIND == MB_LDS_ADD_F64_ROW33) {
             double *row = reinterpret_cast<double *>(lds) + (size_t)mb_pick(r, lds_bytes / (8u * kRow)) * kRow;
 #pragma unroll
             for (int c = 0; c < kRow; ++c) atomicAdd(row + c, 1.0);
+        } else if constexpr (KIND == MB_LDS_ADD_U64_ROW33) {
+            unsigned long long *row =
+                reinterpret_cast<unsigned long long *>(lds) + (size_t)mb_pick(r, lds_bytes / (8u * kRow)) * kRow;
+#pragma unroll
+            for (int c = 0; c < kRow; ++c) atomicAdd(row + c, 1ull);
+        } else {   // MB_LDS_ADD_U64_PRE: eight addresses drawn once per lane, reused in turn
+            (void)r;
+            unsigned long long *base = reinterpret_cast<unsigned long long *>(lds);
+#pragma unroll
+            for (int c = 0; c < 8; ++c) atomicAdd(base + pre[c], 1ull);
         }
     }
     __syncthreads();
@@ -65,9 +78,10 @@ __global__ void __launch_bounds__(1024) k_lds_atomics(uint32_t lds_bytes, uint32
             for (uint32_t i = 0; i < lds_bytes / 4u; ++i)
                 v += KIND == MB_LDS_ADD_F32 ? (double)reinterpret_cast<float *>(lds)[i] : (double)w32[i];
         } else {
+            constexpr bool integer = KIND == MB_LDS_ADD_U64 || KIND == MB_LDS_ADD_U64_ROW33 || KIND == MB_LDS_ADD_U64_PRE;
             for (uint32_t i = 0; i < lds_bytes / 8u; ++i)
-                v += KIND == MB_LDS_ADD_U64 ? (double)reinterpret_cast<unsigned long long *>(lds)[i]
-                                            : reinterpret_cast<double *>(lds)[i];
+                v += integer ? (double)reinterpret_cast<unsigned long long *>(lds)[i]
+                             : reinterpret_cast<double *>(lds)[i];
         }
         sink[blockIdx.x] = v;
     }
@@ -158,6 +172,10 @@ mc_status mb_lds_atomics(int kind, uint32_t lds_bytes, uint32_t block, uint32_t 
         case MB_LDS_ADD_U32: return launch_lds<MB_LDS_ADD_U32>(lds_bytes, block, n_blocks, iters, seed, sink_d, clk_d, s);
         case MB_LDS_ADD_F64_ROW33:
             return launch_lds<MB_LDS_ADD_F64_ROW33>(lds_bytes, block, n_blocks, iters, seed, sink_d, clk_d, s);
+        case MB_LDS_ADD_U64_ROW33:
+            return launch_lds<MB_LDS_ADD_U64_ROW33>(lds_bytes, block, n_blocks, iters, seed, sink_d, clk_d, s);
+        case MB_LDS_ADD_U64_PRE:
+            return launch_lds<MB_LDS_ADD_U64_PRE>(lds_bytes, block, n_blocks, iters, seed, sink_d, clk_d, s);
         default: return MC_ERR_INVALID_ARG;
     }
 }

@@ -59,7 +59,9 @@ def run_all(dev: int = 0) -> dict:
     sink = torch.empty(nblk, dtype=torch.float64, device=d)
     kinds = [(L.MB_LDS_ADD_F64, "ds_add_f64 random", 2048, 1), (L.MB_LDS_ADD_F32, "ds_add_f32 random", 2048, 1),
              (L.MB_LDS_ADD_U64, "ds_add_u64 random", 2048, 1), (L.MB_LDS_ADD_U32, "ds_add_u32 random", 2048, 1),
-             (L.MB_LDS_ADD_F64_ROW33, "ds_add_f64 rows of 33", 64, 33)]
+             (L.MB_LDS_ADD_F64_ROW33, "ds_add_f64 rows of 33", 64, 33),
+             (L.MB_LDS_ADD_U64_ROW33, "ds_add_u64 rows of 33", 64, 33),
+             (L.MB_LDS_ADD_U64_PRE, "ds_add_u64, 8 addresses drawn once", 256, 8)]
     for kind, name, iters, per in kinds:
         t = _time(lambda: _check("mb_lds_atomics", lib.mb_lds_atomics(kind, lds, block, nblk, iters, 7,
                                                                        sink.data_ptr(), clk.data_ptr(), stream)))

@@ -122,19 +122,73 @@ def ledger_dict(buf: torch.Tensor) -> dict:
     return {f: getattr(led, f) for f, _ in L.mc_ledger._fields_}
 
 
-def mc_workspace_bytes(medium: Medium, sources: Sequence, run: L.mc_run) -> int:
+_TUNING_FIELDS = ("live_packets", "job_packets", "max_visits", "tile", "finish_packets", "grid_max_packets",
+                  "flush_track", "tail_visits", "max_generations")
+
+
+def default_tuning() -> dict:
+    """The library's built-in tuning of the tiled transport (see mc_tuning in include/mcrad.h)."""
+    t = L.mc_tuning()
+    L.check("mc_default_tuning", L.load().mc_default_tuning(C.byref(t)))
+    return {f: getattr(t, f) for f in _TUNING_FIELDS}
+
+
+class Timer:
+    """A caller-owned mc_timer: HIP events around every transport launch of
+    the calls it is passed to."""
+
+    def __init__(self):
+        self._h = C.c_void_p()
+        L.check("mc_timer_create", L.load().mc_timer_create(C.byref(self._h)))
+
+    def read(self, reset: bool = True):
+        """(total transport milliseconds, launches) since the last reset; waits for the events."""
+        ms, n = C.c_double(0), C.c_uint64(0)
+        L.check("mc_timer_read", L.load().mc_timer_read(self._h, C.byref(ms), C.byref(n), int(bool(reset))))
+        return ms.value, n.value
+
+    def close(self):
+        if self._h:
+            L.load().mc_timer_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class _Options:
+    """The mc_options of one call and the buffers it points to."""
+
+    def __init__(self, tuning: Optional[dict], timer: Optional[Timer]):
+        self.t = None
+        if tuning:
+            self.t = L.mc_tuning()
+            for f in _TUNING_FIELDS:
+                v = tuning.get(f, 0)
+                setattr(self.t, f, float(v) if f == "flush_track" else int(v))
+        self.o = L.mc_options(C.pointer(self.t) if self.t is not None else None, timer._h if timer else None)
+
+    def ref(self):
+        return C.byref(self.o)
+
+
+def mc_workspace_bytes(medium: Medium, sources: Sequence, run: L.mc_run, tuning: Optional[dict] = None) -> int:
     dev = medium.mua.device
     src = _Sources(sources, dev)
-    return L.load().mc_workspace_bytes(C.byref(medium.c()), src.arr, src.n, C.byref(run))
+    return L.load().mc_workspace_bytes(C.byref(medium.c()), src.arr, src.n, C.byref(run), _Options(tuning, None).ref())
 
 
 def _mc(name: str, medium: Medium, sources: Sequence, run: L.mc_run, out: Optional[torch.Tensor],
-        workspace: Optional[torch.Tensor], want_ledger: bool, stream):
+        workspace: Optional[torch.Tensor], want_ledger: bool, stream, tuning=None, timer=None):
     lib = L.load()
     dev = medium.mua.device
     src = _Sources(sources, dev)
     m = medium.c()
-    need = lib.mc_workspace_bytes(C.byref(m), src.arr, src.n, C.byref(run))
+    opts = _Options(tuning, timer)
+    need = lib.mc_workspace_bytes(C.byref(m), src.arr, src.n, C.byref(run), opts.ref())
     if need == 0:
         raise L.MCError("mc_workspace_bytes", L.MC_ERR_INVALID_ARG)
     if workspace is None or workspace.numel() < need:
@@ -148,22 +202,26 @@ def _mc(name: str, medium: Medium, sources: Sequence, run: L.mc_run, out: Option
         raise ValueError("output must be contiguous float64 [2N+1][nz][nx]")
     led = torch.zeros(C.sizeof(L.mc_ledger), dtype=torch.uint8, device=dev) if want_ledger else None
     fn = getattr(lib, name)
-    L.check(name, fn(C.byref(m), src.arr, src.n, C.byref(run), out.data_ptr(), _ptr(led), base + off,
+    L.check(name, fn(C.byref(m), src.arr, src.n, C.byref(run), opts.ref(), out.data_ptr(), _ptr(led), base + off,
                      workspace.numel() - off, _stream(stream)))
+    if stream is not None:
+        workspace.record_stream(stream)   # freed by the caching allocator only after the stream's work
     return out, led, workspace
 
 
 def mc_forward(medium: Medium, sources: Sequence, run: L.mc_run, out=None, workspace=None, ledger=True,
-               stream=None):
-    """Forward radiance MC.  Returns (coeffs [2N+1][nz][nx] float64, ledger buffer or None)."""
-    out, led, _ = _mc("mc_forward", medium, sources, run, out, workspace, ledger, stream)
+               stream=None, tuning: Optional[dict] = None, timer: Optional[Timer] = None):
+    """Forward radiance MC.  Returns (coeffs [2N+1][nz][nx] float64, ledger buffer or None).
+    tuning: mc_tuning fields (dict; missing or zero fields take the defaults);
+    timer: a Timer that records this call's transport launches."""
+    out, led, _ = _mc("mc_forward", medium, sources, run, out, workspace, ledger, stream, tuning, timer)
     return out, led
 
 
 def mc_adjoint(medium: Medium, sources: Sequence, run: L.mc_run, out=None, workspace=None, ledger=True,
-               stream=None):
+               stream=None, tuning: Optional[dict] = None, timer: Optional[Timer] = None):
     """Adjoint radiance MC (adjoint field phi*, orders already mirrored)."""
-    out, led, _ = _mc("mc_adjoint", medium, sources, run, out, workspace, ledger, stream)
+    out, led, _ = _mc("mc_adjoint", medium, sources, run, out, workspace, ledger, stream, tuning, timer)
     return out, led
 
 
@@ -262,7 +320,8 @@ class Problem:
     adjoint: bool = False
 
 
-def mc_run_batch(problems: Sequence[Problem], ledger: bool = True, stream=None):
+def mc_run_batch(problems: Sequence[Problem], ledger: bool = True, stream=None, tuning: Optional[dict] = None,
+                 timer: Optional[Timer] = None):
     """Run many problems in one packet pool.  Returns a list of (coeffs, ledger
     buffer or None), in the order given."""
     lib = L.load()
@@ -278,13 +337,15 @@ def mc_run_batch(problems: Sequence[Problem], ledger: bool = True, stream=None):
         led = torch.zeros(C.sizeof(L.mc_ledger), dtype=torch.uint8, device=dev) if ledger else None
         outs.append((out, led))
         arr[i] = L.mc_problem(pr.medium.c(), src.arr, src.n, pr.run, int(bool(pr.adjoint)), out.data_ptr(), _ptr(led))
-    need = lib.mc_batch_workspace_bytes(arr, n)
+    opts = _Options(tuning, timer)
+    need = lib.mc_batch_workspace_bytes(arr, n, opts.ref())
     if need == 0:
         raise L.MCError("mc_batch_workspace_bytes", L.MC_ERR_INVALID_ARG)
     dev = problems[0].medium.mua.device
     ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
     off = (-ws.data_ptr()) % 256
-    L.check("mc_run_batch", lib.mc_run_batch(arr, n, ws.data_ptr() + off, ws.numel() - off, _stream(stream)))
+    L.check("mc_run_batch", lib.mc_run_batch(arr, n, opts.ref(), ws.data_ptr() + off, ws.numel() - off,
+                                             _stream(stream)))
     if stream is not None:
         ws.record_stream(stream)   # freed by the caching allocator only after the stream's work
     return outs
@@ -316,43 +377,6 @@ def mc_philox_fill(seed: int, tag: int, pid0: int, n: int, j: int, stream=None) 
     out = torch.empty((n, 4), dtype=torch.int32, device=_device())
     L.check("mc_philox_fill", lib.mc_philox_fill(seed, tag, pid0, n, j, out.data_ptr(), _stream(stream)))
     return out
-
-
-def mc_profile_enable(on: bool = True) -> None:
-    """Time every transport launch with HIP events on its stream."""
-    L.load().mc_profile_enable(int(bool(on)))
-
-
-def mc_profile_read(reset: bool = True):
-    """(total transport milliseconds, number of launches) since the last reset."""
-    ms, n = C.c_double(0), C.c_uint64(0)
-    L.check("mc_profile_read", L.load().mc_profile_read(C.byref(ms), C.byref(n), int(bool(reset))))
-    return ms.value, n.value
-
-
-_TUNING_FIELDS = ("live_packets", "job_packets", "max_visits", "tile", "finish_packets", "grid_max_packets",
-                  "flush_track", "tail_visits")
-
-
-def mc_get_tuning() -> dict:
-    """Current tiled-transport tuning (see mc_tuning in include/mcrad.h)."""
-    t = L.mc_tuning()
-    L.check("mc_get_tuning", L.load().mc_get_tuning(C.byref(t)))
-    return {f: getattr(t, f) for f in _TUNING_FIELDS}
-
-
-def mc_set_tuning(tuning: Optional[dict] = None) -> None:
-    """Set the tiled-transport tuning; None restores the built-in defaults."""
-    lib = L.load()
-    if tuning is None:
-        L.check("mc_set_tuning", lib.mc_set_tuning(None))
-        return
-    t = L.mc_tuning()
-    cur = mc_get_tuning()
-    for f in _TUNING_FIELDS:
-        v = tuning.get(f, cur[f])
-        setattr(t, f, float(v) if f == "flush_track" else int(v))
-    L.check("mc_set_tuning", lib.mc_set_tuning(C.byref(t)))
 
 
 def build_info() -> str:

@@ -16,7 +16,7 @@ def test_microbenchmarks_count_their_operations():
     sink = torch.empty(nblk, dtype=torch.float64, device=d)
     clk = torch.zeros(4, dtype=torch.int64, device=d)
     for kind, per in ((L.MB_LDS_ADD_F64, 1), (L.MB_LDS_ADD_F32, 1), (L.MB_LDS_ADD_U64, 1), (L.MB_LDS_ADD_U32, 1),
-                      (L.MB_LDS_ADD_F64_ROW33, 33)):
+                      (L.MB_LDS_ADD_F64_ROW33, 33), (L.MB_LDS_ADD_U64_ROW33, 33), (L.MB_LDS_ADD_U64_PRE, 8)):
         for lds in (4096, 96 * 1024):
             assert lib.mb_lds_atomics(kind, lds, block, nblk, iters, 5, sink.data_ptr(), clk.data_ptr(), s) == 0
             torch.cuda.synchronize()

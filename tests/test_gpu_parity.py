@@ -38,11 +38,11 @@ def _oracle():
     return oracle
 
 
-def _gpu_run(rmc, ph, specs, n, N, seed=0, adjoint=False, first=0, tag=0, **kw):
+def _gpu_run(rmc, ph, specs, n, N, seed=0, adjoint=False, first=0, tag=0, tuning=None, **kw):
     med = rmc.Medium.from_phantom(ph)
     run = rmc.make_run(n, N, seed=seed, first_packet_id=first, stream_tag=tag, **kw)
     fn = rmc.mc_adjoint if adjoint else rmc.mc_forward
-    co, led = fn(med, specs, run)
+    co, led = fn(med, specs, run, tuning=tuning)
     return co.cpu().numpy(), rmc.ledger_dict(led)
 
 
@@ -62,23 +62,59 @@ def _oracle_batches(O, ph, specs, n, N, B, seed=0, adjoint=False, first=0, tag=0
     return total, se
 
 
-def _assert_maps(name, gpu, ora, se):
+def _assert_maps(name, gpu, ora, se, crn=True):
     """Element-wise bar max(1e-4 relative, 3 SE).  A pixel reached by only a few
     packets (relative SE of a0 above 0.3) can hold most of one packet whose
     FP32 trajectory left the FP64 one at a tie (a face/corner or roulette
     decision within rounding of its threshold); such sparse pixels are exempt,
-    and their number is recorded and bounded."""
+    and their number is recorded and bounded.
+
+    Because both sides follow the same packets with the same random numbers,
+    stronger bars apply on top (the FP32 rounding of the transport, far below
+    any Monte Carlo noise):
+      * the median relative error of the coefficients that do not cancel
+        inside their pixel (|c| >= 0.1 |a0| of the pixel, in pixels whose a0
+        is at least 1e-3 of the largest) is at most 1e-4;
+      * over every channel of those pixels, the median error relative to the
+        pixel's a0 (which bounds every |a_n|, |b_n| of one packet's visits)
+        is at most 3e-5: the FP32 weight carries a relative error up to
+        (k+16) 2^-24 after k free paths (the trajectory model of
+        _compare_traces), 3e-5 at the adjoint's median k of about 500, and a
+        signed source's a0 is a net of contributions of both signs (measured
+        medians: 1e-7 pencil32, 3.4e-6 disc256 forward, 1.0e-5 disc256
+        adjoint).  The direction error dt of the FP32 transport moves
+        T cos(nt) by n T dt, so an order n that nearly cancels inside its
+        pixel (|c_n| = f a0 over V visits) carries a relative error near
+        n dt / (f sqrt(V)): 1e-4 at n = 16, f = 1e-2, dt = 3e-7, V = 100.
+        Its own relative error therefore says little about the transport;
+        its error against a0 does;
+      * the whole-map L2 gap is at most 0.05 of the L2 norm of the standard
+        errors (only packets that diverged at a tie differ; a systematic
+        bias of the order of the noise would fail).
+    crn=False (different packets on the two sides) keeps only the element-wise
+    bar."""
     tol = np.maximum(1e-4 * np.abs(ora), 3 * se)
     bad = np.abs(gpu - ora) > tol + 1e-300
     sparse = se[0] > 0.3 * np.abs(ora[0])
     bad_dense = bad & ~sparse[None]
-    rel = np.abs(gpu - ora) / np.maximum(np.abs(ora), 1e-300)
-    big = np.abs(ora) > 1e-3 * np.abs(ora).max()
-    stats = {"max_rel_err_significant": float(rel[big].max()), "median_rel_err": float(np.median(rel[big])),
-             "frac_outside_tol": float(bad.mean()), "outside_tol_sparse": int((bad & sparse[None]).sum())}
+    err = np.abs(gpu - ora)
+    rel = err / np.maximum(np.abs(ora), 1e-300)
+    a0 = np.abs(ora[0])
+    lit = a0 > 1e-3 * a0.max()
+    keep = (np.abs(ora) >= 0.1 * a0[None]) & lit[None]
+    a0rel = (err / np.maximum(a0[None], 1e-300))[:, lit]
+    l2_gap = float(np.linalg.norm(gpu - ora) / max(np.linalg.norm(se), 1e-300))
+    stats = {"max_rel_err_noncancelling": float(rel[keep].max()), "median_rel_err": float(np.median(rel[keep])),
+             "median_a0rel_err": float(np.median(a0rel)), "max_a0rel_err": float(a0rel.max()),
+             "frac_outside_tol": float(bad.mean()), "outside_tol_sparse": int((bad & sparse[None]).sum()),
+             "l2_gap_over_se": l2_gap}
     _record(name, stats)
     assert not bad_dense.any(), (name, stats, np.argwhere(bad_dense)[:5])
     assert bad.mean() <= 1e-5, (name, stats, np.argwhere(bad)[:5])
+    if crn:
+        assert stats["median_rel_err"] <= 1e-4, (name, stats)
+        assert stats["median_a0rel_err"] <= 3e-5, (name, stats)
+        assert l2_gap <= 0.05, (name, stats)
 
 
 # ---------------------------------------------------------------- RNG
@@ -109,45 +145,92 @@ def _is_tie(ev, dx, tol):
     return ev["type"] in (2, 4) and (nx_ or nz_)
 
 
-K_TIGHT = 256   # interactions over which the 1e-5 bar applies; FP32 drift grows beyond
+U32 = 2.0 ** -24   # unit roundoff of FP32
 
 
-def _compare_traces(g, o, dx, width):
-    """Compare event sequences packet by packet, up to the first divergence.
+def _compare_traces(g, o, dx, width, per_event=None):
+    """Compare event sequences packet by packet, up to the first divergence
+    (a branch taken differently: event type, pixel or free-path index).
 
-    Errors: positions relative to the domain extent, directions absolute,
-    weights relative, and the packet's summed deposit relative.  A divergence
-    (a branch taken differently) is accepted only at a near-tie whose margin
+    Per event, against the FP32 error model of the transport (k = free-path
+    index, L = path length so far, U = 2^-24):
+      * direction: each scatter's rotation is accurate to about 2U and the
+        errors of successive scatters add as a random walk:
+        |ds| <= 2 sqrt(k+16) U;
+      * weight: one rounding per segment of w <- w - dw (and the absorbed
+        fraction's few ulp), accumulated linearly: |dw|/|w| <= (k+17) U;
+      * position: the direction error integrated over the path plus one
+        rounding of the in-pixel offset per segment:
+        err <= rec + (L/dx + k + 16) sqrt(k+16) dx U, rec being the FP32
+        rounding of the recorded position in mm.  The error is taken
+        perpendicular to the track, and along it at scatters; at a crossing
+        the along-track position is ill-conditioned -- a track running at a
+        grazing angle to the face moves its crossing point by the transverse
+        error divided by |s_n|, the direction's component normal to the
+        face -- so there the along-track error times |s_n| is bounded.
+    The spec bar, 1e-5 of the domain, applies to these position errors
+    over the first 1024 free paths; beyond, the transverse error divided by
+    |s_n| at a crossing of a scattering interface (mu_s1 != mu_s2) turns into
+    an along-track error (1 - mu_s1/mu_s2) times as large at the next
+    scatter, which can take an event past 1e-5 while it stays inside the
+    model (measured: 1.3e-5 at free path 2152 of an adjoint history).  A
+    divergence is accepted only at a near-tie whose margin
     is within 1e-3 pixel plus ten times the position error reached so far.
-    Returns (n_packets, n_divergent, n_bad_divergences, tight errors [pos, dir,
-    w, T-sum] over k <= K_TIGHT, loose errors over the whole matched prefix)."""
+    Returns (n_packets, n_divergent, n_bad_divergences, dict of the worst
+    ratios to each bound and the worst relative errors)."""
     div = bad = 0
     pids = np.unique(o["pid"])
-    tight, loose = [], []
+    rec = float(np.spacing(np.float32(width)))
+    worst = {"dir_over_model": 0.0, "w_over_model": 0.0, "pos_over_model": 0.0, "pos_rel_domain": 0.0,
+             "pos_rel_domain_k1024": 0.0, "events": 0, "events_pos_over_1e-5": 0,
+             "dir_abs": 0.0, "w_rel": 0.0, "tsum_rel": 0.0, "along_crossing_rel_domain_raw": 0.0}
     for pid in pids:
         ge, oe = g[g["pid"] == pid], o[o["pid"] == pid]
         n = min(len(ge), len(oe))
-        et, el = np.zeros(4), np.zeros(4)
         tg = to = 0.0
-        tg_t = to_t = 0.0
         perr = 0.0
+        path = 0.0
         diverged = None
         for i in range(n):
             a, b = ge[i], oe[i]
             if a["type"] != b["type"] or a["ix"] != b["ix"] or a["iz"] != b["iz"] or a["k"] != b["k"]:
                 diverged = i
                 break
+            if i > 0:
+                path += float(np.hypot(b["x"] - oe[i - 1]["x"], b["z"] - oe[i - 1]["z"]))
             tg += a["t"]
             to += b["t"]
-            perr = max(abs(a["x"] - b["x"]), abs(a["z"] - b["z"]))
-            e = np.array([perr / width, max(abs(a["sx"] - b["sx"]), abs(a["sz"] - b["sz"])),
-                          abs(a["w"] - b["w"]) / max(abs(b["w"]), 1e-30), 0.0])
-            el = np.maximum(el, e)
-            if b["k"] <= K_TIGHT:
-                tg_t, to_t = tg, to
-                et = np.maximum(et, e)
-        et[3] = abs(tg_t - to_t) / max(abs(to_t), dx)
-        el[3] = abs(tg - to) / max(abs(to), dx)
+            k = float(b["k"]) + 16.0
+            # direction of the segment that ends here (the previous event's, in the oracle)
+            sx, sz = (oe[i - 1]["sx"], oe[i - 1]["sz"]) if i > 0 else (b["sx"], b["sz"])
+            ddx, ddz = float(a["x"] - b["x"]), float(a["z"] - b["z"])
+            perp = abs(ddx * sz - ddz * sx)
+            along = abs(ddx * sx + ddz * sz)
+            if b["type"] in (1, 3):   # crossing or escape: the face's normal component scales the along-track error
+                fxd = abs(b["x"] / dx - np.round(b["x"] / dx))
+                fzd = abs(b["z"] / dx - np.round(b["z"] / dx))
+                along *= abs(sx) if fxd < fzd else abs(sz)
+                worst["along_crossing_rel_domain_raw"] = max(worst["along_crossing_rel_domain_raw"],
+                                                             max(abs(ddx), abs(ddz)) / width)
+            pos = max(perp, along)
+            ddir = max(abs(a["sx"] - b["sx"]), abs(a["sz"] - b["sz"]))
+            dw = abs(a["w"] - b["w"]) / max(abs(b["w"]), 1e-30)
+            pos_model = rec + (path / dx + k) * np.sqrt(k) * dx * U32
+            worst["pos_over_model"] = max(worst["pos_over_model"], pos / pos_model)
+            worst["pos_rel_domain"] = max(worst["pos_rel_domain"], pos / width)
+            if b["k"] <= 1024:
+                worst["pos_rel_domain_k1024"] = max(worst["pos_rel_domain_k1024"], pos / width)
+            worst["events"] += 1
+            worst["events_pos_over_1e-5"] += int(pos > 1e-5 * width)
+            worst["dir_over_model"] = max(worst["dir_over_model"], ddir / (2.0 * np.sqrt(k) * U32))
+            worst["w_over_model"] = max(worst["w_over_model"], dw / ((k + 1.0) * U32))
+            worst["dir_abs"] = max(worst["dir_abs"], ddir)
+            worst["w_rel"] = max(worst["w_rel"], dw)
+            perr = max(abs(ddx), abs(ddz))
+            if per_event is not None:
+                per_event.append((int(pid), i, int(b["k"]), int(b["type"]), perr, ddir, dw,
+                                  abs(a["t"] - b["t"]) / max(abs(b["t"]), 1e-30)))
+        worst["tsum_rel"] = max(worst["tsum_rel"], abs(tg - to) / max(abs(to), dx))
         if diverged is None and len(ge) != len(oe):
             diverged = n
         if diverged is not None:
@@ -156,18 +239,22 @@ def _compare_traces(g, o, dx, width):
             tol = 1e-3 * dx + 10 * perr
             if not (_is_tie(ge[i], dx, tol) or _is_tie(oe[i], dx, tol)):
                 bad += 1
-        tight.append(et)
-        loose.append(el)
-    return len(pids), div, bad, np.array(tight), np.array(loose)
+    return len(pids), div, bad, worst
 
 
-def _trace_case(rmc, O, ph, specs, N, pids, adjoint=False, tag=0, seed=0):
+def _trace_case(rmc, O, ph, specs, N, pids, adjoint=False, tag=0, seed=0, name="case"):
     med = rmc.Medium.from_phantom(ph)
     run = rmc.make_run(1, N, seed=seed, stream_tag=tag)
     g = rmc.mc_trace(med, specs, run, pids, adjoint=adjoint)
     o = O.trace(O.medium_from(ph), O.sources_from(specs), O.Run(1, seed, N, stream_tag=tag, adjoint=int(adjoint)),
                 pids)
-    return _compare_traces(g, o, ph.dx, max(ph.width, ph.depth))
+    per_event = [] if OUT else None
+    res = _compare_traces(g, o, ph.dx, max(ph.width, ph.depth), per_event)
+    if OUT:   # per-event errors (pid, event, k, type, |dpos| mm, |ddir|, rel dw, rel dT) for offline study
+        os.makedirs(OUT, exist_ok=True)
+        np.save(os.path.join(OUT, f"trace_errors_{name}.npy"), np.array(per_event, dtype=np.float64))
+        np.save(os.path.join(OUT, f"trace_gpu_{name}.npy"), g)
+    return res
 
 
 @pytest.mark.parametrize("case", ["pencil32", "disc256", "adjoint_map"])
@@ -189,19 +276,20 @@ def test_trajectory_parity(case):
         specs = [P.map_source(P.residual_like_map(ph))]
         N, adj, tag = 16, True, 1
         pids = rng.integers(0, 100_000_000, 60)
-    n, div, bad, tight, loose = _trace_case(rmc, O, ph, specs, N, pids, adjoint=adj, tag=tag)
-    stats = {"packets": n, "divergent_at_ties": div, "divergent_not_at_ties": bad}
-    for j, nm in enumerate(("pos", "dir", "w", "tsum")):
-        stats[nm + f"_max_k{K_TIGHT}"] = float(tight[:, j].max())
-        stats[nm + "_max_all"] = float(loose[:, j].max())
-        stats[nm + "_median_all"] = float(np.median(loose[:, j]))
+    n, div, bad, worst = _trace_case(rmc, O, ph, specs, N, pids, adjoint=adj, tag=tag, name=case)
+    stats = {"packets": n, "divergent_at_ties": div, "divergent_not_at_ties": bad, **worst}
     _record("trace_" + case, stats)
     assert bad == 0, stats
-    assert div <= max(2, n // 4), stats
-    # FP32 transport against the FP64 oracle: 1e-5 over the first K_TIGHT interactions,
-    # FP32 drift beyond (direction error ~1e-7 per scatter) bounded by 1e-3
-    assert tight.max() < 1e-5, stats
-    assert loose.max() < 1e-3, stats
+    # divergences at ties: measured 0/200 (pencil32), 1/63 (disc256), 3/60 (adjoint)
+    assert div <= max(3, n // 10), stats
+    # every matched event within the FP32 error model (see _compare_traces)
+    assert worst["pos_over_model"] <= 1.0 and worst["dir_over_model"] <= 1.0 and worst["w_over_model"] <= 1.0, stats
+    # the spec bar: positions within 1e-5 of the domain at every event of the
+    # first 1024 free paths and at all but 0.1% of the events beyond; directions at every event
+    assert worst["pos_rel_domain_k1024"] <= 1e-5 and worst["dir_abs"] <= 1e-5, stats
+    assert worst["events_pos_over_1e-5"] <= 1e-3 * worst["events"], stats
+    # each packet's summed deposit
+    assert worst["tsum_rel"] <= 1e-5, stats
 
 
 # ---------------------------------------------------------------- coefficient maps
@@ -286,7 +374,7 @@ def test_forward_global_tally_across_chunks():
     O = _oracle()
     ph = P.disc_phantom(96, 0.1, 0.02, 8.0, 0.9, seed=4)
     specs = P.four_side_lines(ph)
-    live = rmc.mc_get_tuning()["live_packets"]   # the first refill happens at this many packets
+    live = rmc.default_tuning()["live_packets"]   # the first refill happens at this many packets
     n = live + 5000
     full, _ = _gpu_run(rmc, ph, specs, n, 16, seed=9)
     B = 8
@@ -331,6 +419,34 @@ def test_edge_cases_small_runs():
     assert np.all(gpu == 0.0) and led["escaped"] == pytest.approx(100.0)
 
 
+@pytest.mark.parametrize("mode", ["whole_grid", "tiled"])
+def test_roulette_active_parity(mode):
+    """Russian roulette at a threshold where it decides the fate of most
+    packets (w_th = 0.05, m = 4: survive with 1/4, weight x 4), element by
+    element against the oracle on the same packets: the survival draw, the
+    weight gain and the kill all shape the maps.  whole_grid: an 8x8 grid of
+    strong absorption and scattering (whole-grid LDS tally); tiled: a 64x64
+    disc phantom of strong absorption lit from four sides at N = 16 (tiled
+    transport, packets migrating between tiles)."""
+    rmc = _rmc()
+    O = _oracle()
+    if mode == "whole_grid":
+        ph = P.homogeneous(8, 8, 0.5, 2.0, 20.0, 0.0)
+        specs, N, n = P.pencil_top_centre(ph), 4, 100_000
+    else:
+        ph = P.disc_phantom(64, 0.1, 1.0, 12.0, 0.8, seed=14, radius=(0.5, 1.5))
+        specs, N, n = P.four_side_lines(ph), 16, 100_000
+    kw = dict(w_threshold=0.05, roulette_m=4.0)
+    gpu, led = _gpu_run(rmc, ph, specs, n, N, seed=23, **kw)
+    ora, se = _oracle_batches(O, ph, specs, n, N, B=8, seed=23, **kw)
+    _assert_maps(f"roulette_{mode}", gpu, ora, se)
+    assert led["packets"] == n
+    assert led["roulette_gain"] > 0.01 * led["launched"], led
+    assert led["roulette_loss"] > 0.01 * led["launched"], led
+    bal = led["launched"] + led["roulette_gain"] - led["roulette_loss"] - led["absorbed"] - led["escaped"]
+    assert abs(bal) < 1e-5 * led["launched"]
+
+
 def test_literal_truncation_flag():
     rmc = _rmc()
     O = _oracle()
@@ -368,64 +484,61 @@ def test_anisotropic_point_source_sin2_2theta(tiled):
     tile tally for that bound)."""
     rmc = _rmc()
     O = _oracle()
-    base = rmc.mc_get_tuning()
     ph = P.homogeneous(32, 32, 0.25, 0.05, 8.0, 0.8)
     prof = np.zeros(2 * 4 + 1)
     prof[0], prof[4] = 1.0, -0.5
     specs = [P.point_source(4.03, 3.97, prof=prof)]
     n = 40_000
-    try:
-        if tiled:
-            rmc.mc_set_tuning({**base, "grid_max_packets": 1})
-        for adj, tag in ((False, 0), (True, 1)):
-            gpu, _ = _gpu_run(rmc, ph, specs, n, 8, seed=17, adjoint=adj, tag=tag)
-            ora, se = _oracle_batches(O, ph, specs, n, 8, B=8, seed=17, adjoint=adj, tag=tag)
-            _assert_maps(f"sin2_2theta_{'adj' if adj else 'fwd'}{'_tiled' if tiled else ''}", gpu, ora, se)
-    finally:
-        rmc.mc_set_tuning(base)
+    tuning = {"grid_max_packets": 1} if tiled else None
+    for adj, tag in ((False, 0), (True, 1)):
+        gpu, _ = _gpu_run(rmc, ph, specs, n, 8, seed=17, adjoint=adj, tag=tag, tuning=tuning)
+        ora, se = _oracle_batches(O, ph, specs, n, 8, B=8, seed=17, adjoint=adj, tag=tag)
+        _assert_maps(f"sin2_2theta_{'adj' if adj else 'fwd'}{'_tiled' if tiled else ''}", gpu, ora, se)
 
 
 def test_tuning_changes_schedule_not_results():
-    """Other tile sides, generation sizes, job sizes and pause lengths move the
-    same packets in another order, and the maps are bitwise equal: every visit
-    adds the same multiple of 2^(e-32), and FP64 sums such values exactly
-    while a pixel's total stays below 2^(21+e) (here far below), so the order
-    of the additions no longer matters.  Flushing visits in parts changes only
-    FP32 partial sums.  The autotuner picks one of its candidates and applies
-    it."""
+    """Other tile sides, generation sizes, job sizes, pause lengths and
+    generation budgets move the same packets in another order, and the maps
+    are bitwise equal: every visit adds the same multiple of 2^(e-32), and
+    FP64 sums such values exactly while a pixel's total stays below 2^(21+e)
+    (here far below), so the order of the additions no longer matters.  A
+    budget of one or two generations with a small pool leaves most packets
+    unlaunched: the finisher launches and moves them.  Flushing visits in
+    parts changes only FP32 partial sums.  The autotuner returns one of its
+    candidates."""
     rmc = _rmc()
     from paper_1608_05238_amd import autotune
-    base = rmc.mc_get_tuning()
     ph = P.disc_phantom(64, 0.2, 0.02, 8.0, 0.9, seed=12, radius=(1.0, 2.5))
     specs = P.four_side_lines(ph)
     n = 300_000
-    try:
-        ref, lref = _gpu_run(rmc, ph, specs, n, 16, seed=31)
-        for t in ({"tile": 7}, {"live_packets": 4096, "job_packets": 256, "max_visits": 3},
-                  {"live_packets": 1 << 17, "finish_packets": 50_000}, {"tail_visits": 1 << 30},
-                  {"tail_visits": 1}):
-            rmc.mc_set_tuning({**base, **t})
-            got, lgot = _gpu_run(rmc, ph, specs, n, 16, seed=31)
-            assert np.array_equal(got, ref), (t, np.abs(got - ref).max())
-            assert lgot["visits"] == lref["visits"] and lgot["scatters"] == lref["scatters"], t
-        # a visit flushed in parts (here after a quarter pixel of track) adds the
-        # same contributions in other FP32 partial sums; high orders nearly cancel
-        # within a pixel, so the rounding is measured against the pixel's a0
-        # (|a_n| <= a0 for every visit)
-        rmc.mc_set_tuning({**base, "flush_track": 0.25})
-        got, lgot = _gpu_run(rmc, ph, specs, n, 16, seed=31)
-        a0 = np.abs(ref[0])
-        lit = a0 > 1e-6 * a0.max()
-        err = (np.abs(got - ref)[:, lit] / a0[lit]).ravel()
-        assert err.max() < 1e-6 and np.median(err) < 1e-8, (err.max(), np.median(err))
-        assert lgot["visits"] == lref["visits"] and lgot["scatters"] == lref["scatters"]
-        rmc.mc_set_tuning(base)
-        med = rmc.Medium.from_phantom(ph)
-        res = autotune.tune(med, specs, 16, trial_packets=200_000,
-                            space={"job_packets": (1024, 4096), "max_visits": (16, 32)})
-        assert rmc.mc_get_tuning() == res["tuning"] and len(res["trials"]) == 4
-    finally:
-        rmc.mc_set_tuning(base)
+    ref, lref = _gpu_run(rmc, ph, specs, n, 16, seed=31)
+    assert lref["generations"] > 0
+    for t in ({"tile": 7}, {"live_packets": 4096, "job_packets": 256, "max_visits": 3},
+              {"live_packets": 1 << 17, "finish_packets": 50_000}, {"tail_visits": 1 << 30},
+              {"tail_visits": 1}, {"live_packets": 4096, "max_generations": 2},
+              {"max_generations": 1}, {"max_generations": 3, "finish_packets": 1024}):
+        got, lgot = _gpu_run(rmc, ph, specs, n, 16, seed=31, tuning=t)
+        assert np.array_equal(got, ref), (t, np.abs(got - ref).max())
+        for k in ("packets", "visits", "scatters", "segments"):
+            assert lgot[k] == lref[k], (t, k)
+        if "max_generations" in t:
+            assert lgot["generations"] <= t["max_generations"], (t, lgot["generations"])
+    # a visit flushed in parts (here after a quarter pixel of track) adds the
+    # same contributions in other FP32 partial sums; high orders nearly cancel
+    # within a pixel, so the rounding is measured against the pixel's a0
+    # (|a_n| <= a0 for every visit)
+    got, lgot = _gpu_run(rmc, ph, specs, n, 16, seed=31, tuning={"flush_track": 0.25})
+    a0 = np.abs(ref[0])
+    lit = a0 > 1e-6 * a0.max()
+    err = (np.abs(got - ref)[:, lit] / a0[lit]).ravel()
+    assert err.max() < 1e-6 and np.median(err) < 1e-8, (err.max(), np.median(err))
+    assert lgot["visits"] == lref["visits"] and lgot["scatters"] == lref["scatters"]
+    med = rmc.Medium.from_phantom(ph)
+    res = autotune.tune(med, specs, 16, trial_packets=200_000,
+                        space={"job_packets": (1024, 4096), "max_visits": (16, 32)})
+    assert len(res["trials"]) == 4 and res["tuning"] in [r["tuning"] for r in res["trials"]]
+    got, _ = _gpu_run(rmc, ph, specs, n, 16, seed=31, tuning=res["tuning"])
+    assert np.array_equal(got, ref)
 
 
 @pytest.mark.parametrize("live", [None, 1 << 16])
@@ -438,7 +551,6 @@ def test_batch_equals_separate_runs(live):
     source and an all-zero map source; a small pool (2^16 live packets) mixes
     the problems' packets over many generations."""
     rmc = _rmc()
-    base = rmc.mc_get_tuning()
     ph1 = P.disc_phantom(64, 0.2, 0.02, 8.0, 0.9, seed=21, radius=(1.0, 2.5))
     ph2 = P.homogeneous(20, 12, 0.5, 0.05, 5.0, 0.8)
     ph3 = P.disc_phantom(40, 0.25, 0.03, 6.0, 0.85, seed=22, radius=(1.0, 2.0))
@@ -448,24 +560,21 @@ def test_batch_equals_separate_runs(live):
              (ph3, [P.map_source(q3)], True, 120_000, 7, 1),
              (ph3, [P.map_source(np.zeros_like(q3))], True, 1000, 8, 1),
              (ph1, [P.point_source(6.33, 5.91)], False, 80_000, 9, 0)]
-    try:
-        if live:
-            rmc.mc_set_tuning({**base, "live_packets": live})
-        probs = [rmc.Problem(rmc.Medium.from_phantom(ph), src, rmc.make_run(n, 16, seed=sd, stream_tag=tag), adj)
-                 for ph, src, adj, n, sd, tag in cases]
-        outs = rmc.mc_run_batch(probs)
-        for (ph, src, adj, n, sd, tag), (got, lg) in zip(cases, outs):
-            ref, lr = _gpu_run(rmc, ph, src, n, 16, seed=sd, adjoint=adj, tag=tag)
-            got, lg = got.cpu().numpy(), rmc.ledger_dict(lg)
-            if not np.abs(ref).max():
-                assert not np.abs(got).max()
-                continue
-            assert np.array_equal(got, ref), (ph.mua.shape, adj, np.abs(got - ref).max())
-            for k in ("packets", "visits", "scatters", "segments"):
-                assert lg[k] == lr[k], (k, lg[k], lr[k])
-            assert lg["absorbed"] == pytest.approx(lr["absorbed"], rel=1e-9)
-    finally:
-        rmc.mc_set_tuning(base)
+    tuning = {"live_packets": live} if live else None
+    probs = [rmc.Problem(rmc.Medium.from_phantom(ph), src, rmc.make_run(n, 16, seed=sd, stream_tag=tag), adj)
+             for ph, src, adj, n, sd, tag in cases]
+    outs = rmc.mc_run_batch(probs, tuning=tuning)
+    for (ph, src, adj, n, sd, tag), (got, lg) in zip(cases, outs):
+        ref, lr = _gpu_run(rmc, ph, src, n, 16, seed=sd, adjoint=adj, tag=tag)
+        got, lg = got.cpu().numpy(), rmc.ledger_dict(lg)
+        if not np.abs(ref).max():
+            assert not np.abs(got).max()
+            assert lg["packets"] == 0 and lr["packets"] == 0
+            continue
+        assert np.array_equal(got, ref), (ph.mua.shape, adj, np.abs(got - ref).max())
+        for k in ("packets", "visits", "scatters", "segments"):
+            assert lg[k] == lr[k], (k, lg[k], lr[k])
+        assert lg["absorbed"] == pytest.approx(lr["absorbed"], rel=1e-9)
 
 
 # ---------------------------------------------------------------- discrete ordinates

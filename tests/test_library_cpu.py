@@ -40,7 +40,8 @@ def test_library_exports_every_declared_entry_point():
 def test_struct_layouts():
     L, _ = _lib()
     assert C.sizeof(L.mc_event) == 48
-    assert C.sizeof(L.mc_ledger) == 80
+    assert C.sizeof(L.mc_ledger) == 88
+    assert C.sizeof(L.mc_tuning) == 48 and C.sizeof(L.mc_options) == 16
     assert C.sizeof(L.mc_run) == 48
     assert C.sizeof(L.mc_medium) == 40
 
@@ -88,8 +89,8 @@ def test_invalid_arguments_rejected_on_host(bad):
         n_src = 9
     elif bad == "flags":
         run.flags = 4
-    assert lib.mc_workspace_bytes(C.byref(m), src, n_src, C.byref(run)) == 0
-    rc = lib.mc_forward(C.byref(m), src, n_src, C.byref(run), 0x2000, None, 0x3000, 1 << 30, None)
+    assert lib.mc_workspace_bytes(C.byref(m), src, n_src, C.byref(run), None) == 0
+    rc = lib.mc_forward(C.byref(m), src, n_src, C.byref(run), None, 0x2000, None, 0x3000, 1 << 30, None)
     assert rc == L.MC_ERR_INVALID_ARG
 
 
@@ -100,55 +101,69 @@ def test_map_source_must_be_alone_and_workspace_checked():
     a.kind, a.map_d = L.MC_SRC_MAP, 0x4000
     srcs = (L.mc_source * 2)(a, _pencil(L))
     run = L.mc_run(1000, 0, 0, 0, 4, 1e-4, 10.0, 0)
-    assert lib.mc_workspace_bytes(C.byref(m), srcs, 2, C.byref(run)) == 0
+    assert lib.mc_workspace_bytes(C.byref(m), srcs, 2, C.byref(run), None) == 0
     one = (L.mc_source * 1)(_pencil(L))
-    need = lib.mc_workspace_bytes(C.byref(m), one, 1, C.byref(run))
+    need = lib.mc_workspace_bytes(C.byref(m), one, 1, C.byref(run), None)
     assert need > 0
-    rc = lib.mc_forward(C.byref(m), one, 1, C.byref(run), 0x2000, None, 0x3000, need - 1, None)
+    rc = lib.mc_forward(C.byref(m), one, 1, C.byref(run), None, 0x2000, None, 0x3000, need - 1, None)
     assert rc == L.MC_ERR_WORKSPACE
-    rc = lib.mc_forward(C.byref(m), one, 1, C.byref(run), 0x2000, None, 0x3001, need + 256, None)
+    rc = lib.mc_forward(C.byref(m), one, 1, C.byref(run), None, 0x2000, None, 0x3001, need + 256, None)
     assert rc == L.MC_ERR_WORKSPACE
 
 
 def test_workspace_grows_with_grid_and_harmonics():
     L, lib = _lib()
     one = (L.mc_source * 1)(_pencil(L))
-    small = lib.mc_workspace_bytes(C.byref(_medium(L, 4, 4)), one, 1, C.byref(L.mc_run(10, 0, 0, 0, 2, 1e-4, 10.0, 0)))
+    small = lib.mc_workspace_bytes(C.byref(_medium(L, 4, 4)), one, 1, C.byref(L.mc_run(10, 0, 0, 0, 2, 1e-4, 10.0, 0)), None)
     big = lib.mc_workspace_bytes(C.byref(_medium(L, 256, 256, 0.1)), one, 1,
-                                 C.byref(L.mc_run(10, 0, 0, 0, 16, 1e-4, 10.0, 0)))
+                                 C.byref(L.mc_run(10, 0, 0, 0, 16, 1e-4, 10.0, 0)), None)
     assert big > 65536 * 33 * 8 > small > 0
 
 
-def test_tuning_set_get_and_workspace():
-    """mc_set_tuning / mc_get_tuning round-trip, range checks, and the queue
-    sizes follow live_packets (host only)."""
+def test_tuning_is_per_call_and_checked():
+    """The defaults round-trip through mc_default_tuning; a call's tuning
+    (mc_options) sizes its queues -- the library keeps none -- and a tuning
+    out of range makes the call invalid (host only)."""
     L, lib = _lib()
     from paper_1608_05238_amd import rmc
-    base = rmc.mc_get_tuning()
-    try:
-        m = _medium(L)
-        m.nx = m.nz = 256
-        src = (L.mc_source * 1)(_pencil(L))
-        run = L.mc_run(1 << 26, 0, 0, 0, 16, 1e-4, 10.0, 0)
-        rmc.mc_set_tuning({"live_packets": 1 << 20})
-        small = lib.mc_workspace_bytes(C.byref(m), src, 1, C.byref(run))
-        rmc.mc_set_tuning({"live_packets": 1 << 22, "job_packets": 1024, "max_visits": 7, "tile": 9})
-        assert rmc.mc_get_tuning() == {"live_packets": 1 << 22, "job_packets": 1024, "max_visits": 7, "tile": 9,
-                                       "finish_packets": 0, "grid_max_packets": 1 << 21, "flush_track": 65536.0,
-                                       "tail_visits": 8}
-        rmc.mc_set_tuning({"flush_track": 0.25})
-        assert rmc.mc_get_tuning()["flush_track"] == 0.25
-        big = lib.mc_workspace_bytes(C.byref(m), src, 1, C.byref(run))
-        assert big > small + 3 * (1 << 20) * 64
-        for bad in ({"live_packets": 10}, {"job_packets": 1}, {"max_visits": 0}, {"tile": 1000},
-                    {"flush_track": 1e6}, {"flush_track": -1.0}, {"flush_track": float("nan")},
-                    {"tail_visits": (1 << 30) + 1}):
-            with pytest.raises(Exception):
-                rmc.mc_set_tuning(bad)
-        rmc.mc_set_tuning(None)
-        assert rmc.mc_get_tuning()["job_packets"] == 4096 and rmc.mc_get_tuning()["flush_track"] == 65536.0
-    finally:
-        rmc.mc_set_tuning(base)
+    d = rmc.default_tuning()
+    assert d == {"live_packets": 1 << 26, "job_packets": 4096, "max_visits": 64, "tile": 0,
+                 "finish_packets": 1 << 17, "grid_max_packets": 1 << 21, "flush_track": 65536.0,
+                 "tail_visits": 8, "max_generations": 0}
+    m = _medium(L)
+    m.nx = m.nz = 256
+    src = (L.mc_source * 1)(_pencil(L))
+    run = L.mc_run(1 << 26, 0, 0, 0, 16, 1e-4, 10.0, 0)
+
+    def ws(t):
+        return lib.mc_workspace_bytes(C.byref(m), src, 1, C.byref(run), rmc._Options(t, None).ref())
+
+    small = ws({"live_packets": 1 << 20})
+    big = ws({"live_packets": 1 << 22, "job_packets": 1024, "max_visits": 7, "tile": 9})
+    assert big > small + 3 * (1 << 20) * 64 * 2
+    assert ws(None) == lib.mc_workspace_bytes(C.byref(m), src, 1, C.byref(run), None) > big
+    # the same call again is unchanged: nothing was kept
+    assert ws({"live_packets": 1 << 20}) == small
+    for bad in ({"live_packets": 10}, {"job_packets": 1}, {"tile": 1000}, {"flush_track": 1e6},
+                {"flush_track": -1.0}, {"flush_track": float("nan")}, {"tail_visits": (1 << 30) + 1},
+                {"max_generations": 70000}):
+        assert ws(bad) == 0, bad
+        rc = lib.mc_forward(C.byref(m), src, 1, C.byref(run), rmc._Options(bad, None).ref(), 0x2000, None, 0x3000,
+                            1 << 40, None)
+        assert rc == L.MC_ERR_INVALID_ARG, bad
+
+
+def test_timer_handles():
+    """mc_timer: created and destroyed on the host; an empty timer reads zero."""
+    L, lib = _lib()
+    h = C.c_void_p()
+    assert lib.mc_timer_create(C.byref(h)) == 0 and h.value
+    ms, n = C.c_double(1.0), C.c_uint64(7)
+    assert lib.mc_timer_read(h, C.byref(ms), C.byref(n), 1) == 0
+    assert ms.value == 0.0 and n.value == 0
+    assert lib.mc_timer_destroy(h) == 0
+    assert lib.mc_timer_create(None) == L.MC_ERR_INVALID_ARG
+    assert lib.mc_timer_read(None, None, None, 0) == L.MC_ERR_INVALID_ARG
 
 
 def test_batch_arguments_checked_on_host():
@@ -160,20 +175,20 @@ def test_batch_arguments_checked_on_host():
     run4 = L.mc_run(1000, 0, 0, 0, 4, 1e-4, 10.0, 0)
     run5 = L.mc_run(1000, 0, 0, 0, 5, 1e-4, 10.0, 0)
     ok = L.mc_problem(m, src, 1, run4, 0, 0x2000, None)
-    assert lib.mc_batch_workspace_bytes((L.mc_problem * 1)(ok), 1) > 0
-    assert lib.mc_batch_workspace_bytes((L.mc_problem * 1)(ok), 0) == 0
-    assert lib.mc_batch_workspace_bytes(None, 1) == 0
+    assert lib.mc_batch_workspace_bytes((L.mc_problem * 1)(ok), 1, None) > 0
+    assert lib.mc_batch_workspace_bytes((L.mc_problem * 1)(ok), 0, None) == 0
+    assert lib.mc_batch_workspace_bytes(None, 1, None) == 0
     mixed = (L.mc_problem * 2)(ok, L.mc_problem(m, src, 1, run5, 0, 0x2000, None))
-    assert lib.mc_batch_workspace_bytes(mixed, 2) == 0
-    assert lib.mc_run_batch(mixed, 2, 0x3000, 1 << 30, None) == L.MC_ERR_INVALID_ARG
+    assert lib.mc_batch_workspace_bytes(mixed, 2, None) == 0
+    assert lib.mc_run_batch(mixed, 2, None, 0x3000, 1 << 30, None) == L.MC_ERR_INVALID_ARG
     bad = L.mc_problem(m, src, 1, L.mc_run(0, 0, 0, 0, 4, 1e-4, 10.0, 0), 0, 0x2000, None)
-    assert lib.mc_run_batch((L.mc_problem * 1)(bad), 1, 0x3000, 1 << 30, None) == L.MC_ERR_INVALID_ARG
+    assert lib.mc_run_batch((L.mc_problem * 1)(bad), 1, None, 0x3000, 1 << 30, None) == L.MC_ERR_INVALID_ARG
     nocoeffs = L.mc_problem(m, src, 1, run4, 0, None, None)
-    assert lib.mc_run_batch((L.mc_problem * 1)(nocoeffs), 1, 0x3000, 1 << 30, None) == L.MC_ERR_INVALID_ARG
-    assert lib.mc_run_batch((L.mc_problem * 1)(ok), 5000, 0x3000, 1 << 30, None) == \
+    assert lib.mc_run_batch((L.mc_problem * 1)(nocoeffs), 1, None, 0x3000, 1 << 30, None) == L.MC_ERR_INVALID_ARG
+    assert lib.mc_run_batch((L.mc_problem * 1)(ok), 5000, None, 0x3000, 1 << 30, None) == \
         L.MC_ERR_INVALID_ARG
     # too small a workspace is reported before anything is enqueued
-    assert lib.mc_run_batch((L.mc_problem * 1)(ok), 1, 0x3000, 16, None) == L.MC_ERR_WORKSPACE
+    assert lib.mc_run_batch((L.mc_problem * 1)(ok), 1, None, 0x3000, 16, None) == L.MC_ERR_WORKSPACE
 
 
 def test_denoiser_arguments_checked_on_host():
@@ -217,16 +232,16 @@ def test_weight_bound_beyond_the_fixed_point_range_is_unsupported():
     pt.kind, pt.x0, pt.z0, pt.power, pt.prof_h, pt.n_prof = L.MC_SRC_POINT, 1.0, 1.0, 1.0, prof, 1
     src = (L.mc_source * 1)(pt)
     run = L.mc_run(1000, 0, 0, 0, 4, 1e-4, 10.0, 0)
-    assert lib.mc_workspace_bytes(C.byref(m), src, 1, C.byref(run)) > 0
+    assert lib.mc_workspace_bytes(C.byref(m), src, 1, C.byref(run), None) > 0
     run.w_threshold, run.roulette_m = 1.0, 2.0 ** 31      # 2 x 2^31 = 2^32: still inside
-    assert lib.mc_workspace_bytes(C.byref(m), src, 1, C.byref(run)) > 0
+    assert lib.mc_workspace_bytes(C.byref(m), src, 1, C.byref(run), None) > 0
     run.roulette_m = 2.0 ** 32                           # 2^33
-    assert lib.mc_workspace_bytes(C.byref(m), src, 1, C.byref(run)) == 0
-    rc = lib.mc_forward(C.byref(m), src, 1, C.byref(run), 0x2000, None, 0x3000, 1 << 30, None)
+    assert lib.mc_workspace_bytes(C.byref(m), src, 1, C.byref(run), None) == 0
+    rc = lib.mc_forward(C.byref(m), src, 1, C.byref(run), None, 0x2000, None, 0x3000, 1 << 30, None)
     assert rc == L.MC_ERR_UNSUPPORTED
     run.roulette_m, run.w_threshold = 10.0, 1e-4
     prof[0] = 1e10
-    assert lib.mc_forward(C.byref(m), src, 1, C.byref(run), 0x2000, None, 0x3000, 1 << 30, None) == \
+    assert lib.mc_forward(C.byref(m), src, 1, C.byref(run), None, 0x2000, None, 0x3000, 1 << 30, None) == \
         L.MC_ERR_UNSUPPORTED
 
 

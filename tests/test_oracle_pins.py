@@ -522,3 +522,170 @@ def test_equal_count_map_launch_is_unbiased(oracle_lib):
     # the summed absorbed power agrees too (a global check of the normalisation)
     pa, pb = (ph.mua * a[:, 0]).sum((1, 2)), (ph.mua * b[:, 0]).sum((1, 2))
     assert abs(pa.mean() - pb.mean()) < 3 * np.sqrt(pa.var(ddof=1) / 8 + pb.var(ddof=1) / 8)
+
+
+# ---------------------------------------------------------------- roulette law (Sec. 3, Sec. 6)
+def _roulette_case():
+    """A medium where most packets fall below w_th = 0.05 before they leave:
+    strong absorption (albedo 0.91) and scattering in a small square."""
+    ph = P.homogeneous(8, 8, 0.5, 2.0, 20.0, 0.0)
+    return ph, P.pencil_top_centre(ph)
+
+
+def test_roulette_maps_match_a_negligible_threshold(oracle_lib):
+    """Russian roulette at w_th = 0.05 (survive with 1/m, weight x m, m = 4)
+    is an unbiased termination: its maps agree within the standard error with
+    those of w_th = 1e-8, where roulette (almost) never fires and packets end
+    only by escape.  Roulette here kills a large share of the packets, so a
+    wrong survival branch (probability or weight factor) shifts every map."""
+    O = oracle_lib
+    ph, specs = _roulette_case()
+    med, src = O.medium_from(ph), O.sources_from(specs)
+    res = {}
+    for wth in (0.05, 1e-8):
+        outs, leds = _batches(O, med, src, dict(seed=6, n_harm=3, w_threshold=wth, roulette_m=4.0), B=8,
+                              n_per=40_000)
+        res[wth] = (outs, leds)
+    high = res[0.05][1]
+    launched = sum(l.launched for l in high)
+    # roulette decides the fate of a large share of the packets: its kills
+    # remove at least 20% of them (each kill carries less than w_th of weight,
+    # so loss / w_th bounds the number of kills from below)
+    assert sum(l.roulette_loss for l in high) / 0.05 > 0.2 * launched
+    assert sum(l.roulette_gain for l in high) > 0.01 * launched
+    assert sum(l.roulette_gain for l in res[1e-8][1]) < 1e-6 * launched
+    a, b = res[0.05][0], res[1e-8][0]
+    ma, mb = a.mean(0), b.mean(0)
+    se = np.sqrt(a.var(0, ddof=1) / len(a) + b.var(0, ddof=1) / len(b))
+    big = np.abs(ma[0]) > 0.02 * np.abs(ma[0]).max()
+    z = np.abs(ma - mb)[:, big] / np.maximum(se[:, big], 1e-300)
+    assert np.mean(z < 3) > 0.97 and np.max(z) < 5.5, (np.mean(z < 3), np.max(z))
+    # the absorbed power of the whole map agrees too
+    pa, pb = (ph.mua * a[:, 0]).sum((1, 2)), (ph.mua * b[:, 0]).sum((1, 2))
+    assert abs(pa.mean() - pb.mean()) < 3.5 * np.sqrt(pa.var(ddof=1) / 8 + pb.var(ddof=1) / 8)
+
+
+def test_roulette_expected_gain_equals_expected_loss(oracle_lib):
+    """At a roulette event of weight W, survival with probability 1/m and
+    weight m W gains (m-1) W with probability 1/m and loses W with
+    probability 1 - 1/m: the expected gain and loss are both (1 - 1/m) W.
+    So the per-packet mean of (gain - loss) is zero within its standard
+    error, while the gain itself is far from zero.  A survival probability p
+    other than 1/m with the weight factor m makes gain / loss = (m-1) p / (1-p)."""
+    O = oracle_lib
+    ph, specs = _roulette_case()
+    med, src = O.medium_from(ph), O.sources_from(specs)
+    for m in (4.0, 10.0):
+        _, leds = _batches(O, med, src, dict(seed=9, n_harm=0, w_threshold=0.05, roulette_m=m), B=16,
+                           n_per=20_000)
+        net = np.array([(l.roulette_gain - l.roulette_loss) / l.launched for l in leds])
+        gain = np.array([l.roulette_gain / l.launched for l in leds])
+        mn, se = batch_mean_se(net)
+        mg, _ = batch_mean_se(gain)
+        assert mg > 30 * se, (m, mg, se)
+        assert abs(mn) < 4 * se, (m, mn, se)
+
+
+# ---------------------------------------------------------------- angular source profiles
+def test_point_source_profile_quadrature(oracle_lib):
+    """A point source with an angular profile of cosine and sine terms up to
+    order 5 (p = c0/2pi + (1/pi) sum (c_n cos nt + s_n sin nt), the expansion
+    of Sec. 3.1) in a non-scattering medium: the maps equal the angular
+    quadrature of p(t) times the exact attenuated chords.  Every coefficient
+    of the profile, its sign and its cosine/sine role shows in the maps."""
+    O = oracle_lib
+    rng = np.random.default_rng(17)
+    nz, nx, dx, N = 5, 5, 1.0, 6
+    mua = rng.uniform(0.05, 0.8, size=(nz, nx))
+    x0, z0 = 2.3, 2.6
+    n = 5
+    prof = np.zeros(2 * n + 1)
+    prof[0] = 1.0
+    prof[1:n + 1] = [0.3, -0.2, 0.15, 0.1, -0.08]        # c_1..c_5
+    prof[n + 1:] = [0.25, 0.12, -0.18, 0.07, 0.05]       # s_1..s_5
+    M = 4000
+    exp = np.zeros((2 * N + 1, nz, nx))
+    for t in (np.arange(M) + 0.5) / M * 2 * np.pi - np.pi:
+        p = prof[0] / (2 * np.pi) + sum(prof[k] * np.cos(k * t) + prof[n + k] * np.sin(k * t)
+                                        for k in range(1, n + 1)) / np.pi
+        exp += 2 * np.pi * p * ballistic_tally(mua, dx, x0, z0, t, N)
+    exp /= M
+    med = O.Medium(mua, np.zeros((nz, nx)), np.zeros((nz, nx)), dx)
+    src = [O.Source(O.POINT, x0=x0, z0=z0, prof=prof)]
+    outs, _ = _batches(O, med, src, dict(seed=3, n_harm=N), B=10, n_per=30_000)
+    mean, se = batch_mean_se(outs)
+    z = np.abs(mean - exp) / np.maximum(se, 1e-12)
+    assert np.max(z) < 5.0, np.max(z)
+    # the profile's own harmonics reach the tally: the source pixel's a_n, b_n
+    # track c_n, s_n (an isotropic or cosine-only profile would not)
+    assert np.abs(mean[N + 1:N + n + 1]).max() > 20 * se[N + 1:N + n + 1].max()
+
+
+# ---------------------------------------------------------------- reciprocity at the paper's validation geometry
+def _e2_setup():
+    """The adjoint validation geometry of Sec. 4.1: 40 mm x 40 mm on 101 x 101
+    pixels, 10 harmonics, source at the centre, detectors on the line 23.6 mm
+    deep.  The paper gives no optical properties for it; those of its forward
+    validation (mua 0.01, mus 10 1/mm, g 0.9) are used."""
+    n = 101
+    ph = P.homogeneous(n, n, 40.0 / n, 0.01, 10.0, 0.9)
+    dx = ph.dx
+    s = (int(20.0 / dx), int(20.0 / dx))                 # (iz, ix) of the centre
+    d = (int(23.6 / dx), int(21.4 / dx))                 # a detector pixel on the line z = 23.6 mm
+    return ph, s, d
+
+
+def test_reciprocity_anisotropic_detector_e2(oracle_lib):
+    """Case 2 of Sec. 4.1 (eq. adj_definition): an isotropic source and a
+    detector with angular weight sin^2(2(t - alpha))/pi, rotated by alpha so
+    that the profile has a sine term of order 4 as well as a cosine term.  The
+    forward readout int phi P_d dt = c0 a0 + 2 (c4 a4 + s4 b4) at the
+    detector equals the adjoint field (detector as source, profile mirrored
+    for the adjoint) read isotropically at the source."""
+    O = oracle_lib
+    ph, s, d = _e2_setup()
+    A = ph.dx ** 2
+    med = O.medium_from(ph)
+    al = 0.3
+    prof = np.zeros(9)                                   # P_d = 2 pi p: c0, c1..c4, s1..s4
+    prof[0] = 1 / (2 * np.pi)
+    prof[4] = -np.cos(4 * al) / (4 * np.pi)
+    prof[8] = -np.sin(4 * al) / (4 * np.pi)
+    N = 10
+    fwd_src = [O.Source(O.MAP, map=_pixel_map(ph, *s, 1.0 / (2 * np.pi * A)))]
+    adj_src = [O.Source(O.MAP, map=_pixel_map(ph, *d, 1.0 / A), prof=prof)]
+    fo, _ = _batches(O, med, fwd_src, dict(seed=31, n_harm=N), B=8, n_per=12_500)
+    ad, _ = _batches(O, med, adj_src, dict(seed=32, n_harm=N, stream_tag=1, adjoint=1), B=8, n_per=12_500)
+    lhs = (prof[0] * fo[:, 0] + 2 * (prof[4] * fo[:, 4] + prof[8] * fo[:, N + 4]))[:, d[0], d[1]]
+    rhs = ad[:, 0][:, s[0], s[1]] / (2 * np.pi)
+    ml, sl = batch_mean_se(lhs)
+    mr, sr = batch_mean_se(rhs)
+    assert abs(ml - mr) < 4 * np.hypot(sl, sr), (ml, mr, sl, sr)
+    assert abs(ml - mr) < 0.1 * abs(ml)
+
+
+def test_reciprocity_distributed_e2(oracle_lib):
+    """Case 3 of Sec. 4.1: a distributed isotropic source density S(x) and a
+    distributed isotropic detector D(x) (smooth blobs, signed detector):
+    <L S, D> = sum_i A D_i a0_i of the forward field equals
+    <S, L* D> = sum_i A S_i a0*_i of the adjoint field whose source is D."""
+    O = oracle_lib
+    ph, _, _ = _e2_setup()
+    A = ph.dx ** 2
+    c = (np.arange(ph.nx) + 0.5) * ph.dx
+    X, Z = np.meshgrid(c, c)
+    S = np.exp(-((X - 18.0) ** 2 + (Z - 19.0) ** 2) / (2 * 1.5 ** 2))
+    D = np.exp(-((X - 21.5) ** 2 + (Z - 23.6) ** 2) / (2 * 1.0 ** 2)) \
+        - 0.3 * np.exp(-((X - 25.0) ** 2 + (Z - 20.0) ** 2) / (2 * 1.2 ** 2))
+    med = O.medium_from(ph)
+    N = 10
+    fo, _ = _batches(O, med, [O.Source(O.MAP, map=S)], dict(seed=41, n_harm=N), B=8, n_per=12_500)
+    ad, _ = _batches(O, med, [O.Source(O.MAP, map=D)], dict(seed=42, n_harm=N, stream_tag=1, adjoint=1), B=8,
+                     n_per=12_500)
+    lhs = (fo[:, 0] * D).sum((1, 2)) * A
+    rhs = (ad[:, 0] * S).sum((1, 2)) * A
+    ml, sl = batch_mean_se(lhs)
+    mr, sr = batch_mean_se(rhs)
+    # the comparison resolves the readout to a few percent, and both sides agree within it
+    assert np.hypot(sl, sr) < 0.05 * abs(ml), (ml, sl, sr)
+    assert abs(ml - mr) < 4 * np.hypot(sl, sr), (ml, mr, sl, sr)
