@@ -51,7 +51,8 @@ typedef enum {
     MC_ERR_INVALID_ARG = 1,   /* a size, pointer or parameter is out of range */
     MC_ERR_UNSUPPORTED = 2,   /* a valid request this library does not serve */
     MC_ERR_DEVICE = 3,        /* a HIP call or launch failed */
-    MC_ERR_WORKSPACE = 4      /* workspace missing or smaller than mc_workspace_bytes() */
+    MC_ERR_WORKSPACE = 4,     /* workspace missing or smaller than mc_workspace_bytes() */
+    MC_ERR_SCRATCH = 5        /* mc_run_noalloc: the run's workspace exceeds MC_SCRATCH_BYTES */
 } mc_status;
 
 /* Optical properties (Sec. 2 and 3): device FP32 maps [nz][nx] of the
@@ -261,6 +262,28 @@ size_t mc_batch_workspace_bytes(const mc_problem *probs_h, int n_probs, const mc
  * are exact, see mc_forward).  probs_h: host array of n_probs (1 .. MC_BATCH_MAX) problems. */
 mc_status mc_run_batch(const mc_problem *probs_h, int n_probs, const mc_options *opts, void *workspace_d,
                        size_t workspace_bytes, void *stream);
+
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation: a forward
+ * (adjoint = 0, as mc_forward) or adjoint (adjoint = 1, as mc_adjoint) run
+ * whose workspace is the library's own static device array of
+ * MC_SCRATCH_BYTES, which each GPU the library runs on holds until the
+ * process ends.  The caller passes inputs and outputs only.  The call
+ * allocates nothing (no device, host or pinned memory, no events:
+ * opts->timer must be NULL, else MC_ERR_INVALID_ARG) and, like every entry
+ * point, does not wait for the device.  Unless opts->tuning sets
+ * live_packets, the tiled transport keeps the largest pool of live packets
+ * whose queues fit the scratch; the results equal mc_forward's / mc_adjoint's
+ * (bitwise while the FP64 sums are exact).  A run whose workspace exceeds
+ * MC_SCRATCH_BYTES even with the smallest pool (1024 live packets), or with
+ * the caller's live_packets, returns MC_ERR_SCRATCH before anything is
+ * enqueued.  Every call on one GPU uses that GPU's one array and overwrites
+ * it (the call's own kernels clear what must start at zero): calls that
+ * overlap on one GPU -- on different streams, or from different threads --
+ * race and give wrong results; serialise them (one stream, or events). */
+#define MC_SCRATCH_BYTES (256ull << 20)
+mc_status mc_run_noalloc(const mc_medium *medium, const mc_source *src, int n_src, const mc_run *run, int adjoint,
+                         const mc_options *opts, double *coeffs_d, mc_ledger *ledger_d, void *stream);
 
 /* Residual (Sec. 2 eq. error_function3, Sec. 6): H = mua a0 (Grueneisen 1),
  * r = hmeas - H, q* = mua r (per unit angle), eps = (dx^2 / 2) sum r^2.

@@ -11,7 +11,7 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librmc.so")
 
-MC_OK, MC_ERR_INVALID_ARG, MC_ERR_UNSUPPORTED, MC_ERR_DEVICE, MC_ERR_WORKSPACE = range(5)
+MC_OK, MC_ERR_INVALID_ARG, MC_ERR_UNSUPPORTED, MC_ERR_DEVICE, MC_ERR_WORKSPACE, MC_ERR_SCRATCH = range(6)
 MC_SRC_PENCIL, MC_SRC_LINE, MC_SRC_POINT, MC_SRC_MAP = range(4)
 MC_FLAG_LITERAL_TRUNCATION = 1
 MC_FLAG_EQUAL_COUNT = 2
@@ -21,6 +21,7 @@ MC_NHARM_MAX = 32
 SYMBOLS = ("mc_workspace_bytes", "mc_forward", "mc_adjoint", "mc_residual", "mc_gradient", "mc_absorbed",
            "mc_adjoint_source", "mc_gradient_h", "mc_detect", "mc_trace", "mc_philox_fill", "mc_default_tuning",
            "mc_timer_create", "mc_timer_destroy", "mc_timer_read", "mc_batch_workspace_bytes", "mc_run_batch",
+           "mc_run_noalloc",
            "mc_binned_workspace_bytes", "mc_run_binned",
            "mc_status_string", "mc_build_info", "dn_conv3x3_fwd", "dn_conv3x3_wgrad",
            "mb_lds_atomics", "mb_global_atomics_f64", "mb_copy", "mb_fma_f32", "mb_wall_clock_khz")
@@ -117,6 +118,8 @@ def load() -> C.CDLL:
     lib.mc_timer_read.restype = St
     lib.mc_default_tuning.argtypes = [P(mc_tuning)]
     lib.mc_default_tuning.restype = St
+    lib.mc_run_noalloc.argtypes = [P(mc_medium), P(mc_source), C.c_int, P(mc_run), C.c_int, P(mc_options), V, V, V]
+    lib.mc_run_noalloc.restype = St
     lib.mc_batch_workspace_bytes.argtypes = [P(mc_problem), C.c_int, P(mc_options)]
     lib.mc_batch_workspace_bytes.restype = C.c_size_t
     lib.mc_run_batch.argtypes = [P(mc_problem), C.c_int, P(mc_options), V, C.c_size_t, V]

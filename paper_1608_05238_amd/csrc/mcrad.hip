@@ -1995,7 +1995,7 @@ struct TileTuning {
     uint64_t grid_max = kGridMaxPackets;
     double flush_track = kFlushTrackMax;
     uint32_t max_gen = 0;      // 0: kGenBase + kGenPerPool per pool of live packets the run holds
-    uint32_t slice = kSlice;   // not a caller knob
+    uint32_t slice = kSlice;   // not a caller knob: the no-alloc entry point narrows it to save scratch
 };
 
 bool tuning_from(const mc_options *o, TileTuning &v) {
@@ -2594,6 +2594,63 @@ mc_status run_binned(const mc_medium *m, const mc_source *src, int n_src, const 
     return hipGetLastError() == hipSuccess ? MC_OK : MC_ERR_DEVICE;
 }
 
+// ------------------------------------------------------------------ no-alloc runs
+// mc_run_noalloc takes its workspace from this file-scope device array (each
+// GPU the library runs on holds its own copy until the process ends).  In
+// host code its name is only a stand-in: its device address comes from
+// hipGetSymbolAddress, taken once per device and kept in scratch_table.
+constexpr size_t kScratchBytes = MC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+constexpr uint32_t kScratchSlice = 64;   // narrower queue slices: less padding held in the scratch
+
+struct ScratchTable {
+    std::mutex mu;
+    void *ptr[kMaxDevices] = {};
+};
+ScratchTable &scratch_table() {
+    static ScratchTable t;
+    return t;
+}
+
+// The device address of the current device's scratch (nullptr on failure).
+void *scratch_ptr() {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    ScratchTable &t = scratch_table();
+    std::lock_guard<std::mutex> g(t.mu);
+    if (!t.ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+        t.ptr[dev] = p;
+    }
+    return t.ptr[dev];
+}
+
+// The tuning of a no-alloc run: the caller's, with narrow slices, and -- unless
+// the caller fixed live_packets -- the largest pool whose workspace fits the
+// scratch.  Returns false if the run does not fit (host arithmetic only).
+bool noalloc_tuning(const mc_medium *m, const mc_source *src, int n_src, const mc_run *run, int adjoint,
+                    const mc_options *opts, TileTuning &tt) {
+    tt.slice = kScratchSlice;
+    if (!is_tiled(m, run, tt)) return layout(m, src, run).total <= kScratchBytes;
+    const BatchProblem one{m, src, n_src, run, adjoint, nullptr, nullptr};
+    auto fits = [&](uint64_t live) {
+        TileTuning t = tt;
+        t.live = live;
+        return batch_layout(&one, 1, t).total <= kScratchBytes;
+    };
+    if (opts && opts->tuning && opts->tuning->live_packets) return fits(tt.live);
+    if (!fits(1024)) return false;
+    uint64_t lo = 1024, hi = tt.live;   // largest live in [1024, tt.live] that fits
+    while (lo < hi) {
+        const uint64_t mid = lo + (hi - lo + 1) / 2;
+        if (fits(mid)) lo = mid; else hi = mid - 1;
+    }
+    tt.live = lo;
+    return true;
+}
+
 }  // namespace
 
 extern "C" {
@@ -2666,6 +2723,20 @@ mc_status mc_adjoint(const mc_medium *medium, const mc_source *src, int n_src, c
     if (!tuning_from(opts, tt)) return MC_ERR_INVALID_ARG;
     return run_mc(medium, src, n_src, run, tt, opts ? opts->timer : nullptr, coeffs_d, ledger_d, workspace_d,
                   workspace_bytes, reinterpret_cast<hipStream_t>(stream), 1);
+}
+
+mc_status mc_run_noalloc(const mc_medium *medium, const mc_source *src, int n_src, const mc_run *run, int adjoint,
+                         const mc_options *opts, double *coeffs_d, mc_ledger *ledger_d, void *stream) {
+    mc_status st = validate(medium, src, n_src, run);
+    if (st != MC_OK) return st;
+    if (!coeffs_d || (adjoint != 0 && adjoint != 1) || (opts && opts->timer)) return MC_ERR_INVALID_ARG;
+    TileTuning tt;
+    if (!tuning_from(opts, tt)) return MC_ERR_INVALID_ARG;
+    if (!noalloc_tuning(medium, src, n_src, run, adjoint, opts, tt)) return MC_ERR_SCRATCH;
+    void *ws = scratch_ptr();
+    if (!ws) return MC_ERR_DEVICE;
+    return run_mc(medium, src, n_src, run, tt, nullptr, coeffs_d, ledger_d, ws, kScratchBytes,
+                  reinterpret_cast<hipStream_t>(stream), adjoint);
 }
 
 mc_status mc_residual(const mc_medium *m, const double *coeffs_d, const double *hmeas_d, double *q_star_d,
@@ -2789,6 +2860,7 @@ const char *mc_status_string(mc_status s) {
         case MC_ERR_UNSUPPORTED: return "unsupported";
         case MC_ERR_DEVICE: return "device error";
         case MC_ERR_WORKSPACE: return "workspace too small or misaligned";
+        case MC_ERR_SCRATCH: return "the run's workspace exceeds the library's static scratch (MC_SCRATCH_BYTES)";
     }
     return "unknown status";
 }

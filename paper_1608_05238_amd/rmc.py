@@ -225,6 +225,24 @@ def mc_adjoint(medium: Medium, sources: Sequence, run: L.mc_run, out=None, works
     return out, led
 
 
+def mc_run_noalloc(medium: Medium, sources: Sequence, run: L.mc_run, adjoint: bool = False, out=None, ledger=True,
+                   stream=None, tuning: Optional[dict] = None):
+    """A forward or adjoint run on the library's static scratch (no workspace,
+    no allocation inside the call; see mc_run_noalloc in include/mcrad.h).
+    The binding itself allocates the output and ledger if not given."""
+    lib = L.load()
+    dev = medium.mua.device
+    src = _Sources(sources, dev)
+    K = 2 * run.n_harm + 1
+    if out is None:
+        out = torch.empty((K, medium.nz, medium.nx), dtype=torch.float64, device=dev)
+    led = torch.zeros(C.sizeof(L.mc_ledger), dtype=torch.uint8, device=dev) if ledger else None
+    L.check("mc_run_noalloc", lib.mc_run_noalloc(C.byref(medium.c()), src.arr, src.n, C.byref(run), int(bool(adjoint)),
+                                                 _Options(tuning, None).ref(), out.data_ptr(), _ptr(led),
+                                                 _stream(stream)))
+    return out, led
+
+
 def mc_binned(medium: Medium, sources: Sequence, run: L.mc_run, n_bins: int, adjoint: bool = False, ledger=True,
               stream=None):
     """Discrete-ordinates comparison tally: radiance averaged over n_bins equal
