@@ -145,22 +145,29 @@ typedef struct {
  *                 workgroups per CU)
  *  finish_packets once every packet is launched and at most this many remain
  *                 they finish without migration (default: the smaller of
- *                 2^17 and live_packets / 128)
+ *                 2^16 and live_packets / 128)
  *  grid_max_packets  a run whose tally fits one workgroup's LDS uses the
  *                 whole-grid kernel only up to this many packets, larger runs
  *                 the tiled transport (default 2^21)
  *  flush_track    a pixel visit whose accumulated track length, in units of
  *                 the run's weight bound, exceeds this many pixels is added
  *                 to the tile tally in parts, 0 .. 65536 (default 65536)
- *  tail_visits    once a job has handed out its last packet, its packets
- *                 pause after this many more visits, 0 .. 2^30 (default 8)
+ *  tail_visits    once a job has turned quiet (quiet_percent), its packets
+ *                 pause after this many more visits, 0 .. 2^30 (default 4)
  *  max_generations  tiled generations enqueued per call, 1 .. 65536
  *                 (default 0: 448 + 48 per pool of live_packets the run's
  *                 packets fill).  The host enqueues this many without
  *                 waiting; a generation that finds the finisher threshold
  *                 reached does nothing.  Packets still in flight (or not yet
  *                 launched) after the last one are moved to their end by the
- *                 finisher, so the results never depend on it. */
+ *                 finisher, so the results never depend on it.
+ *  min_job_packets  a generation whose records would not give every
+ *                 workgroup of the tiled kernel two jobs cuts its tiles into
+ *                 smaller jobs, down to this size, 64 .. 2^20 (default 512)
+ *  quiet_percent  a job turns quiet once the packets whose stay in its tile
+ *                 has not ended number at most this percent of
+ *                 min(job packets, 512); its packets then pause after
+ *                 tail_visits more visits, 1 .. 100 (default 50) */
 typedef struct {
     uint64_t live_packets;
     uint32_t job_packets;
@@ -171,6 +178,9 @@ typedef struct {
     float flush_track;
     uint32_t tail_visits;
     uint32_t max_generations;
+    uint32_t min_job_packets;
+    uint32_t quiet_percent;
+    uint32_t reserved;   /* must be 0 */
 } mc_tuning;
 
 /* The built-in defaults, every field filled in. */

@@ -68,7 +68,8 @@ class mc_problem(C.Structure):
 class mc_tuning(C.Structure):
     _fields_ = [("live_packets", C.c_uint64), ("job_packets", C.c_uint32), ("max_visits", C.c_uint32),
                 ("tile", C.c_uint32), ("grid_max_packets", C.c_uint32), ("finish_packets", C.c_uint64),
-                ("flush_track", C.c_float), ("tail_visits", C.c_uint32), ("max_generations", C.c_uint32)]
+                ("flush_track", C.c_float), ("tail_visits", C.c_uint32), ("max_generations", C.c_uint32),
+                ("min_job_packets", C.c_uint32), ("quiet_percent", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class mc_options(C.Structure):

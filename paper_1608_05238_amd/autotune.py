@@ -1,6 +1,6 @@
 """Autotuner of the tiled transport: live packets, job size, visits per stay,
-visits after a job's last packet and the tile side (any other mc_tuning
-field can be searched through the `space` argument).
+the pause rule of quiet jobs, the smallest job and the tile side (any other
+mc_tuning field can be searched through the `space` argument).
 
 `tune()` times short forward (or adjoint) runs of the caller's problem over
 candidate tunings and returns the fastest (record it in an optional JSON
@@ -9,7 +9,7 @@ the same for a batch of problems (mc_run_batch) on a sample of it.  The
 library keeps no tuning state: the caller passes the tuning it got to its
 runs (`tuning=` of mc_forward, mc_adjoint, mc_run_batch).  The default search
 is coordinate-wise: each knob in turn takes the candidate that runs fastest
-with the others held at the best values found so far (13 trials); `grid=True`
+with the others held at the best values found so far (19 trials); `grid=True`
 tries every combination.  The tuning changes only the schedule (which packets
 move together, how often they are sorted); the result of a run is the same
 (bitwise while its FP64 sums are exact, see mc_forward in include/mcrad.h).
@@ -32,7 +32,9 @@ DEFAULT_CANDIDATES = {
     "live_packets": (1 << 25, 1 << 26),
     "job_packets": (2048, 4096, 8192),
     "max_visits": (32, 64, 128),
-    "tail_visits": (4, 8, 16),
+    "tail_visits": (2, 4, 8),
+    "quiet_percent": (35, 50, 75),
+    "min_job_packets": (256, 512, 1024),
     "tile": (12, 16),
 }
 

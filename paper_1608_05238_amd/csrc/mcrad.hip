@@ -121,6 +121,24 @@ __device__ __forceinline__ Hot hot_of(const ProbDev &S) {
     return Hot{S.nx, S.nz, S.tag, S.flags, S.seed, S.wth, S.rm, S.inv_rm};
 }
 
+// The device pointers held in device memory (ProbDev's) are generic: an
+// access through one compiles to a flat_* instruction, which counts on the
+// LDS counter as well as the vector-memory one, so a wait for an LDS read
+// also waits for every such load or atomic in flight.  They all point into
+// global memory; these two accesses say so (global_* instructions).
+typedef float v4f_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float4 load_medium(const float4 *med, int i) {
+    const v4f_t v = ((const __attribute__((address_space(1))) v4f_t *)med)[i];
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+
+// An FP64 add to a tally in global memory whose old value nobody reads.
+__device__ __forceinline__ void tally_add(double *p, double v) {
+    __hip_atomic_fetch_add((__attribute__((address_space(1))) double *)p, v, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // ------------------------------------------------------------------ Philox
 // Philox4x32-10 (Salmon et al., SC'11): 10 rounds of two 32x32->64-bit
 // products; key bumped by the Weyl constants between rounds.
@@ -676,7 +694,7 @@ __global__ void __launch_bounds__(grid_block(NH)) k_transport_grid(GridArgs A) {
         const bool live = p.alive;
         const int pix = live ? p.iz * H.nx + p.ix : 0;
         float T = 0.f, dw = 0.f;
-        const float4 mm = med[pix];
+        const float4 mm = load_medium(med, pix);
         int ev = step(H, p, mm, T, dw);
         ev = live ? ev : EV_NONE;
         T = live ? T : 0.f;
@@ -708,9 +726,13 @@ __global__ void __launch_bounds__(grid_block(NH)) k_transport_grid(GridArgs A) {
     if (lane == 0) atomicAdd(&s_mag, wm);
     __syncthreads();
     if (threadIdx.x == 0 && !(s_mag < 0x1p62f)) atomicAdd(S.ledc + 4, 1ull);   // see k_normalise
+    // read once: the atomics below may alias S for all the compiler knows, and
+    // a reload per add would make each add wait for the one before it
+    double *const t64 = S.t64;
+    const double fx_inv = S.fx_inv;
     for (int i = threadIdx.x; i < npix * K; i += blockDim.x) {
-        const double v = (double)(long long)gfx[i] * S.fx_inv;
-        if (v != 0.0) unsafeAtomicAdd(S.t64 + i, v);
+        const double v = (double)(long long)gfx[i] * fx_inv;
+        if (v != 0.0) tally_add(t64 + i, v);
     }
 }
 
@@ -752,6 +774,9 @@ struct Gen {
     uint32_t live;                // packets kept alive per generation
     uint32_t cap_c, cap_l;        // slots of a pool's carried and launch regions
     uint32_t job_size, max_visits, tail_visits, finish_at;
+    uint32_t job_min;             // smallest job a generation with few packets splits its tiles into
+    uint32_t slots;               // workgroups of the tile kernel
+    uint32_t quiet_pct;           // a job turns quiet when this percent of its lanes' worth of stays is left
     uint32_t slice;               // slots a wave reserves at a time in a carried region (64 .. 256)
     const ProbDev *probs;
     const uint32_t *tile_prob;    // problem of each global tile
@@ -904,31 +929,41 @@ __device__ void gen_scan(const Gen &G, int g, uint32_t *buf, int np, const uint3
     uint32_t *s_rec = buf, *s_job = buf + kGenBlock;
     const int per = (G.ntiles + kGenBlock - 1) / kGenBlock;
     const int a = t * per, b = min(G.ntiles, a + per);
-    uint32_t nrec = 0, njob = 0;
-    for (int i = a; i < b; ++i) {
-        const uint32_t c = G.tile_count[i];
-        nrec += c;
-        njob += (c + G.job_size - 1) / G.job_size;
-    }
+    uint32_t nrec = 0;
+    for (int i = a; i < b; ++i) nrec += G.tile_count[i];
     s_rec[t] = nrec;
-    s_job[t] = njob;
     __syncthreads();
     for (int off = 1; off < kGenBlock; off <<= 1) {   // inclusive Hillis-Steele scan
-        const uint32_t vr = t >= off ? s_rec[t - off] : 0u, vj = t >= off ? s_job[t - off] : 0u;
+        const uint32_t vr = t >= off ? s_rec[t - off] : 0u;
         __syncthreads();
         s_rec[t] += vr;
+        __syncthreads();
+    }
+    const uint32_t total = s_rec[kGenBlock - 1];
+    // job size: job_size, or smaller when the generation's records would not
+    // give every workgroup two jobs (never below job_min): a generation with
+    // few packets then spreads its larger tiles over several workgroups
+    const uint32_t want = (uint32_t)(((uint64_t)total + 2ull * G.slots - 1) / (2ull * G.slots));
+    const uint32_t js = min(G.job_size, max(G.job_min, want));
+    uint32_t njob = 0;
+    for (int i = a; i < b; ++i) njob += (G.tile_count[i] + js - 1) / js;
+    s_job[t] = njob;
+    __syncthreads();
+    for (int off = 1; off < kGenBlock; off <<= 1) {
+        const uint32_t vj = t >= off ? s_job[t - off] : 0u;
+        __syncthreads();
         s_job[t] += vj;
         __syncthreads();
     }
-    const uint32_t total = s_rec[kGenBlock - 1], total_jobs = s_job[kGenBlock - 1];
+    const uint32_t total_jobs = s_job[kGenBlock - 1];
     const bool fits = total <= G.live && total_jobs <= G.max_jobs;   // hold by construction
     uint32_t roff = s_rec[t] - nrec, joff = s_job[t] - njob;
     for (int i = a; i < b; ++i) {
         const uint32_t c = G.tile_count[i];
         G.tile_cursor[i] = roff;
         if (fits)
-            for (uint32_t s0 = 0; s0 < c; s0 += G.job_size)
-                G.jobs[joff++] = make_uint4((uint32_t)i, roff + s0, min(G.job_size, c - s0), G.tile_prob[i]);
+            for (uint32_t s0 = 0; s0 < c; s0 += js)
+                G.jobs[joff++] = make_uint4((uint32_t)i, roff + s0, min(js, c - s0), G.tile_prob[i]);
         roff += c;
         G.tile_count[i] = 0;
     }
@@ -1159,6 +1194,7 @@ k_transport_tile(Gen G, int g) {
     uint32_t *sadds = reinterpret_cast<uint32_t *>(smed + G.tw * G.th);   // fixed_add_raw adds per pixel
     __shared__ uint32_t s_job[5];
     __shared__ uint32_t s_next;
+    __shared__ uint32_t s_left;   // packets of the job whose stay has not ended
     __shared__ float s_mag;
     GenCtl *C = G.ctl;
     if (C->done) return;
@@ -1183,6 +1219,7 @@ k_transport_tile(Gen G, int g) {
             s_job[3] = jb.z;
             s_job[4] = jb.w;
             s_next = 0;
+            s_left = jb.z;
             s_mag = 0.f;
         }
         __syncthreads();
@@ -1208,7 +1245,7 @@ k_transport_tile(Gen G, int g) {
         for (int i = threadIdx.x; i < ntp; i += blockDim.x) {
             const int gx = tx0 + i % G.tw, gz = tz0 + i / G.tw;
             const bool in_grid = gx < H.nx && gz < H.nz;
-            smed[i] = in_grid ? gmed[gz * H.nx + gx] : make_float4(0.f, 0.f, 0.f, 0.f);
+            smed[i] = in_grid ? load_medium(gmed, gz * H.nx + gx) : make_float4(0.f, 0.f, 0.f, 0.f);
         }
         __syncthreads();
 
@@ -1225,7 +1262,13 @@ k_transport_tile(Gen G, int g) {
         // load waits for memory.
         bool more = true, has_next = false;
         uint32_t nslot = kNone;   // claimed slot whose record is not loaded yet
-        uint32_t tail_nvis = 0;   // visits of the current stay when the job ran out of packets
+        // The job turns quiet once the stays not yet ended are at most
+        // quiet_pct percent of its lanes' worth (min(cnt, lanes)); from then
+        // on a packet pauses after tail_visits more visits, so the workgroup
+        // is not held by its longest stays (they resume next generation).
+        const uint32_t quiet_at = (uint32_t)(((uint64_t)min(cnt, (uint32_t)kBlockTile) * G.quiet_pct) / 100u);
+        bool quiet = false;       // wave-uniform
+        uint32_t tail_nvis = 0;   // visits of the current stay when the job turned quiet
         // (the last word is the packet id alone: a load whose destination
         // registers are partly dead lets them be reused, and the reuse must then
         // wait for the load)
@@ -1246,14 +1289,18 @@ k_transport_tile(Gen G, int g) {
             const int lp = live ? __mul24(p.iz - tz0, G.tw) + (p.ix - tx0) : 0;
             const float4 mm = smed[lp];
             // free record registers take the record of the slot claimed earlier
+            // (the slot index is checked here, a stay after its load, not at
+            // the claim, where the check would wait for that load)
             if (!has_next && nslot != kNone) {
-                const uint4 *r = reinterpret_cast<const uint4 *>(in + nslot);
-                nr0 = r[0];
-                nr1 = r[1];
-                nr2 = r[2];
-                const uint64_t id = in[nslot].pid;
-                nr3 = make_uint2((uint32_t)id, (uint32_t)(id >> 32));
-                has_next = true;
+                if (nslot < G.cap_c + G.cap_l) {   // always true; guards the loads
+                    const uint4 *r = reinterpret_cast<const uint4 *>(in + nslot);
+                    nr0 = r[0];
+                    nr1 = r[1];
+                    nr2 = r[2];
+                    const uint64_t id = in[nslot].pid;
+                    nr3 = make_uint2((uint32_t)id, (uint32_t)(id >> 32));
+                    has_next = true;
+                }
                 nslot = kNone;
             }
             // lanes without a claimed slot claim the next ones of the job
@@ -1265,21 +1312,19 @@ k_transport_tile(Gen G, int g) {
                     uint32_t base = 0;
                     if (lane == leader) base = atomicAdd(&s_next, (uint32_t)nw);
                     base = __shfl(base, leader);
-                    if (base + nw >= cnt) {
-                        more = false;
-                        tail_nvis = nvis;
-                    }
+                    if (base + nw >= cnt) more = false;
                     if (nslot == kNone) {
                         const uint32_t my = base + __popcll(want & lt_mask);
-                        if (my < cnt) {
-                            const uint32_t sl = G.sidx[first + my];
-                            nslot = sl < G.cap_c + G.cap_l ? sl : kNone;   // always true; guards the load below
-                        }
+                        if (my < cnt) nslot = G.sidx[first + my];
                     }
                 }
             }
             if (!__ballot(p.alive)) {
                 if (!more && !__ballot(has_next || nslot != kNone)) break;
+            }
+            if (!quiet && __hip_atomic_load(&s_left, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) <= quiet_at) {
+                quiet = true;
+                tail_nvis = nvis;
             }
             // every lane steps (no branch); a free lane's result is discarded
             float T = 0.f, dw = 0.f;
@@ -1321,10 +1366,7 @@ k_transport_tile(Gen G, int g) {
                     const int oz = p.iz < tz0 ? -1 : (p.iz >= tz0 + G.th ? 1 : 0);
                     const bool out = (ox | oz) != 0;
                     dest = (uint32_t)((int)tile + __mul24(oz, ntx) + ox);   // a crossing moves one pixel: a neighbour tile
-                    // once the job has no packets left to hand out, a packet pauses
-                    // after tail_visits more visits so the workgroup is not held by
-                    // its longest stay (it resumes next generation)
-                    leave = out || nvis >= (more ? G.max_visits : min(G.max_visits, tail_nvis + G.tail_visits));
+                    leave = out || nvis >= (quiet ? min(G.max_visits, tail_nvis + G.tail_visits) : G.max_visits);
                 }
             }
             keep = flush ? 0.f : 1.f;
@@ -1333,6 +1375,8 @@ k_transport_tile(Gen G, int g) {
                 p.alive = false;
                 nvis = 0;
             }
+            const unsigned long long ended = __ballot(live && !p.alive);   // stays that ended here
+            if (ended && lane == 0) atomicSub(&s_left, (uint32_t)__popcll(ended));
         }
         // no slot can exceed the sum of the magnitudes flushed into the tile;
         // a job that could have wrapped the 64-bit sums is counted and its
@@ -1343,11 +1387,14 @@ k_transport_tile(Gen G, int g) {
         if (lane == 0) atomicAdd(&s_mag, wm);
         __syncthreads();
         if (threadIdx.x == 0 && !(s_mag < 0x1p62f)) atomicAdd(pd.ledc + 4, 1ull);
+        // fx_inv is read once: the atomics may alias pd for all the compiler
+        // knows, and a reload per add would make each add wait for the one before
+        const double fx_inv = pd.fx_inv;
         for (int i = threadIdx.x; i < ntp * K; i += blockDim.x) {
             const int lp = i / K, c = i - lp * K;
-            const double v = (double)fixed_value(fxt[i], sadds[lp]) * pd.fx_inv;
+            const double v = (double)fixed_value(fxt[i], sadds[lp]) * fx_inv;
             const int gx = tx0 + lp % G.tw, gz = tz0 + lp / G.tw;
-            if (v != 0.0 && gx < H.nx && gz < H.nz) unsafeAtomicAdd(t64 + (size_t)(gz * H.nx + gx) * K + c, v);
+            if (v != 0.0 && gx < H.nx && gz < H.nz) tally_add(t64 + (size_t)(gz * H.nx + gx) * K + c, v);
         }
         __syncthreads();
     }
@@ -1369,9 +1416,11 @@ constexpr int kBlockFinish = 256;
 
 // Adds a wave's staged visit sums (n visits of K values) to the HBM tallies:
 // consecutive lanes take consecutive values, so each pixel's K channels go
-// out as one contiguous run of atomics.
-__device__ __forceinline__ void finish_flush_stage(const Gen &G, const float *stage, const int *stage_pix,
-                                                   const int *stage_prob, int n, int K) {
+// out as one contiguous run of atomics.  A staged visit carries the address
+// of its pixel's K sums and its problem's inverse scale, so the loop reads
+// only LDS and its atomics go out back to back.
+__device__ __forceinline__ void finish_flush_stage(const float *stage, const unsigned long long *stage_dst,
+                                                   const double *stage_scale, int n, int K) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -1379,10 +1428,9 @@ __device__ __forceinline__ void finish_flush_stage(const Gen &G, const float *st
     for (int e = __lane_id(); e < total; e += 64) {
         const int v = e / K;
         const float val = stage[e];
-        if (val != 0.f) {
-            const ProbDev &S = G.probs[stage_prob[v]];
-            unsafeAtomicAdd(S.t64 + (size_t)stage_pix[v] * K + (e - v * K), __builtin_rint((double)val) * S.fx_inv);
-        }
+        if (val != 0.f)
+            tally_add(reinterpret_cast<double *>(stage_dst[v]) + (e - v * K),
+                      __builtin_rint((double)val) * stage_scale[v]);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -1440,8 +1488,11 @@ __global__ void __launch_bounds__(kBlockFinish) k_finish(Gen G, int g_last, int 
     const int lane = __lane_id();
     const int wave = threadIdx.x >> 6;
     float *stage = stage_all + wave * 64 * K;
-    int *stage_pix = reinterpret_cast<int *>(stage_all + (kBlockFinish / 64) * 64 * K) + wave * 64;
-    int *stage_prob = stage_pix + (kBlockFinish / 64) * 64;
+    // after the K-vectors (kBlockFinish * K floats, a multiple of 8 bytes):
+    // [wave][64] addresses of the visits' sums, then [wave][64] inverse scales
+    unsigned long long *dst_all = reinterpret_cast<unsigned long long *>(stage_all + kBlockFinish * K);
+    unsigned long long *stage_dst = dst_all + wave * 64;
+    double *stage_scale = reinterpret_cast<double *>(dst_all + kBlockFinish) + wave * 64;
     const unsigned long long lt_mask = (1ull << lane) - 1ull;
     // the work: records of a pool (prob_only < 0) or the unlaunched packets of one problem
     uint32_t pool = 0, nc = 0, nl = 0;
@@ -1467,9 +1518,12 @@ __global__ void __launch_bounds__(kBlockFinish) k_finish(Gen G, int g_last, int 
     int lprob = -1;   // problem of the ledger L
     Packet p;
     idle_packet(p, 0, 0);
-    int prob = -1;    // problem of the lane's packet
     Hot H{};
-    const float4 *med = nullptr;
+    // a lane's problem: medium (valid from the start, so that an idle lane's
+    // prefetch below reads a real pixel), tally, scales
+    const float4 *med = G.probs[prob_only < 0 ? 0 : prob_only].med;
+    double *t64 = nullptr;
+    double fx_inv = 0.0;
     float fx = 0.f, flush_at = 0.f;
     float4 mm = make_float4(0.f, 0.f, 0.f, 0.f);   // medium of the packet's pixel
     float acc[K], keep = 1.f;   // keep = 0 after a flush: the next deposit restarts the sums
@@ -1518,12 +1572,13 @@ __global__ void __launch_bounds__(kBlockFinish) k_finish(Gen G, int g_last, int 
                         if (prob_only >= 0) launch_state(S, S.pid0 + pid_first + my, q, L);
                         if (q.alive) {
                             p = q;
-                            prob = np_;
                             H = hot_of(S);
                             med = S.med;
+                            t64 = S.t64;
+                            fx_inv = S.fx_inv;
                             fx = S.fx;
                             flush_at = S.flush_at;
-                            mm = med[p.iz * H.nx + p.ix];   // a queued or launched packet is inside the grid
+                            mm = load_medium(med, p.iz * H.nx + p.ix);   // a queued or launched packet is inside the grid
                         }
                     }
                 }
@@ -1536,18 +1591,14 @@ __global__ void __launch_bounds__(kBlockFinish) k_finish(Gen G, int g_last, int 
         float T = 0.f;
         bool vend = false;
         if (p.alive) {
-            const float g = mm.w;   // read before mm is reloaded: the scatter need not wait for that load
             float dw = 0.f;
             pix = p.iz * H.nx + p.ix;
             ev = step(H, p, mm, T, dw);
             L.absorbed += (double)dw;
             L.segments += 1;
-            // the medium of the pixel the next step starts in (a crossing's new
-            // pixel, else the same one)
-            if (ev == EV_CROSS) mm = med[p.iz * H.nx + p.ix];
             deposit_harmonics<NH>(T * fx, p.sx, p.sz, keep, acc);   // direction of the segment, before any scatter
             if (ev == EV_SCATTER) {
-                if (!scatter_dir(H, p, g, L)) vend = true;   // killed by roulette: the visit ends
+                if (!scatter_dir(H, p, mm.w, L)) vend = true;   // killed by roulette: the visit ends
             } else {
                 vend = true;
                 if (ev == EV_ESCAPE) {
@@ -1556,13 +1607,17 @@ __global__ void __launch_bounds__(kBlockFinish) k_finish(Gen G, int g_last, int 
                 }
             }
         }
+        // the medium of the pixel the next step starts in (a crossing's new
+        // pixel, else the same one; pixel 0 for a lane without a packet),
+        // loaded outside any branch so that nothing waits for it before that step
+        mm = load_medium(med, p.alive ? p.iz * H.nx + p.ix : 0);
         const bool flush = vend || (ev != EV_NONE && fabsf(acc[0]) > flush_at);
         L.visits += vend ? 1u : 0u;
         const unsigned long long fm = __ballot(flush);
         if (fm) {
             const int nf = __popcll(fm);
             if (used + nf > 64) {   // no room: the staged visits go to the tally first
-                finish_flush_stage(G, stage, stage_pix, stage_prob, used, K);
+                finish_flush_stage(stage, stage_dst, stage_scale, used, K);
                 used = 0;
             }
             if (flush) {
@@ -1570,14 +1625,14 @@ __global__ void __launch_bounds__(kBlockFinish) k_finish(Gen G, int g_last, int 
                 float *st = stage + slot * K;
 #pragma unroll
                 for (int j = 0; j < K; ++j) st[j] = acc[j];
-                stage_pix[slot] = pix;
-                stage_prob[slot] = prob;
+                stage_dst[slot] = reinterpret_cast<unsigned long long>(t64 + (size_t)pix * K);
+                stage_scale[slot] = fx_inv;
             }
             used += nf;
         }
         if (ev != EV_NONE) keep = flush ? 0.f : 1.f;
     }
-    if (used) finish_flush_stage(G, stage, stage_pix, stage_prob, used, K);
+    if (used) finish_flush_stage(stage, stage_dst, stage_scale, used, K);
     ledger_flush_lanes(G, lprob, L);
 }
 
@@ -1967,24 +2022,28 @@ size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
 // Defaults of the tiled transport.  Live packets per generation: on the
 // 1e8-packet disc256 gradient 2^25 against 2^24: -1.8% time, 2^26 against
-// 2^25: -1.1%; small runs unchanged once the finisher threshold is kept at
-// 2^17.
+// 2^25: -1.1%.  The finisher threshold, the quiet rule, its tail and the
+// smallest job were set together on the 2.83e6-packet disc256 gradient
+// (2^16 / 50% / 4 / 512: 206 ms against 234 ms for 2^17 / 100% / 8 / no
+// split), which also shortens the 1e8-packet one by 3%.
 constexpr uint64_t kLiveMax = 1ull << 26;
-constexpr uint64_t kFinishMax = 1ull << 17;   // default finisher threshold: min(this, live / 128)
+constexpr uint64_t kFinishMax = 1ull << 16;   // default finisher threshold: min(this, live / 128)
 constexpr uint64_t kGridMaxPackets = 1ull << 21;   // larger runs take the tiled transport
 constexpr uint32_t kJobSize = 4096;           // packets per job
 constexpr uint64_t kSmallPool = 1ull << 23;   // pools below this many live packets use half-size jobs
 constexpr uint32_t kMaxVisitsPerStay = 64;    // a packet pauses after this many visits in one job
-// once a job has handed out its last packet, its packets pause after this many
-// more visits, so a wave does not idle behind its longest stay (measured on
-// the 256x256 disc: 8 beats 2, 4, 16 and no limit by 7-9%)
-constexpr uint32_t kTailVisits = 8;
+// once a job has turned quiet, its packets pause after this many more visits,
+// so a wave does not idle behind its longest stay
+constexpr uint32_t kTailVisits = 4;
 // generations enqueued per call unless the caller says: a base for the drain
 // of the longest histories plus a share per pool turnover (measured on the
 // disc256 workload: ~210 generations for 2.8e6 packets, ~390 for 1e8 at 2^26
 // live packets, ~720 for 1e9)
 constexpr uint32_t kGenBase = 448, kGenPerPool = 48;
 constexpr int kTileWavesMax = 256 * 16;       // bound on resident waves of the tiled kernel
+constexpr int kTileSlotsMax = kTileWavesMax / (kBlockTile / 64);   // and on its workgroups
+constexpr uint32_t kJobMin = 512;              // smallest job of a generation with few packets (see gen_scan)
+constexpr uint32_t kQuietPercent = 50;         // see the quiet rule of k_transport_tile
 
 // The tuning a call runs with: the caller's fields, defaults where zero.
 struct TileTuning {
@@ -1995,6 +2054,8 @@ struct TileTuning {
     uint64_t grid_max = kGridMaxPackets;
     double flush_track = kFlushTrackMax;
     uint32_t max_gen = 0;      // 0: kGenBase + kGenPerPool per pool of live packets the run holds
+    uint32_t job_min = kJobMin;
+    uint32_t quiet = kQuietPercent;
     uint32_t slice = kSlice;   // not a caller knob: the no-alloc entry point narrows it to save scratch
 };
 
@@ -2006,6 +2067,9 @@ bool tuning_from(const mc_options *o, TileTuning &v) {
     if (t.job_packets && (t.job_packets < 64 || t.job_packets > (1u << 20))) return false;
     if (t.tile > 256 || t.finish_packets > kLiveMax || t.tail_visits > (1u << 30) || t.max_generations > 65536)
         return false;
+    if ((t.min_job_packets && (t.min_job_packets < 64 || t.min_job_packets > (1u << 20))) || t.quiet_percent > 100 ||
+        t.reserved)
+        return false;
     if (!(t.flush_track >= 0.f && t.flush_track <= (float)kFlushTrackMax)) return false;
     if (t.live_packets) v.live = t.live_packets;
     if (t.job_packets) v.job = t.job_packets;
@@ -2016,6 +2080,8 @@ bool tuning_from(const mc_options *o, TileTuning &v) {
     if (t.flush_track > 0.f) v.flush_track = (double)t.flush_track;
     if (t.tail_visits) v.tailvis = t.tail_visits;
     if (t.max_generations) v.max_gen = t.max_generations;
+    if (t.min_job_packets) v.job_min = t.min_job_packets;
+    if (t.quiet_percent) v.quiet = t.quiet_percent;
     return true;
 }
 
@@ -2163,7 +2229,9 @@ BatchLayout batch_layout(const BatchProblem *pb, int n, const TileTuning &tt) {
     // size to fill the device: half-size jobs (measured on 1e6- and 4e6-packet
     // disc256 gradients: -7%; 4096 stays better for full pools)
     B.job = (B.live < kSmallPool && B.tt.job >= 128) ? B.tt.job / 2 : B.tt.job;
-    B.max_jobs = (uint64_t)B.ntiles + B.live / B.job + 2;
+    // jobs of one generation: one per tile plus one per job_size records, or
+    // (when job sizes shrink to fill the workgroups) at most two per workgroup
+    B.max_jobs = (uint64_t)B.ntiles + std::max<uint64_t>(B.live / B.job, 2ull * kTileSlotsMax) + 2;
     if (!B.tt.max_gen)
         B.tt.max_gen = (uint32_t)std::min<uint64_t>(65536, kGenBase + kGenPerPool * ((B.total_packets + B.live - 1) / B.live));
     B.probs = off;
@@ -2424,6 +2492,8 @@ mc_status run_batch(const BatchProblem *pb, int n, const TileTuning &tt, mc_time
     G.cap_c = (uint32_t)B.cap_c;
     G.cap_l = (uint32_t)B.cap_l;
     G.job_size = B.job;
+    G.job_min = std::min(B.tt.job_min, B.job);
+    G.quiet_pct = B.tt.quiet;
     G.max_visits = B.tt.maxvis;
     G.tail_visits = B.tt.tailvis;
     G.finish_at = (uint32_t)(B.tt.finish ? B.tt.finish : std::min<uint64_t>(kFinishMax, B.tt.live / 128));
@@ -2448,7 +2518,8 @@ mc_status run_batch(const BatchProblem *pb, int n, const TileTuning &tt, mc_time
     if ((st = set_lds_limit(reinterpret_cast<const void *>(fn), B.tile_lds)) != MC_OK) return st;
     const int occ = occupancy_blocks(reinterpret_cast<const void *>(fn), kBlockTile, B.tile_lds);
     const int cus = device_cus();
-    const unsigned tgrid = (unsigned)std::max(1, std::min(cus * occ, kTileWavesMax / (kBlockTile / 64)));
+    const unsigned tgrid = (unsigned)std::max(1, std::min(cus * occ, kTileSlotsMax));
+    G.slots = tgrid;
     const unsigned cgrid = (unsigned)std::max(1, cus);
     const unsigned sgrid = (unsigned)std::max(1, 4 * cus);
     for (uint32_t g = 0; g < B.tt.max_gen; ++g) {
@@ -2462,8 +2533,8 @@ mc_status run_batch(const BatchProblem *pb, int n, const TileTuning &tt, mc_time
     }
     // the finisher: the records left, then any packets the generations did not launch
     const FinishFn ff = kernels().fin[N];
-    const size_t flds = (size_t)(kBlockFinish / 64) * 64 * (2 * N + 1) * sizeof(float) +
-                        2 * (kBlockFinish / 64) * 64 * sizeof(int);
+    const size_t flds = (size_t)kBlockFinish * (2 * N + 1) * sizeof(float) +
+                        (size_t)kBlockFinish * (sizeof(unsigned long long) + sizeof(double));
     if ((st = set_lds_limit(reinterpret_cast<const void *>(ff), flds)) != MC_OK) return st;
     const int focc = occupancy_blocks(reinterpret_cast<const void *>(ff), kBlockFinish, flds);
     const unsigned fgrid = (unsigned)std::max<uint64_t>(
@@ -2877,6 +2948,8 @@ mc_status mc_default_tuning(mc_tuning *t) {
     t->flush_track = (float)v.flush_track;
     t->tail_visits = v.tailvis;
     t->max_generations = 0;   // chosen per run from its packet count and pool
+    t->min_job_packets = v.job_min;
+    t->quiet_percent = v.quiet;
     return MC_OK;
 }
 

@@ -123,7 +123,8 @@ def ledger_dict(buf: torch.Tensor) -> dict:
 
 
 _TUNING_FIELDS = ("live_packets", "job_packets", "max_visits", "tile", "finish_packets", "grid_max_packets",
-                  "flush_track", "tail_visits", "max_generations")
+                  "flush_track", "tail_visits", "max_generations", "min_job_packets",
+                  "quiet_percent")
 
 
 def default_tuning() -> dict:

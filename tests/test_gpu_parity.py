@@ -497,8 +497,9 @@ def test_anisotropic_point_source_sin2_2theta(tiled):
 
 
 def test_tuning_changes_schedule_not_results():
-    """Other tile sides, generation sizes, job sizes, pause lengths and
-    generation budgets move the same packets in another order, and the maps
+    """Other tile sides, generation sizes, job sizes (fixed or cut to fill the
+    workgroups), pause rules and generation budgets move the same packets in
+    another order, and the maps
     are bitwise equal: every visit adds the same multiple of 2^(e-32), and
     FP64 sums such values exactly while a pixel's total stays below 2^(21+e)
     (here far below), so the order of the additions no longer matters.  A
@@ -516,7 +517,8 @@ def test_tuning_changes_schedule_not_results():
     for t in ({"tile": 7}, {"live_packets": 4096, "job_packets": 256, "max_visits": 3},
               {"live_packets": 1 << 17, "finish_packets": 50_000}, {"tail_visits": 1 << 30},
               {"tail_visits": 1}, {"live_packets": 4096, "max_generations": 2},
-              {"max_generations": 1}, {"max_generations": 3, "finish_packets": 1024}):
+              {"max_generations": 1}, {"max_generations": 3, "finish_packets": 1024},
+              {"min_job_packets": 64, "quiet_percent": 1}, {"min_job_packets": 4096, "quiet_percent": 100}):
         got, lgot = _gpu_run(rmc, ph, specs, n, 16, seed=31, tuning=t)
         assert np.array_equal(got, ref), (t, np.abs(got - ref).max())
         for k in ("packets", "visits", "scatters", "segments"):

@@ -41,7 +41,7 @@ def test_struct_layouts():
     L, _ = _lib()
     assert C.sizeof(L.mc_event) == 48
     assert C.sizeof(L.mc_ledger) == 88
-    assert C.sizeof(L.mc_tuning) == 48 and C.sizeof(L.mc_options) == 16
+    assert C.sizeof(L.mc_tuning) == 56 and C.sizeof(L.mc_options) == 16
     assert C.sizeof(L.mc_run) == 48
     assert C.sizeof(L.mc_medium) == 40
 
@@ -128,8 +128,8 @@ def test_tuning_is_per_call_and_checked():
     from paper_1608_05238_amd import rmc
     d = rmc.default_tuning()
     assert d == {"live_packets": 1 << 26, "job_packets": 4096, "max_visits": 64, "tile": 0,
-                 "finish_packets": 1 << 17, "grid_max_packets": 1 << 21, "flush_track": 65536.0,
-                 "tail_visits": 8, "max_generations": 0}
+                 "finish_packets": 1 << 16, "grid_max_packets": 1 << 21, "flush_track": 65536.0,
+                 "tail_visits": 4, "max_generations": 0, "min_job_packets": 512, "quiet_percent": 50}
     m = _medium(L)
     m.nx = m.nz = 256
     src = (L.mc_source * 1)(_pencil(L))
@@ -146,7 +146,7 @@ def test_tuning_is_per_call_and_checked():
     assert ws({"live_packets": 1 << 20}) == small
     for bad in ({"live_packets": 10}, {"job_packets": 1}, {"tile": 1000}, {"flush_track": 1e6},
                 {"flush_track": -1.0}, {"flush_track": float("nan")}, {"tail_visits": (1 << 30) + 1},
-                {"max_generations": 70000}):
+                {"max_generations": 70000}, {"min_job_packets": 10}, {"quiet_percent": 101}):
         assert ws(bad) == 0, bad
         rc = lib.mc_forward(C.byref(m), src, 1, C.byref(run), rmc._Options(bad, None).ref(), 0x2000, None, 0x3000,
                             1 << 40, None)
