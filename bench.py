@@ -55,12 +55,12 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
 # reads for a plain 1 GiB device copy.  Valid only for the kernel source it
 # was measured on: reported as null once that source changes.
 TRAFFIC = {
-    "source_sha256": "acb2c6d744c7990c7892e442ad93cc19e8cc09672bd7207f78f9c803cf6eaf7c",
-    "fetch_kib_per_launch": 272942.70, "fetch_factor": 2.000,
-    "write_kib_per_launch": 835908.56, "write_factor": 1.000,
+    "source_sha256": "6954498b660da4c8fd10b08cf8fb0bc62180db227f6defc138bcf357212f2648",
+    "fetch_kib_per_launch": 342964.0, "fetch_factor": 2.000,
+    "write_kib_per_launch": 546638.3, "write_factor": 1.000,
     # VALU wave-instructions per pixel visit (rocprofv3 SQ_INSTS_VALU over the
     # k_transport_tile<16> and k_finish<16> dispatches of one benchmark step)
-    "valu_per_visit": 13.023,
+    "valu_per_visit": 13.891,
 }
 
 # Algorithmic arithmetic of the method, in lane-operations (one FMA, compare,

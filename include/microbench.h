@@ -60,6 +60,15 @@ mc_status mb_lds_atomics(int kind, uint32_t lds_bytes, uint32_t block, uint32_t 
 mc_status mb_global_atomics_f64(double *buf_d, uint64_t n_elem, uint32_t n_blocks, uint32_t iters, uint32_t seed,
                                 void *stream);
 
+/* FP64 atomic adds of 1.0 (global_atomic_add_f64, no return) to buf_d
+ * [n_rows][row_len] in the pattern of the tail finisher's flush: the lanes of
+ * a wave take consecutive elements of rows drawn at random, so one wave
+ * instruction covers 64 / row_len rows.  n_blocks workgroups of 256 threads,
+ * `iters` adds per thread; 1 <= row_len <= 4096, n_rows * row_len < 2^32.
+ * buf_d is accumulated into, not cleared. */
+mc_status mb_global_atomics_rows_f64(double *buf_d, uint32_t n_rows, uint32_t row_len, uint32_t n_blocks,
+                                     uint32_t iters, uint32_t seed, void *stream);
+
 /* Device copy dst_d[i] = src_d[i] of n16 16-byte elements (both 16-byte
  * aligned, not overlapping): bytes moved through HBM = 32 * n16. */
 mc_status mb_copy(const void *src_d, void *dst_d, uint64_t n16, void *stream);

@@ -24,7 +24,7 @@ SYMBOLS = ("mc_workspace_bytes", "mc_forward", "mc_adjoint", "mc_residual", "mc_
            "mc_run_noalloc",
            "mc_binned_workspace_bytes", "mc_run_binned",
            "mc_status_string", "mc_build_info", "dn_conv3x3_fwd", "dn_conv3x3_wgrad",
-           "mb_lds_atomics", "mb_global_atomics_f64", "mb_copy", "mb_fma_f32", "mb_wall_clock_khz")
+           "mb_lds_atomics", "mb_global_atomics_f64", "mb_global_atomics_rows_f64", "mb_copy", "mb_fma_f32", "mb_wall_clock_khz")
 (MB_LDS_ADD_F64, MB_LDS_ADD_F32, MB_LDS_ADD_U64, MB_LDS_ADD_U32, MB_LDS_ADD_F64_ROW33, MB_LDS_ADD_U64_ROW33,
  MB_LDS_ADD_U64_PRE) = range(7)
 
@@ -138,6 +138,8 @@ def load() -> C.CDLL:
     lib.mb_lds_atomics.restype = St
     lib.mb_global_atomics_f64.argtypes = [V, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, V]
     lib.mb_global_atomics_f64.restype = St
+    lib.mb_global_atomics_rows_f64.argtypes = [V, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, V]
+    lib.mb_global_atomics_rows_f64.restype = St
     lib.mb_copy.argtypes = [V, V, C.c_uint64, V]
     lib.mb_copy.restype = St
     lib.mb_fma_f32.argtypes = [V, C.c_uint32, C.c_uint32, V, V]

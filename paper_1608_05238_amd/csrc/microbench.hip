@@ -102,6 +102,23 @@ __global__ void __launch_bounds__(256) k_global_atomics_f64(double *buf, uint32_
     }
 }
 
+// The finisher's pattern: each wave adds to runs of row_len consecutive
+// doubles (one pixel's K sums) of random rows, consecutive lanes on
+// consecutive elements, so one wave instruction covers about two rows.
+__global__ void __launch_bounds__(256) k_global_atomics_rows_f64(double *buf, uint32_t n_rows, uint32_t row_len,
+                                                                 uint32_t iters, uint32_t seed) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t ws = mb_hash(wave ^ (seed * 0x9e3779b9u));
+    for (uint32_t it = 0; it < iters; ++it) {
+        const uint32_t e = lane + 64u * it;
+        const uint32_t v = e / row_len, c = e - v * row_len;
+        const uint32_t row = mb_pick(mb_hash(ws + v * 0x85ebca6bu), n_rows);
+        __hip_atomic_fetch_add((__attribute__((address_space(1))) double *)(buf + (size_t)row * row_len + c), 1.0,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // each workgroup copies one contiguous chunk of 4 x 256 16-byte elements:
@@ -185,6 +202,16 @@ mc_status mb_global_atomics_f64(double *buf_d, uint64_t n_elem, uint32_t n_block
     if (!buf_d || n_elem == 0 || n_elem >= (1ull << 32) || n_blocks == 0 || iters == 0) return MC_ERR_INVALID_ARG;
     hipLaunchKernelGGL(k_global_atomics_f64, dim3(n_blocks), dim3(256), 0, reinterpret_cast<hipStream_t>(stream), buf_d,
                        (uint32_t)n_elem, iters, seed);
+    return hipGetLastError() == hipSuccess ? MC_OK : MC_ERR_DEVICE;
+}
+
+mc_status mb_global_atomics_rows_f64(double *buf_d, uint32_t n_rows, uint32_t row_len, uint32_t n_blocks,
+                                     uint32_t iters, uint32_t seed, void *stream) {
+    if (!buf_d || n_rows == 0 || row_len == 0 || row_len > 4096 || (uint64_t)n_rows * row_len >= (1ull << 32) ||
+        n_blocks == 0 || iters == 0 || (uint64_t)iters * 64u >= (1ull << 32))
+        return MC_ERR_INVALID_ARG;
+    hipLaunchKernelGGL(k_global_atomics_rows_f64, dim3(n_blocks), dim3(256), 0, reinterpret_cast<hipStream_t>(stream),
+                       buf_d, n_rows, row_len, iters, seed);
     return hipGetLastError() == hipSuccess ? MC_OK : MC_ERR_DEVICE;
 }
 

@@ -78,6 +78,14 @@ def run_all(dev: int = 0) -> dict:
                                                                                      stream)))
         out["global_atomics"].append({"buffer": label, "atomics_per_s": nb * 256 * iters / t, "seconds": t})
         del buf
+    # the finisher's flush: runs of 33 consecutive doubles of random pixels of the 256x256 (N = 16) tally
+    buf = torch.zeros(65536 * 33, dtype=torch.float64, device=d)
+    nb, iters = ncu * 8, 33 * 16
+    t = _time(lambda: _check("mb_global_atomics_rows_f64", lib.mb_global_atomics_rows_f64(
+        buf.data_ptr(), 65536, 33, nb, iters, 5, stream)))
+    out["global_atomics_rows"] = {"buffer": "65536 px x 33 (17.3 MB), runs of 33", "atomics_per_s": nb * 256 * iters / t,
+                                  "seconds": t}
+    del buf
 
     # HBM: 1 GiB device copy
     n16 = 1 << 26
@@ -108,6 +116,8 @@ def table(r: dict) -> str:
                     f"{e['shader_mhz']:.0f} |")
     for e in r["global_atomics"]:
         rows.append(f"| global FP64 atomic, random, {e['buffer']} | {e['atomics_per_s']:.3e} /s | | |")
+    e = r["global_atomics_rows"]
+    rows.append(f"| global FP64 atomic, {e['buffer']} | {e['atomics_per_s']:.3e} /s | | |")
     rows.append(f"| HBM copy (1 GiB read + 1 GiB write) | {r['hbm_copy']['gb_per_s']:.0f} GB/s | | |")
     rows.append(f"| HBM copy, torch copy_ (same buffers) | {r['hbm_copy_runtime']['gb_per_s']:.0f} GB/s | | |")
     e = r["fma_f32"]

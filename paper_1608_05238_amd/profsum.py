@@ -4,13 +4,17 @@ measurements.
     python -m paper_1608_05238_amd.profsum stats <dir>      # --kernel-trace --stats -f csv
     python -m paper_1608_05238_amd.profsum counters <dir>   # --pmc ... -f csv
     python -m paper_1608_05238_amd.profsum tail <dir> <n> <kernel>[,<kernel>...]
+    python -m paper_1608_05238_amd.profsum counters-tail <dir> <n> <kernel>[,<kernel>...]
+    python -m paper_1608_05238_amd.profsum runs <dir>       # --kernel-trace, per Monte Carlo run
 
 `stats` prints the kernel summary table (calls, total, average); `counters`
 sums every counter per kernel over its dispatches and prints the per-dispatch
 average, so a counter of a plain copy of known size can calibrate the others;
 `tail` averages the durations of the last n dispatches of the named kernels
 (from the per-dispatch kernel trace), e.g. the launches of a benchmark's
-timed steps.  Only reads CSV files; no GPU work.
+timed steps; `counters-tail` sums each counter over the last n dispatches of
+the named kernels; `runs` cuts a kernel trace into Monte Carlo runs and sums
+each run's generation, tile and finisher kernels.  Only reads CSV files; no GPU work.
 """
 from __future__ import annotations
 
@@ -72,6 +76,81 @@ def counters(root: str) -> str:
     return "\n".join(out)
 
 
+def counters_tail(root: str, n: int, kernels: list) -> str:
+    """Each counter summed over the last n dispatches (by dispatch id) of the
+    named kernels, and its average per dispatch: the launches of a
+    benchmark's timed steps without its set-up runs."""
+    files = _find(root, "counter_collection.csv")
+    if not files:
+        raise SystemExit(f"no *counter_collection.csv under {root}")
+    vals = defaultdict(lambda: defaultdict(float))
+    names = {}
+    for f in files:
+        with open(f, newline="") as fh:
+            for r in csv.DictReader(fh):
+                k = _short(r["Kernel_Name"])
+                if k in kernels:
+                    d = (int(r["Dispatch_Id"]), r.get("Agent_Id", ""))
+                    vals[d][r["Counter_Name"]] += float(r["Counter_Value"])
+                    names[d] = k
+    last = sorted(vals)[-n:]
+    if not last:
+        raise SystemExit(f"no dispatch of {kernels} under {root}")
+    per = defaultdict(int)
+    for d in last:
+        per[names[d]] += 1
+    tot = defaultdict(float)
+    for d in last:
+        for c, v in vals[d].items():
+            tot[c] += v
+    kinds = ", ".join(f"{k}: {m}" for k, m in sorted(per.items()))
+    out = [f"last {len(last)} dispatches ({kinds})", "| counter | sum | per dispatch |", "|---|---|---|"]
+    for c, v in sorted(tot.items()):
+        out.append(f"| {c} | {v:.6e} | {v / len(last):.6e} |")
+    return "\n".join(out)
+
+
+def runs(root: str, first_kernel: str = "k_ctl_init") -> str:
+    """The kernel trace cut into Monte Carlo runs (a run starts at each
+    dispatch of first_kernel): per run its span from that dispatch to the end
+    of its last transport dispatch, the summed durations of the generation
+    kernels, of the tile kernel and of the finisher, and how many tile
+    launches found work (longer than 6 us)."""
+    files = _find(root, "kernel_trace.csv")
+    if not files:
+        raise SystemExit(f"no *kernel_trace.csv under {root}")
+    rows = []
+    for f in files:
+        with open(f, newline="") as fh:
+            for r in csv.DictReader(fh):
+                rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), _short(r["Kernel_Name"])))
+    rows.sort()
+    out = ["| run | span ms | tile ms | busy / tile launches | generation kernels ms | finisher ms |",
+           "|---|---|---|---|---|---|"]
+    cur, k = None, 0
+    def emit(run, k):
+        tr = [x for x in run if x[2].startswith(("k_transport_tile", "k_finish", "k_gen_"))]
+        if not tr:
+            return
+        span = (tr[-1][1] - run[0][0]) / 1e6
+        tile = [(e - b) / 1e3 for b, e, n in run if n.startswith("k_transport_tile")]
+        gen = sum((e - b) / 1e3 for b, e, n in run if n.startswith("k_gen_"))
+        fin = sum((e - b) / 1e3 for b, e, n in run if n.startswith("k_finish"))
+        busy = sum(1 for t in tile if t > 6.0)
+        out.append(f"| {k} | {span:.1f} | {sum(tile) / 1e3:.1f} | {busy} / {len(tile)} | {gen / 1e3:.1f} | {fin / 1e3:.1f} |")
+    for row in rows:
+        if row[2] == first_kernel:
+            if cur:
+                emit(cur, k)
+                k += 1
+            cur = []
+        if cur is not None:
+            cur.append(row)
+    if cur:
+        emit(cur, k)
+    return "\n".join(out)
+
+
 def tail(root: str, n: int, kernels: list) -> str:
     files = _find(root, "kernel_trace.csv")
     if not files:
@@ -99,6 +178,12 @@ def tail(root: str, n: int, kernels: list) -> str:
 def main(argv) -> int:
     if len(argv) == 5 and argv[1] == "tail":
         print(tail(argv[2], int(argv[3]), argv[4].split(",")))
+        return 0
+    if len(argv) == 3 and argv[1] == "runs":
+        print(runs(argv[2]))
+        return 0
+    if len(argv) == 5 and argv[1] == "counters-tail":
+        print(counters_tail(argv[2], int(argv[3]), argv[4].split(",")))
         return 0
     if len(argv) != 3 or argv[1] not in ("stats", "counters"):
         print(__doc__, file=sys.stderr)

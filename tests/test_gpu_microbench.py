@@ -28,6 +28,10 @@ def test_microbenchmarks_count_their_operations():
     assert lib.mb_global_atomics_f64(buf.data_ptr(), n, 16, 10, 1, s) == 0
     torch.cuda.synchronize()
     assert float(buf.sum()) == 16 * 256 * 10
+    rows = torch.zeros(500 * 33, dtype=torch.float64, device=d)
+    assert lib.mb_global_atomics_rows_f64(rows.data_ptr(), 500, 33, 16, 40, 2, s) == 0
+    torch.cuda.synchronize()
+    assert float(rows.sum()) == 16 * 256 * 40 and float(rows.min()) >= 0
     a = torch.arange(4 * 3000, dtype=torch.float32, device=d)
     b = torch.zeros_like(a)
     assert lib.mb_copy(a.data_ptr(), b.data_ptr(), 3000, s) == 0

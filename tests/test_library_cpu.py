@@ -213,6 +213,8 @@ def test_microbenchmark_arguments_checked_on_host():
     assert lib.mb_lds_atomics(L.MB_LDS_ADD_F64, 65536, 512, 8, 4, 0, None, None, None) == bad
     assert lib.mb_global_atomics_f64(sink, 0, 8, 4, 0, None) == bad
     assert lib.mb_global_atomics_f64(sink, 1 << 32, 8, 4, 0, None) == bad
+    for args in ((0, 33, 8, 4), (10, 0, 8, 4), (10, 5000, 8, 4), (1 << 28, 33, 8, 4), (10, 33, 0, 4), (10, 33, 8, 0)):
+        assert lib.mb_global_atomics_rows_f64(sink, *args, 0, None) == bad, args
     assert lib.mb_copy(0x1000, 0x1008, 4, None) == bad          # misaligned destination
     assert lib.mb_copy(0x1000, 0x1010, 4, None) == bad          # overlapping
     assert lib.mb_copy(None, 0x100000, 4, None) == bad
