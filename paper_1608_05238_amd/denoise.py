@@ -35,40 +35,61 @@ def _stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+def _pad8(n: int) -> int:
+    return (n + 7) // 8 * 8
+
+
+def _nhwc_bf16(t: torch.Tensor, c_pad: int) -> torch.Tensor:
+    """[n][c][h][w] as BF16 in channels-last storage ([n][h][w][c] in memory),
+    zero channels appended up to c_pad."""
+    t = t.detach().to(torch.bfloat16)
+    if c_pad > t.shape[1]:
+        t = F.pad(t, (0, 0, 0, 0, 0, c_pad - t.shape[1]))
+    return t.contiguous(memory_format=torch.channels_last)
+
+
 class _Conv3x3(torch.autograd.Function):
-    """3x3 convolution, stride 1, padding 1, with BF16 operands on the MFMA units."""
+    """3x3 convolution, stride 1, padding 1, with BF16 operands on the MFMA
+    units.  The kernels take channels-last data with a multiple of 8 channels:
+    the operands are converted here (channels padded with zeros); outputs are
+    channels-last FP32 tensors."""
 
     @staticmethod
     def forward(ctx, x, w, b):
         lib = L.load()
         n, ci, h, wd = x.shape
         co = w.shape[0]
-        xb = x.detach().to(torch.bfloat16).contiguous()
-        wb = w.detach().to(torch.bfloat16).contiguous()
-        y = torch.empty((n, co, h, wd), dtype=torch.float32, device=x.device)
+        cip = _pad8(ci)
+        xb = _nhwc_bf16(x, cip)
+        wb = F.pad(w.detach().to(torch.bfloat16), (0, 0, 0, 0, 0, cip - ci)).permute(0, 2, 3, 1).contiguous()
+        y = torch.empty((n, co, h, wd), dtype=torch.float32, device=x.device, memory_format=torch.channels_last)
         bias = b.detach().float().contiguous()
         L.check("dn_conv3x3_fwd", lib.dn_conv3x3_fwd(xb.data_ptr(), wb.data_ptr(), bias.data_ptr(), y.data_ptr(),
-                                                     n, ci, co, h, wd, _stream()))
-        ctx.save_for_backward(xb, wb)
+                                                     n, cip, co, h, wd, _stream()))
+        ctx.save_for_backward(xb, w.detach())
         ctx.shape = (n, ci, co, h, wd)
         return y
 
     @staticmethod
     def backward(ctx, gy):
         lib = L.load()
-        xb, wb = ctx.saved_tensors
+        xb, w = ctx.saved_tensors
         n, ci, co, h, wd = ctx.shape
-        gyb = gy.to(torch.bfloat16).contiguous()
+        cip, cop = _pad8(ci), _pad8(co)
+        gyb = _nhwc_bf16(gy, cop)
         gx = gw = gb = None
         if ctx.needs_input_grad[0]:
-            wt = wb.flip(2, 3).transpose(0, 1).contiguous()   # [ci][co][3][3], flipped
-            gx = torch.empty((n, ci, h, wd), dtype=torch.float32, device=gy.device)
+            # the input gradient: the same convolution with the weights flipped
+            # and input / output channels swapped, [ci][3][3][co]
+            wt = F.pad(w.to(torch.bfloat16).flip(2, 3).permute(1, 2, 3, 0), (0, cop - co)).contiguous()
+            gx = torch.empty((n, ci, h, wd), dtype=torch.float32, device=gy.device, memory_format=torch.channels_last)
             L.check("dn_conv3x3_fwd", lib.dn_conv3x3_fwd(gyb.data_ptr(), wt.data_ptr(), None, gx.data_ptr(),
-                                                         n, co, ci, h, wd, _stream()))
+                                                         n, cop, ci, h, wd, _stream()))
         if ctx.needs_input_grad[1]:
-            gw = torch.empty((co, ci, 3, 3), dtype=torch.float32, device=gy.device)
-            L.check("dn_conv3x3_wgrad", lib.dn_conv3x3_wgrad(xb.data_ptr(), gyb.data_ptr(), gw.data_ptr(),
-                                                             n, ci, co, h, wd, _stream()))
+            g = torch.empty((cop, 3, 3, cip), dtype=torch.float32, device=gy.device)
+            L.check("dn_conv3x3_wgrad", lib.dn_conv3x3_wgrad(xb.data_ptr(), gyb.data_ptr(), g.data_ptr(),
+                                                             n, cip, cop, h, wd, _stream()))
+            gw = g[:co, :, :, :ci].permute(0, 3, 1, 2).contiguous()
         if ctx.needs_input_grad[2]:
             gb = gy.sum(dim=(0, 2, 3))
         return gx, gw, gb

@@ -1,7 +1,9 @@
 """BF16 matrix-core convolution kernels of the denoiser against PyTorch's FP64
 convolution on the CPU, on the same BF16-rounded operands (the products are
-exact in FP32; only the order of the FP32 sums differs), and a short
-training run of the U-Net built on them."""
+exact in FP32; only the order of the FP32 sums differs), over channel counts
+that need zero padding, several 32-channel chunks and 64-channel output
+tiles, and images that end inside an 8 x 8 tile; and a short training run of
+the U-Net built on them."""
 import numpy as np
 import pytest
 
@@ -15,7 +17,8 @@ def _mods():
     return torch, F, D
 
 
-@pytest.mark.parametrize("shape", [(2, 33, 48, 17, 17), (1, 5, 70, 8, 13), (3, 64, 64, 32, 32), (1, 1, 1, 1, 1)])
+@pytest.mark.parametrize("shape", [(2, 33, 48, 17, 17), (1, 5, 70, 8, 13), (3, 64, 64, 32, 32), (1, 1, 1, 1, 1),
+                                   (2, 160, 96, 19, 21), (1, 112, 48, 9, 64)])
 def test_conv3x3_forward_and_gradients(shape):
     torch, F, D = _mods()
     n, ci, co, h, w = shape

@@ -196,6 +196,12 @@ def test_denoiser_arguments_checked_on_host():
     assert lib.dn_conv3x3_fwd(None, 0x1000, None, 0x2000, 1, 1, 1, 4, 4, None) == L.MC_ERR_INVALID_ARG
     assert lib.dn_conv3x3_fwd(0x1000, 0x1000, None, 0x2000, 0, 1, 1, 4, 4, None) == L.MC_ERR_INVALID_ARG
     assert lib.dn_conv3x3_wgrad(0x1000, 0x1000, 0x2000, 1, 1, 1, 4, -1, None) == L.MC_ERR_INVALID_ARG
+    # channels-last operands: a multiple of 8 channels, 16-byte aligned rows
+    assert lib.dn_conv3x3_fwd(0x1000, 0x1000, None, 0x2000, 1, 12, 8, 4, 4, None) == L.MC_ERR_INVALID_ARG
+    assert lib.dn_conv3x3_fwd(0x1008, 0x1000, None, 0x2000, 1, 8, 8, 4, 4, None) == L.MC_ERR_INVALID_ARG
+    assert lib.dn_conv3x3_fwd(0x1000, 0x1000, None, 0x2004, 1, 8, 8, 4, 4, None) == L.MC_ERR_INVALID_ARG
+    assert lib.dn_conv3x3_wgrad(0x1000, 0x1000, 0x2000, 1, 8, 12, 4, 4, None) == L.MC_ERR_INVALID_ARG
+    assert lib.dn_conv3x3_wgrad(0x1000, 0x1008, 0x2000, 1, 8, 8, 4, 4, None) == L.MC_ERR_INVALID_ARG
 
 
 def test_microbenchmark_arguments_checked_on_host():
