@@ -59,3 +59,53 @@ def test_unet_training_reduces_loss():
     assert hist[-1] < 0.7 * hist[0], hist
     den = D.denoise(model, noisy[:16].cuda())
     assert D.rel_error(den.cpu(), clean[:16]) < D.rel_error(noisy[:16], clean[:16])
+
+
+def test_error_prediction_of_an_identity_network():
+    """With the output layer at zero the U-Net is the identity, so the denoised
+    maps are the packet-weighted mean of the two halves and their only error is
+    the halves' noise: the split-half prediction must match the actual a0
+    error (expected squared norms agree exactly; one sample fluctuates by
+    ~1/sqrt(pixels)).  Calibration then finds (almost) no systematic part."""
+    torch, F, D = _mods()
+    torch.manual_seed(3)
+    s, c, hw, sig = 24, 5, 32, 0.05
+    base = torch.randn(s, c, hw // 4, hw // 4)
+    clean = (F.interpolate(base, size=(hw, hw), mode="bilinear", align_corners=False).abs() + 1.0).cuda()
+    na, nb = 3000, 5000   # unequal halves: noise variance ~ 1/packets
+    ha = clean + sig * (8000 / na) ** 0.5 * torch.randn_like(clean)
+    hb = clean + sig * (8000 / nb) ** 0.5 * torch.randn_like(clean)
+    model = D.UNet(c, widths=(8, 8)).cuda()
+    den, p0, pall = D.predicted_error(model, ha, hb, na, nb)
+    mean = (ha * na + hb * nb) / (na + nb)
+    assert torch.allclose(den, mean, rtol=1e-5, atol=1e-6)
+    act0 = (den[:, 0] - clean[:, 0]).double().pow(2).sum((1, 2)).sqrt() / den[:, 0].double().pow(2).sum((1, 2)).sqrt()
+    ratio = (p0 / act0).cpu().numpy()
+    assert 0.93 < float(np.median(ratio)) < 1.07, ratio
+    assert ratio.min() > 0.7 and ratio.max() < 1.4, ratio
+    high = clean + 0.01 * sig * torch.randn_like(clean)
+    cal = D.calibrate(model, ha, hb, high, na + nb, 100 * (na + nb))
+    assert cal["bias2"][0] < (0.2 * float(act0.mean())) ** 2, cal
+
+
+def test_denoise_or_mc_decides_per_input():
+    """The per-input path: a threshold the prediction meets returns the
+    denoised mean of the two half-runs; one it cannot meet returns exactly the
+    plain run with the fallback packet count."""
+    torch, F, D = _mods()
+    from paper_1608_05238_amd import rmc
+    import phantoms as P
+    ph = P.disc_phantom(32, 0.5, 0.05, 5.0, 0.8, seed=4)
+    med = rmc.Medium.from_phantom(ph)
+    src = P.four_side_lines(ph)
+    nh = 2
+    model = D.UNet(2 * nh + 1, widths=(8, 8)).cuda()
+    cal = {"bias2": (0.0, 0.0)}
+    maps, kind, pred = D.denoise_or_mc(model, cal, med, src, 20_000, 50_000, nh, threshold=1.0, seed=9)
+    assert kind == "denoised" and 0 < pred < 1.0
+    a, b, na, nb = D.split_runs(med, src, 20_000, nh, seed=9)
+    assert torch.allclose(maps.float(), ((a * na + b * nb) / (na + nb)).float(), rtol=1e-5, atol=1e-7)
+    maps, kind, pred2 = D.denoise_or_mc(model, cal, med, src, 20_000, 50_000, nh, threshold=0.0, seed=9)
+    assert kind == "monte-carlo" and pred2 == pred
+    ref, _ = rmc.mc_forward(med, src, rmc.make_run(50_000, nh, seed=9), ledger=False)
+    assert torch.equal(maps, ref)
