@@ -318,12 +318,22 @@ def single_gradient(args) -> dict:
 
 
 def batch_workload(args) -> dict:
-    """64 problems in one packet pool: 16 sources x 4 wavelengths (mua scaled
-    0.5, 1, 2, 4), grids drawn from {128, 192, 256, 512}^2 over the same
-    25.6 mm square, packets per problem log-uniform in [args.batch_min,
-    args.batch_max], N = 16.  Timed as one mc_run_batch call and as the same
-    64 runs one after the other (the same packets), after autotuning on a
-    sample of the batch when args.autotune is set."""
+    """Multi-wavelength gradients of 64 problems: 16 sources x 4 wavelengths
+    (mua scaled 0.5, 1, 2, 4), grids drawn from {128, 192, 256, 512}^2 over
+    the same 25.6 mm square, packets per problem log-uniform in
+    [args.batch_min, args.batch_max], N = 16.  Each problem's gradient is its
+    forward run, the residual against its measured data (a 1e6-packet run on
+    a second phantom, untimed set-up), its adjoint run and the gradient.
+    Timed two ways on the same problems and packets: batched (the 64 forward
+    runs in one mc_run_batch call, then the 64 adjoint runs in another) and
+    one problem after the other.  The batch moves each problem's packets
+    exactly as its own run does, so both reach the same gradient error and
+    the ratio of the wall times is the time to the same error.  The maps are
+    the same bits while every pixel's FP64 sum is exact; at 1e7-1e8 packets
+    the brightest pixels' sums pass 2^53 of their quanta and round in the
+    order the atomics arrive, so the comparison reports the largest relative
+    differences of the forward maps and of the gradients.  With
+    args.autotune the batch first tunes on a sample of itself."""
     import numpy as np
     import torch
     import phantoms as P
@@ -331,6 +341,7 @@ def batch_workload(args) -> dict:
     rng = np.random.default_rng(3)
     dev = torch.device("cuda", 0)
     side = 25.6
+    N = 16
     sizes = rng.choice([128, 192, 256, 512], size=16)      # one grid per source
     # 16 sources: four collimated segments along each side, inward
     segs = []
@@ -340,45 +351,82 @@ def batch_workload(args) -> dict:
                  P.SourceSpec("line", a, side, b, side, 0.0, -1.0, 0, 1.0),
                  P.SourceSpec("line", 0.0, a, 0.0, b, 1.0, 0.0, 0, 1.0),
                  P.SourceSpec("line", side, a, side, b, -1.0, 0.0, 0, 1.0)]
-    probs, meta = [], []
+    probs, truth, meta = [], [], []
     for si in range(16):
         n = int(sizes[si])
         base = P.disc_phantom(n, side / n, 0.01, 10.0, 0.9, seed=100 + si)
+        true = P.disc_phantom(n, side / n, 0.01, 10.0, 0.9, seed=500 + si)
         for wi, f in enumerate((0.5, 1.0, 2.0, 4.0)):
-            ph = base.copy()
+            ph, tp = base.copy(), true.copy()
             ph.mua = (ph.mua * f).astype(np.float32)
+            tp.mua = (tp.mua * f).astype(np.float32)
             npk = int(np.exp(rng.uniform(np.log(args.batch_min), np.log(args.batch_max))))
             probs.append(rmc.Problem(rmc.Medium.from_phantom(ph, dev), [segs[si]],
-                                     rmc.make_run(npk, 16, seed=1000 + 4 * si + wi)))
+                                     rmc.make_run(npk, N, seed=1000 + 4 * si + wi)))
+            truth.append(rmc.Problem(rmc.Medium.from_phantom(tp, dev), [segs[si]],
+                                     rmc.make_run(1_000_000, N, seed=3000 + 4 * si + wi)))
             meta.append((n, f, npk))
     total = sum(m[2] for m in meta)
+    log(f"batch: measured data of 64 problems ({sum(n * n for n, _, _ in meta):.3e} pixels)")
+    hmeas = [rmc.mc_absorbed(t.medium, o[0]) for t, o in zip(truth, rmc.mc_run_batch(truth, ledger=False))]
     tuned = None
     if args.autotune:
         from paper_1608_05238_amd import autotune
         log("autotune on every 4th problem at a quarter of its packets")
         tuned = autotune.tune_batch(probs, every=4, scale=0.25, log=log)["tuning"]
+
+    def adjoint_problem(pr, q):
+        r = pr.run
+        return rmc.Problem(pr.medium, [rmc.Source("map", map=q)],
+                           rmc.make_run(r.n_packets, N, seed=r.seed, stream_tag=1), True)
+
+    def batched():
+        fw = [o[0] for o in rmc.mc_run_batch(probs, ledger=False, tuning=tuned)]
+        qs = [rmc.mc_residual(pr.medium, f, h)[0] for pr, f, h in zip(probs, fw, hmeas)]
+        ad = [o[0] for o in rmc.mc_run_batch([adjoint_problem(pr, q) for pr, q in zip(probs, qs)], ledger=False,
+                                             tuning=tuned)]
+        return fw, [rmc.mc_gradient(pr.medium, N, f, a, h) for pr, f, a, h in zip(probs, fw, ad, hmeas)]
+
+    def one_by_one():
+        out, fws = [], []
+        for k, (pr, h) in enumerate(zip(probs, hmeas)):
+            if k % 16 == 0:
+                log(f"one by one: problem {k}")
+            f, _ = rmc.mc_forward(pr.medium, pr.sources, pr.run, ledger=False, tuning=tuned)
+            fws.append(f)
+            q, _ = rmc.mc_residual(pr.medium, f, h)
+            ap = adjoint_problem(pr, q)
+            a, _ = rmc.mc_adjoint(ap.medium, ap.sources, ap.run, ledger=False, tuning=tuned)
+            out.append(rmc.mc_gradient(pr.medium, N, f, a, h))
+        return fws, out
+
     rmc.mc_run_batch(probs[:2], ledger=False)   # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    rmc.mc_run_batch(probs, ledger=False)
+    fb, gb = batched()
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
-    log(f"batch: {t_batch:.2f} s for {total:.3e} packets")
+    log(f"batched: {t_batch:.2f} s for {total:.3e} + {total:.3e} packets")
     t0 = time.perf_counter()
-    for pr in probs:
-        rmc.mc_forward(pr.medium, pr.sources, pr.run, ledger=False)
+    fs, gs = one_by_one()
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t0
     log(f"one by one: {t_seq:.2f} s")
-    return {"metric": "packets/s fwd MC, 64 problems in one packet pool (N=16 harmonics)",
-            "value": total / t_batch, "unit": "packets/s", "higher_is_better": True, "n_gpus": 1,
+    same = all(torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) for a, b in zip(gb, gs))
+    rel = lambda a, b: float((a - b).abs().max() / b.abs().max().clamp_min(1e-300))
+    diff_f = max(rel(a, b) for a, b in zip(fb, fs))
+    diff_g = max(max(rel(a[0], b[0]), rel(a[1], b[1])) for a, b in zip(gb, gs))
+    return {"metric": "wall time to 64 multi-wavelength gradients (fwd + residual + adj + gradient each, N=16)",
+            "value": t_batch, "unit": "s", "higher_is_better": False, "n_gpus": 1,
             "dtype": "f32", "data": "synthetic",
             "config": {"workload": "64 problems: 16 segment sources x 4 wavelengths (mua x0.5-4), grids "
                                    "{128,192,256,512}^2 over 25.6 mm, disc phantoms",
-                       "packets_total": total, "packets_per_problem": [args.batch_min, args.batch_max],
+                       "packets_per_run_total": total, "packets_per_problem": [args.batch_min, args.batch_max],
                        "grids": [int(x) for x in sizes]},
-            "batch_s": t_batch, "one_by_one_s": t_seq, "one_by_one_packets_per_s": total / t_seq,
-            "speedup": t_seq / t_batch, "tuning": tuned}
+            "batched_s": t_batch, "one_by_one_s": t_seq, "speedup": t_seq / t_batch,
+            "packets_per_s_batched": 2 * total / t_batch, "packets_per_s_one_by_one": 2 * total / t_seq,
+            "gradients_bitwise_equal": same, "max_rel_diff_forward_maps": diff_f, "max_rel_diff_gradients": diff_g,
+            "tuning": tuned}
 
 
 def pencil32(args) -> dict:
@@ -441,9 +489,9 @@ def main() -> int:
                     help="time single gradients (forward + residual + adjoint + gradient) at this many packets "
                          "per run, without the reference and the search of --time-to-error")
     ap.add_argument("--batch", action="store_true",
-                    help="instead of the throughput line, time the 64-problem batched workload")
-    ap.add_argument("--batch-min", type=float, default=1e6)
-    ap.add_argument("--batch-max", type=float, default=1e7)
+                    help="instead of the throughput line, time the 64-problem gradients batched and one by one")
+    ap.add_argument("--batch-min", type=float, default=1e7)
+    ap.add_argument("--batch-max", type=float, default=1e8)
     ap.add_argument("--autotune", action="store_true", help="with --batch: autotune before timing")
     ap.add_argument("--pencil32", action="store_true",
                     help="instead of the throughput line, time the 32x32 pencil-beam forward run (N = 8 and 16)")

@@ -897,7 +897,7 @@ __device__ __forceinline__ void slice_finish(const Gen &G, int pool, QueueSlice 
 
 // ---- generation step 1: launch and count (the last workgroup scans)
 constexpr int kGenBlock = 1024;
-constexpr int kHistTiles = 4096;   // tiles histogrammed in LDS; beyond, wave-aggregated global atomics
+constexpr int kHistTiles = 32768;  // tiles histogrammed in LDS (dynamic, 4 bytes each); beyond, wave-aggregated global atomics
 constexpr int kMaxAlloc = 256;     // problems that receive new packets in one generation
 
 // Counts one record of tile t (LDS histogram, or the global count directly).
@@ -1001,7 +1001,7 @@ __device__ void gen_scan(const Gen &G, int g, uint32_t *buf, int np, const uint3
 
 __global__ void __launch_bounds__(kGenBlock) k_gen_count(Gen G, int g) {
     GenCtl *C = G.ctl;
-    __shared__ uint32_t hist[kHistTiles];
+    extern __shared__ uint32_t hist[];   // max(ntiles, 2 kGenBlock) counts (gen_hist_lds), or the scan's buffer
     __shared__ uint32_t a_prob[kMaxAlloc], a_new[kMaxAlloc], a_pre[kMaxAlloc + 1];
     __shared__ uint64_t a_base[kMaxAlloc];
     __shared__ uint32_t w_cnt[kGenBlock / 64];
@@ -1115,10 +1115,12 @@ __global__ void __launch_bounds__(kGenBlock) k_gen_count(Gen G, int g) {
 // ---- generation step 2: sort the record indices by tile
 // A workgroup takes chunks of kScatterChunk records of the generation (the
 // pool's carried region, then its launch region); each record gets its rank
-// among the chunk's records of its tile from an LDS atomic, the workgroup
-// reserves one range per tile it holds with a single global atomic, and the
-// record's slot index lands at range start + rank.  Beyond kHistTiles tiles,
-// ranks come from wave-aggregated global atomics.
+// among the chunk's records of its tile from an LDS atomic on that tile's
+// counter, the record of rank 0 reserves the tile's range with one global
+// atomic and leaves the range's start in the counter, and every record's
+// slot index lands at start + rank; the rank-0 records then clear their
+// counters, so a chunk costs in proportion to its records, not to the tiles.
+// Beyond kHistTiles tiles, ranks come from wave-aggregated global atomics.
 constexpr int kScatterPer = 8;                              // records per thread and chunk
 constexpr uint32_t kScatterChunk = 256u * kScatterPer;
 
@@ -1127,8 +1129,7 @@ __device__ __forceinline__ uint32_t gen_slot(const Gen &G, uint32_t u, uint32_t 
 }
 
 __global__ void __launch_bounds__(256) k_gen_scatter(Gen G, int g) {
-    __shared__ uint32_t cnt[kHistTiles];
-    __shared__ uint32_t start[kHistTiles];
+    extern __shared__ uint32_t cnt[];   // [ntiles] when ntiles <= kHistTiles (gen_hist_lds)
     GenCtl *C = G.ctl;
     if (C->done) return;
     const int cur = g & 1;
@@ -1137,9 +1138,9 @@ __global__ void __launch_bounds__(256) k_gen_scatter(Gen G, int g) {
     const uint32_t *pt = G.ptile[cur];
     const int lane = __lane_id();
     if (G.ntiles <= kHistTiles) {
+        for (int i = threadIdx.x; i < G.ntiles; i += blockDim.x) cnt[i] = 0u;
+        __syncthreads();
         for (uint32_t c0 = blockIdx.x * kScatterChunk; c0 < n; c0 += gridDim.x * kScatterChunk) {
-            for (int i = threadIdx.x; i < G.ntiles; i += blockDim.x) cnt[i] = 0u;
-            __syncthreads();
             uint32_t t[kScatterPer], rank[kScatterPer];
 #pragma unroll
             for (int r = 0; r < kScatterPer; ++r) {
@@ -1148,15 +1149,20 @@ __global__ void __launch_bounds__(256) k_gen_scatter(Gen G, int g) {
                 rank[r] = t[r] != kInvalidTile ? atomicAdd(cnt + t[r], 1u) : 0u;
             }
             __syncthreads();
-            for (int i = threadIdx.x; i < G.ntiles; i += blockDim.x)
-                start[i] = cnt[i] ? atomicAdd(G.tile_cursor + i, cnt[i]) : 0u;
+#pragma unroll
+            for (int r = 0; r < kScatterPer; ++r)
+                if (t[r] != kInvalidTile && rank[r] == 0u) cnt[t[r]] = atomicAdd(G.tile_cursor + t[r], cnt[t[r]]);
             __syncthreads();
 #pragma unroll
             for (int r = 0; r < kScatterPer; ++r) {
                 if (t[r] == kInvalidTile) continue;
-                const uint32_t pos = start[t[r]] + rank[r];
+                const uint32_t pos = cnt[t[r]] + rank[r];
                 if (pos < G.live) G.sidx[pos] = gen_slot(G, c0 + r * 256u + threadIdx.x, nc);
             }
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < kScatterPer; ++r)
+                if (t[r] != kInvalidTile && rank[r] == 0u) cnt[t[r]] = 0u;
             __syncthreads();
         }
         return;
@@ -2522,9 +2528,15 @@ mc_status run_batch(const BatchProblem *pb, int n, const TileTuning &tt, mc_time
     G.slots = tgrid;
     const unsigned cgrid = (unsigned)std::max(1, cus);
     const unsigned sgrid = (unsigned)std::max(1, 4 * cus);
+    // the generation kernels' tile histograms (and the scan's buffer) in dynamic LDS
+    const bool local_hist = B.ntiles <= kHistTiles;
+    const size_t count_lds = sizeof(uint32_t) * std::max<size_t>(local_hist ? B.ntiles : 0, 2 * kGenBlock);
+    const size_t scatter_lds = local_hist ? sizeof(uint32_t) * B.ntiles : 0;
+    if ((st = set_lds_limit(reinterpret_cast<const void *>(k_gen_count), count_lds)) != MC_OK) return st;
+    if ((st = set_lds_limit(reinterpret_cast<const void *>(k_gen_scatter), scatter_lds)) != MC_OK) return st;
     for (uint32_t g = 0; g < B.tt.max_gen; ++g) {
-        hipLaunchKernelGGL(k_gen_count, dim3(cgrid), dim3(kGenBlock), 0, s, G, (int)g);
-        hipLaunchKernelGGL(k_gen_scatter, dim3(sgrid), dim3(256), 0, s, G, (int)g);
+        hipLaunchKernelGGL(k_gen_count, dim3(cgrid), dim3(kGenBlock), count_lds, s, G, (int)g);
+        hipLaunchKernelGGL(k_gen_scatter, dim3(sgrid), dim3(256), scatter_lds, s, G, (int)g);
         LaunchTimer tm(timer);
         if ((st = tm.begin(s)) != MC_OK) return st;
         hipLaunchKernelGGL(fn, dim3(tgrid), dim3(kBlockTile), B.tile_lds, s, G, (int)g);
