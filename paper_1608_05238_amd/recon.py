@@ -9,6 +9,9 @@ coefficients.  The paper itself used gradient descent with line searches
 (Sec. 6); L-BFGS is the quasi-Newton alternative on the same gradients.
 
     python -m paper_1608_05238_amd.recon            # 256x256 two-inclusion phantom
+
+Before the iterations it checks the gradient at the initial guess against a
+reference from 1e9 + 1e9 packets (--ref-packets).
 """
 from __future__ import annotations
 
@@ -55,6 +58,40 @@ def reconstruct(mua0: torch.Tensor, mus0: torch.Tensor, g: torch.Tensor, dx: flo
     return torch.exp(th_a).detach(), torch.exp(th_s).detach(), hist
 
 
+def reference_check(mua0, mus0, g, dx, sources, hmeas, packets: int, ref_packets: int, n_harm: int = 16,
+                    margin: int = 10, log=None) -> dict:
+    """The autograd gradient of eps at (mua0, mus0) from `packets`-packet runs
+    (two seeds) against the explicit residual / adjoint / gradient chain from
+    ref_packets + ref_packets packets: relative L2 errors over pixels at least
+    `margin` from the boundary, and the error the two seeds' difference
+    predicts from Monte Carlo noise alone."""
+    from .autograd import MCConfig
+    med = rmc.Medium(mua0.float().contiguous(), mus0.float().contiguous(), g.float().contiguous(), float(dx))
+    t0 = time.time()
+    f, _ = rmc.mc_forward(med, sources, rmc.make_run(ref_packets, n_harm, seed=555), ledger=False)
+    q, _ = rmc.mc_residual(med, f, hmeas)
+    a, _ = rmc.mc_adjoint(med, [rmc.Source("map", map=q)], rmc.make_run(ref_packets, n_harm, seed=555, stream_tag=1),
+                          ledger=False)
+    ref = rmc.mc_gradient(med, n_harm, f, a, hmeas)
+    if log:
+        log(f"reference gradient from {ref_packets:.0e} + {ref_packets:.0e} packets: {time.time() - t0:.1f} s")
+    grads = []
+    for seed in (7, 8):
+        ta = mua0.double().clone().requires_grad_(True)
+        ts = mus0.double().clone().requires_grad_(True)
+        h = absorbed_energy(ta, ts, g, dx, sources, MCConfig(packets, n_harm, seed=seed))
+        error_functional(h, hmeas, dx).backward()
+        grads.append((ta.grad.detach(), ts.grad.detach()))
+    m = margin
+    out = {"packets": packets, "reference_packets": ref_packets}
+    for k, name in ((0, "dmua"), (1, "dmus")):
+        r = ref[k][m:-m, m:-m]
+        g1, g2 = grads[0][k][m:-m, m:-m], grads[1][k][m:-m, m:-m]
+        out[f"err_{name}"] = [float((gg - r).norm() / r.norm()) for gg in (g1, g2)]
+        out[f"noise_{name}"] = float((g1 - g2).norm() / 2 ** 0.5 / r.norm())
+    return out
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--n", type=int, default=256)
@@ -63,6 +100,8 @@ def main(argv=None) -> int:
     ap.add_argument("--packets", type=float, default=1e7)
     ap.add_argument("--hmeas-packets", type=float, default=1e8)
     ap.add_argument("--fit", choices=("mua", "mus", "both"), default="both")
+    ap.add_argument("--ref-packets", type=float, default=1e9,
+                    help="packets per run of the reference gradient at the initial guess (0: skip)")
     args = ap.parse_args(argv)
     dev = torch.device("cuda", 0)
     n, dx = args.n, args.dx
@@ -81,6 +120,10 @@ def main(argv=None) -> int:
     hmeas = rmc.mc_absorbed(true, f)
     mua0 = torch.full((n, n), 0.01, dtype=torch.float32, device=dev) if args.fit != "mus" else true.mua.clone()
     mus0 = torch.full((n, n), 10.0, dtype=torch.float32, device=dev) if args.fit != "mua" else true.mus.clone()
+    check = None
+    if args.ref_packets > 0:
+        check = reference_check(mua0, mus0, g, dx, sources, hmeas, int(args.packets), int(args.ref_packets),
+                                log=lambda m: print(m, file=sys.stderr, flush=True))
     t0 = time.time()
     mua, mus, hist = reconstruct(mua0, mus0, g, dx, sources, hmeas, MCConfig(int(args.packets), 16, seed=7),
                                  args.iters, fit_mua=args.fit != "mus", fit_mus=args.fit != "mua",
@@ -93,7 +136,8 @@ def main(argv=None) -> int:
            "mua_rel_l2_error_initial": float((mua0.double() - ta).norm() / ta.norm()),
            "mua_rel_l2_error_final": float((mua.double() - ta).norm() / ta.norm()),
            "mus_rel_l2_error_initial": float((mus0.double() - ts).norm() / ts.norm()),
-           "mus_rel_l2_error_final": float((mus.double() - ts).norm() / ts.norm())}
+           "mus_rel_l2_error_final": float((mus.double() - ts).norm() / ts.norm()),
+           "gradient_vs_reference_at_start": check}
     print(json.dumps(out), flush=True)
     return 0
 

@@ -114,3 +114,37 @@ def test_lbfgs_reduces_eps():
     err0 = float((mua0.double() - true.mua.double()).norm())
     err1 = float((mua.double() - true.mua.double()).norm())
     assert err1 < err0, (err0, err1)
+
+
+def test_autograd_gradient_against_a_high_count_reference():
+    """The autograd gradient of eps from 2e5-packet runs against the explicit
+    chain's gradient from 2e7 + 2e7 packets: each of two independent seeds
+    misses the reference by what its Monte Carlo noise explains (estimated
+    from the two seeds' difference, the reference's own noise a tenth of it),
+    and their mean is closer than either -- the gradient is unbiased up to
+    the reference's noise."""
+    torch, A, rmc = _mods()
+    ph, med, src = _case(torch, rmc)
+    hm = torch.as_tensor(P.smooth_hmeas(ph, level=0.02), device=med.mua.device)
+    N, n, n_ref = 16, 200_000, 20_000_000
+    f, _ = rmc.mc_forward(med, src, rmc.make_run(n_ref, N, seed=99), ledger=False)
+    q, _ = rmc.mc_residual(med, f, hm)
+    a, _ = rmc.mc_adjoint(med, [rmc.Source("map", map=q)], rmc.make_run(n_ref, N, seed=99, stream_tag=1), ledger=False)
+    ref = rmc.mc_gradient(med, N, f, a, hm)
+    grads = []
+    for seed in (11, 12):
+        mua = med.mua.double().clone().requires_grad_(True)
+        mus = med.mus.double().clone().requires_grad_(True)
+        h = A.absorbed_energy(mua, mus, med.g, med.dx, src, A.MCConfig(n, N, seed=seed))
+        A.error_functional(h, hm, med.dx).backward()
+        grads.append((mua.grad.detach(), mus.grad.detach()))
+    m = 4   # interior pixels
+    for k in range(2):
+        r = ref[k][m:-m, m:-m]
+        g1, g2 = grads[0][k][m:-m, m:-m], grads[1][k][m:-m, m:-m]
+        noise = float((g1 - g2).norm() / 2 ** 0.5 / r.norm())   # one low-count gradient's relative noise
+        e1, e2 = float((g1 - r).norm() / r.norm()), float((g2 - r).norm() / r.norm())
+        em = float(((g1 + g2) / 2 - r).norm() / r.norm())
+        bound = 1.3 * (noise ** 2 * (1 + n / n_ref)) ** 0.5 + 0.01
+        assert e1 < bound and e2 < bound, (k, e1, e2, noise)
+        assert em < min(e1, e2), (k, em, e1, e2)
