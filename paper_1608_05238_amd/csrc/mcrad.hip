@@ -769,6 +769,11 @@ struct GenCtl {
 };
 
 // Batch-wide parameters of the tiled kernels (by value).
+// Each tile's sort cursor sits in a 128-byte line of its own: the sort's
+// reservations are device atomics, and those on one line are serialised, so
+// cursors packed 32 to a line would make the tiles wait for each other.
+constexpr uint32_t kCursorStride = 32;
+
 struct Gen {
     int tw, th, ntiles, nprob;
     uint32_t live;                // packets kept alive per generation
@@ -783,7 +788,8 @@ struct Gen {
     struct PacketRec *pool[2];    // [cap_c + cap_l] records
     uint32_t *ptile[2];           // tile of each slot (kInvalidTile: empty slot)
     uint32_t *sidx;               // slots of the generation's records sorted by tile [live]
-    uint32_t *tile_count, *tile_cursor;
+    uint32_t *tile_count;
+    uint32_t *tile_cursor;        // [ntiles][kCursorStride]: one 128-byte line per tile's cursor
     uint4 *jobs;                  // (tile, first position in sidx, count, problem)
     uint32_t max_jobs;
     GenCtl *ctl;
@@ -899,6 +905,7 @@ __device__ __forceinline__ void slice_finish(const Gen &G, int pool, QueueSlice 
 constexpr int kGenBlock = 1024;
 constexpr int kHistTiles = 32768;  // tiles histogrammed in LDS (dynamic, 4 bytes each); beyond, wave-aggregated global atomics
 constexpr int kMaxAlloc = 256;     // problems that receive new packets in one generation
+constexpr int kCountPer = 8;       // carried records per thread and pass of the count
 
 // Counts one record of tile t (LDS histogram, or the global count directly).
 __device__ __forceinline__ void count_tile(const Gen &G, uint32_t *hist, bool local, uint32_t t, bool valid) {
@@ -960,7 +967,7 @@ __device__ void gen_scan(const Gen &G, int g, uint32_t *buf, int np, const uint3
     uint32_t roff = s_rec[t] - nrec, joff = s_job[t] - njob;
     for (int i = a; i < b; ++i) {
         const uint32_t c = G.tile_count[i];
-        G.tile_cursor[i] = roff;
+        G.tile_cursor[(size_t)i * kCursorStride] = roff;
         if (fits)
             for (uint32_t s0 = 0; s0 < c; s0 += js)
                 G.jobs[joff++] = make_uint4((uint32_t)i, roff + s0, min(js, c - s0), G.tile_prob[i]);
@@ -1089,12 +1096,20 @@ __global__ void __launch_bounds__(kGenBlock) k_gen_count(Gen G, int g) {
         const ProbDev &q = G.probs[a_prob[lk]];
         ledger_flush_block(q.led, q.ledc, L);
     }
-    // the records carried over from the last generation
+    // the records carried over from the last generation, kCountPer per
+    // thread with every load issued before the first is counted (an index
+    // past the records reads the last one, then counts as no record)
     const uint32_t nc = min(C->nc[cur], G.cap_c);
-    for (uint32_t b0 = blockIdx.x * kGenBlock; b0 < nc; b0 += gridDim.x * kGenBlock) {
-        const uint32_t i = b0 + threadIdx.x;
-        const uint32_t t = i < nc ? G.ptile[cur][i] : kInvalidTile;
-        count_tile(G, hist, local, t, t != kInvalidTile);
+    const uint32_t *ct = G.ptile[cur];
+    for (uint32_t b0 = blockIdx.x * kGenBlock * kCountPer; b0 < nc; b0 += gridDim.x * kGenBlock * kCountPer) {
+        uint32_t t[kCountPer];
+#pragma unroll
+        for (int r = 0; r < kCountPer; ++r) t[r] = ct[min(b0 + r * kGenBlock + threadIdx.x, nc - 1u)];
+#pragma unroll
+        for (int r = 0; r < kCountPer; ++r) {
+            const bool in = b0 + r * kGenBlock + threadIdx.x < nc;
+            count_tile(G, hist, local, t[r], in && t[r] != kInvalidTile);
+        }
     }
     __syncthreads();
     if (local)
@@ -1141,28 +1156,54 @@ __global__ void __launch_bounds__(256) k_gen_scatter(Gen G, int g) {
         for (int i = threadIdx.x; i < G.ntiles; i += blockDim.x) cnt[i] = 0u;
         __syncthreads();
         for (uint32_t c0 = blockIdx.x * kScatterChunk; c0 < n; c0 += gridDim.x * kScatterChunk) {
+            // the chunk's tiles, every load issued before the first is used
+            // (an index past the records reads the last record, then counts
+            // as no record)
             uint32_t t[kScatterPer], rank[kScatterPer];
 #pragma unroll
+            for (int r = 0; r < kScatterPer; ++r) t[r] = pt[gen_slot(G, min(c0 + r * 256u + threadIdx.x, n - 1u), nc)];
+#pragma unroll
             for (int r = 0; r < kScatterPer; ++r) {
-                const uint32_t u = c0 + r * 256u + threadIdx.x;
-                t[r] = u < n ? pt[gen_slot(G, u, nc)] : kInvalidTile;
+                if (c0 + r * 256u + threadIdx.x >= n) t[r] = kInvalidTile;
                 rank[r] = t[r] != kInvalidTile ? atomicAdd(cnt + t[r], 1u) : 0u;
             }
             __syncthreads();
+            // all counts read, then all reservations issued, then all starts
+            // written: the compiler cannot tell that a thread's rank-0 records
+            // are of different tiles, and interleaved, each LDS write would
+            // wait for its atomic's return before the next count is read
+            uint32_t cn[kScatterPer], base[kScatterPer];
+#pragma unroll
+            for (int r = 0; r < kScatterPer; ++r) cn[r] = t[r] != kInvalidTile && rank[r] == 0u ? cnt[t[r]] : 0u;
 #pragma unroll
             for (int r = 0; r < kScatterPer; ++r)
-                if (t[r] != kInvalidTile && rank[r] == 0u) cnt[t[r]] = atomicAdd(G.tile_cursor + t[r], cnt[t[r]]);
+                base[r] = cn[r] ? atomicAdd(G.tile_cursor + (size_t)t[r] * kCursorStride, cn[r]) : 0u;
+#pragma unroll
+            for (int r = 0; r < kScatterPer; ++r)
+                if (cn[r]) cnt[t[r]] = base[r];
             __syncthreads();
+            // the slot indices: every address formed before the first store
+            // (an address register reused from one store to the next would
+            // make each store wait for the one before)
+            uint32_t *dst[kScatterPer];
+            uint32_t val[kScatterPer];
 #pragma unroll
             for (int r = 0; r < kScatterPer; ++r) {
-                if (t[r] == kInvalidTile) continue;
-                const uint32_t pos = cnt[t[r]] + rank[r];
-                if (pos < G.live) G.sidx[pos] = gen_slot(G, c0 + r * 256u + threadIdx.x, nc);
+                const uint32_t pos = t[r] != kInvalidTile ? cnt[t[r]] + rank[r] : G.live;
+                dst[r] = pos < G.live ? G.sidx + pos : nullptr;
+                val[r] = gen_slot(G, c0 + r * 256u + threadIdx.x, nc);
             }
+#pragma unroll
+            for (int r = 0; r < kScatterPer; ++r)
+                if (dst[r]) *dst[r] = val[r];
+            // keeps every address and value in its own register until all
+            // stores are issued (emits no instruction)
+#pragma unroll
+            for (int r = 0; r < kScatterPer; ++r) asm volatile("" ::"v"(dst[r]), "v"(val[r]));
             __syncthreads();
 #pragma unroll
             for (int r = 0; r < kScatterPer; ++r)
-                if (t[r] != kInvalidTile && rank[r] == 0u) cnt[t[r]] = 0u;
+                if (cn[r]) cnt[t[r]] = 0u;
             __syncthreads();
         }
         return;
@@ -1178,7 +1219,7 @@ __global__ void __launch_bounds__(256) k_gen_scatter(Gen G, int g) {
             const uint32_t t0 = __shfl(t, leader);
             const unsigned long long same = __ballot(pend && t == t0);
             uint32_t b = 0;
-            if (lane == leader) b = atomicAdd(G.tile_cursor + t0, (uint32_t)__popcll(same));
+            if (lane == leader) b = atomicAdd(G.tile_cursor + (size_t)t0 * kCursorStride, (uint32_t)__popcll(same));
             b = __shfl(b, leader);
             if (pend && t == t0) {
                 const uint32_t pos = b + __popcll(same & ((1ull << lane) - 1ull));
@@ -2254,7 +2295,7 @@ BatchLayout batch_layout(const BatchProblem *pb, int n, const TileTuning &tt) {
     B.tcount = off;
     off = align_up(off + (size_t)B.ntiles * sizeof(uint32_t));
     B.tcursor = off;
-    off = align_up(off + (size_t)B.ntiles * sizeof(uint32_t));
+    off = align_up(off + (size_t)B.ntiles * kCursorStride * sizeof(uint32_t));
     B.jobs = off;
     off = align_up(off + B.max_jobs * sizeof(uint4));
     B.sidx = off;

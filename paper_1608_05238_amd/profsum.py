@@ -3,8 +3,8 @@ measurements.
 
     python -m paper_1608_05238_amd.profsum stats <dir>      # --kernel-trace --stats -f csv
     python -m paper_1608_05238_amd.profsum counters <dir>   # --pmc ... -f csv
-    python -m paper_1608_05238_amd.profsum tail <dir> <n> <kernel>[,<kernel>...]
-    python -m paper_1608_05238_amd.profsum counters-tail <dir> <n> <kernel>[,<kernel>...]
+    python -m paper_1608_05238_amd.profsum tail <dir> <n> <kernel>[,<kernel>...] [<launches>]
+    python -m paper_1608_05238_amd.profsum counters-tail <dir> <n> <kernel>[,<kernel>...] [<launches>]
     python -m paper_1608_05238_amd.profsum runs <dir>       # --kernel-trace, per Monte Carlo run
 
 `stats` prints the kernel summary table (calls, total, average); `counters`
@@ -14,7 +14,11 @@ average, so a counter of a plain copy of known size can calibrate the others;
 (from the per-dispatch kernel trace), e.g. the launches of a benchmark's
 timed steps; `counters-tail` sums each counter over the last n dispatches of
 the named kernels; `runs` cuts a kernel trace into Monte Carlo runs and sums
-each run's generation, tile and finisher kernels.  Only reads CSV files; no GPU work.
+each run's generation, tile and finisher kernels.  Given <launches>, `tail`
+and `counters-tail` also divide the totals by it: a benchmark's timer may
+bracket fewer launches than the dispatches its steps make (a launch that
+returns at once and is not timed), and the per-launch figures then match the
+timer's count.  Only reads CSV files; no GPU work.
 """
 from __future__ import annotations
 
@@ -76,7 +80,7 @@ def counters(root: str) -> str:
     return "\n".join(out)
 
 
-def counters_tail(root: str, n: int, kernels: list) -> str:
+def counters_tail(root: str, n: int, kernels: list, launches: int = 0) -> str:
     """Each counter summed over the last n dispatches (by dispatch id) of the
     named kernels, and its average per dispatch: the launches of a
     benchmark's timed steps without its set-up runs."""
@@ -104,9 +108,15 @@ def counters_tail(root: str, n: int, kernels: list) -> str:
         for c, v in vals[d].items():
             tot[c] += v
     kinds = ", ".join(f"{k}: {m}" for k, m in sorted(per.items()))
-    out = [f"last {len(last)} dispatches ({kinds})", "| counter | sum | per dispatch |", "|---|---|---|"]
-    for c, v in sorted(tot.items()):
-        out.append(f"| {c} | {v:.6e} | {v / len(last):.6e} |")
+    if launches:
+        out = [f"last {len(last)} dispatches ({kinds}), per launch over {launches} timed launches",
+               "| counter | sum | per dispatch | per launch |", "|---|---|---|---|"]
+        for c, v in sorted(tot.items()):
+            out.append(f"| {c} | {v:.6e} | {v / len(last):.6e} | {v / launches:.6e} |")
+    else:
+        out = [f"last {len(last)} dispatches ({kinds})", "| counter | sum | per dispatch |", "|---|---|---|"]
+        for c, v in sorted(tot.items()):
+            out.append(f"| {c} | {v:.6e} | {v / len(last):.6e} |")
     return "\n".join(out)
 
 
@@ -151,7 +161,7 @@ def runs(root: str, first_kernel: str = "k_ctl_init") -> str:
     return "\n".join(out)
 
 
-def tail(root: str, n: int, kernels: list) -> str:
+def tail(root: str, n: int, kernels: list, launches: int = 0) -> str:
     files = _find(root, "kernel_trace.csv")
     if not files:
         raise SystemExit(f"no *kernel_trace.csv under {root}")
@@ -171,19 +181,22 @@ def tail(root: str, n: int, kernels: list) -> str:
     for _, _, k in last:
         per[k] += 1
     mix = ", ".join(f"{k}: {c}" for k, c in sorted(per.items()))
-    return (f"last {len(last)} of {len(rows)} dispatches ({mix}): average {sum(dur) / len(dur) / 1e3:.2f} us, "
+    line = (f"last {len(last)} of {len(rows)} dispatches ({mix}): average {sum(dur) / len(dur) / 1e3:.2f} us, "
             f"total {sum(dur) / 1e3:.1f} us")
+    if launches:
+        line += f", {sum(dur) / launches / 1e3:.2f} us per timed launch ({launches})"
+    return line
 
 
 def main(argv) -> int:
-    if len(argv) == 5 and argv[1] == "tail":
-        print(tail(argv[2], int(argv[3]), argv[4].split(",")))
+    if len(argv) in (5, 6) and argv[1] == "tail":
+        print(tail(argv[2], int(argv[3]), argv[4].split(","), int(argv[5]) if len(argv) == 6 else 0))
         return 0
     if len(argv) == 3 and argv[1] == "runs":
         print(runs(argv[2]))
         return 0
-    if len(argv) == 5 and argv[1] == "counters-tail":
-        print(counters_tail(argv[2], int(argv[3]), argv[4].split(",")))
+    if len(argv) in (5, 6) and argv[1] == "counters-tail":
+        print(counters_tail(argv[2], int(argv[3]), argv[4].split(","), int(argv[5]) if len(argv) == 6 else 0))
         return 0
     if len(argv) != 3 or argv[1] not in ("stats", "counters"):
         print(__doc__, file=sys.stderr)
