@@ -50,17 +50,19 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
 
 # HBM traffic of the transport launches from two rocprofv3 counter passes
-# (FETCH_SIZE, then WRITE_SIZE, KiB summed over the launches of one benchmark
-# step and divided by their number), each scaled by what the same counter
-# reads for a plain 1 GiB device copy.  Valid only for the kernel source it
-# was measured on: reported as null once that source changes.
+# (FETCH_SIZE, then WRITE_SIZE, KiB summed over all 1092 transport dispatches
+# of one benchmark step and divided by the 1090 launches the timer brackets:
+# the two untimed finisher passes for unlaunched packets find none), each
+# scaled by what the same counter reads for a plain 1 GiB device copy.  Valid
+# only for the kernel source it was measured on: reported as null once that
+# source changes.
 TRAFFIC = {
-    "source_sha256": "6954498b660da4c8fd10b08cf8fb0bc62180db227f6defc138bcf357212f2648",
-    "fetch_kib_per_launch": 342964.0, "fetch_factor": 2.000,
-    "write_kib_per_launch": 546638.3, "write_factor": 1.000,
+    "source_sha256": "8e245917a7a2a3e34a7108d8fe9eda2af79c0200440e2d1b417b64b329cd3e44",
+    "fetch_kib_per_launch": 350624.3, "fetch_factor": 2.000,
+    "write_kib_per_launch": 555591.8, "write_factor": 1.000,
     # VALU wave-instructions per pixel visit (rocprofv3 SQ_INSTS_VALU over the
-    # k_transport_tile<16> and k_finish<16> dispatches of one benchmark step)
-    "valu_per_visit": 13.891,
+    # same dispatches, divided by the step's pixel visits)
+    "valu_per_visit": 14.201,
 }
 
 # Algorithmic arithmetic of the method, in lane-operations (one FMA, compare,
