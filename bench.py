@@ -57,12 +57,12 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
 # only for the kernel source it was measured on: reported as null once that
 # source changes.
 TRAFFIC = {
-    "source_sha256": "8e245917a7a2a3e34a7108d8fe9eda2af79c0200440e2d1b417b64b329cd3e44",
-    "fetch_kib_per_launch": 350624.3, "fetch_factor": 2.000,
-    "write_kib_per_launch": 555591.8, "write_factor": 1.000,
+    "source_sha256": "0d91fdad3c5157d724a61d4d6b5a90a0e4f6d7b97f2067f47481680647051e7b",
+    "fetch_kib_per_launch": 347011.0, "fetch_factor": 2.000,
+    "write_kib_per_launch": 488758.0, "write_factor": 1.000,
     # VALU wave-instructions per pixel visit (rocprofv3 SQ_INSTS_VALU over the
     # same dispatches, divided by the step's pixel visits)
-    "valu_per_visit": 14.201,
+    "valu_per_visit": 13.147,
 }
 
 # Algorithmic arithmetic of the method, in lane-operations (one FMA, compare,

@@ -137,7 +137,7 @@ typedef struct {
  *  job_packets    packets of one tile handed to one workgroup, 64 .. 2^20
  *                 (a run or batch whose pool holds fewer than 2^23 live
  *                 packets uses half that, to spread over more workgroups;
- *                 default 4096)
+ *                 default 8192)
  *  max_visits     visits in one tile before a packet pauses until the next
  *                 generation, >= 1 (default 64)
  *  tile           tile side in pixels, 1 .. 256 (default, or a tile whose
@@ -153,7 +153,7 @@ typedef struct {
  *                 the run's weight bound, exceeds this many pixels is added
  *                 to the tile tally in parts, 0 .. 65536 (default 65536)
  *  tail_visits    once a job has turned quiet (quiet_percent), its packets
- *                 pause after this many more visits, 0 .. 2^30 (default 4)
+ *                 pause after this many more visits, 0 .. 2^30 (default 1)
  *  max_generations  tiled generations enqueued per call, 1 .. 65536
  *                 (default 0: 448 + 48 per pool of live_packets the run's
  *                 packets fill).  The host enqueues this many without
@@ -163,7 +163,7 @@ typedef struct {
  *                 finisher, so the results never depend on it.
  *  min_job_packets  a generation whose records would not give every
  *                 workgroup of the tiled kernel two jobs cuts its tiles into
- *                 smaller jobs, down to this size, 64 .. 2^20 (default 512)
+ *                 smaller jobs, down to this size, 64 .. 2^20 (default 1024)
  *  quiet_percent  a job turns quiet once the packets whose stay in its tile
  *                 has not ended number at most this percent of
  *                 min(job packets, 512); its packets then pause after

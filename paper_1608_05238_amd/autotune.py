@@ -30,11 +30,11 @@ from . import rmc
 
 DEFAULT_CANDIDATES = {
     "live_packets": (1 << 25, 1 << 26),
-    "job_packets": (2048, 4096, 8192),
+    "job_packets": (4096, 8192, 16384),
     "max_visits": (32, 64, 128),
-    "tail_visits": (2, 4, 8),
+    "tail_visits": (1, 2, 4),
     "quiet_percent": (35, 50, 75),
-    "min_job_packets": (256, 512, 1024),
+    "min_job_packets": (512, 1024, 2048),
     "tile": (12, 16),
 }
 

@@ -2072,16 +2072,20 @@ size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 // 2^25: -1.1%.  The finisher threshold, the quiet rule, its tail and the
 // smallest job were set together on the 2.83e6-packet disc256 gradient
 // (2^16 / 50% / 4 / 512: 206 ms against 234 ms for 2^17 / 100% / 8 / no
-// split), which also shortens the 1e8-packet one by 3%.
+// split), which also shortened the 1e8-packet one by 3%.  Once the sort no
+// longer serialised on its cursors, generations got cheap enough for a
+// shorter tail and larger jobs: tail 1, jobs of 8192, smallest job 1024 run
+// forward + adjoint at 2.83e6 packets in 195 ms against 205 ms, and at 1e8
+// in 2382 ms against 2484 ms (results bitwise the same).
 constexpr uint64_t kLiveMax = 1ull << 26;
 constexpr uint64_t kFinishMax = 1ull << 16;   // default finisher threshold: min(this, live / 128)
 constexpr uint64_t kGridMaxPackets = 1ull << 21;   // larger runs take the tiled transport
-constexpr uint32_t kJobSize = 4096;           // packets per job
+constexpr uint32_t kJobSize = 8192;           // packets per job
 constexpr uint64_t kSmallPool = 1ull << 23;   // pools below this many live packets use half-size jobs
 constexpr uint32_t kMaxVisitsPerStay = 64;    // a packet pauses after this many visits in one job
 // once a job has turned quiet, its packets pause after this many more visits,
 // so a wave does not idle behind its longest stay
-constexpr uint32_t kTailVisits = 4;
+constexpr uint32_t kTailVisits = 1;
 // generations enqueued per call unless the caller says: a base for the drain
 // of the longest histories plus a share per pool turnover (measured on the
 // disc256 workload: ~210 generations for 2.8e6 packets, ~390 for 1e8 at 2^26
@@ -2089,7 +2093,7 @@ constexpr uint32_t kTailVisits = 4;
 constexpr uint32_t kGenBase = 448, kGenPerPool = 48;
 constexpr int kTileWavesMax = 256 * 16;       // bound on resident waves of the tiled kernel
 constexpr int kTileSlotsMax = kTileWavesMax / (kBlockTile / 64);   // and on its workgroups
-constexpr uint32_t kJobMin = 512;              // smallest job of a generation with few packets (see gen_scan)
+constexpr uint32_t kJobMin = 1024;             // smallest job of a generation with few packets (see gen_scan)
 constexpr uint32_t kQuietPercent = 50;         // see the quiet rule of k_transport_tile
 
 // The tuning a call runs with: the caller's fields, defaults where zero.

@@ -127,9 +127,9 @@ def test_tuning_is_per_call_and_checked():
     L, lib = _lib()
     from paper_1608_05238_amd import rmc
     d = rmc.default_tuning()
-    assert d == {"live_packets": 1 << 26, "job_packets": 4096, "max_visits": 64, "tile": 0,
+    assert d == {"live_packets": 1 << 26, "job_packets": 8192, "max_visits": 64, "tile": 0,
                  "finish_packets": 1 << 16, "grid_max_packets": 1 << 21, "flush_track": 65536.0,
-                 "tail_visits": 4, "max_generations": 0, "min_job_packets": 512, "quiet_percent": 50}
+                 "tail_visits": 1, "max_generations": 0, "min_job_packets": 1024, "quiet_percent": 50}
     m = _medium(L)
     m.nx = m.nz = 256
     src = (L.mc_source * 1)(_pencil(L))
