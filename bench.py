@@ -57,9 +57,9 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
 # only for the kernel source it was measured on: reported as null once that
 # source changes.
 TRAFFIC = {
-    "source_sha256": "0d91fdad3c5157d724a61d4d6b5a90a0e4f6d7b97f2067f47481680647051e7b",
-    "fetch_kib_per_launch": 347011.0, "fetch_factor": 2.000,
-    "write_kib_per_launch": 488758.0, "write_factor": 1.000,
+    "source_sha256": "a121475aa5b74e52a501489e21bc30a3c5d08624349eb8d903cd4dec6fb91ef3",
+    "fetch_kib_per_launch": 258703.2, "fetch_factor": 2.000,
+    "write_kib_per_launch": 372396.9, "write_factor": 1.000,
     # VALU wave-instructions per pixel visit (rocprofv3 SQ_INSTS_VALU over the
     # same dispatches, divided by the step's pixel visits)
     "valu_per_visit": 13.147,
@@ -114,22 +114,23 @@ def valu_per_visit():
 def lds_atomic_ceiling(dev) -> float:
     """Lane-operations per second of random-address 64-bit integer LDS adds
     (the tally's atomic) on this device, measured now with the microbenchmark
-    kernel in the transport's shape (512-thread workgroups, 64 KiB of LDS
-    each), each lane adding to all 33 slots of a random row (one address per
-    33 adds, the pattern of a tally flush at N = 16); best of four launches."""
+    kernel in the transport's shape (1024-thread workgroups, 144 KiB of LDS
+    each, one per CU), each lane adding to all 33 slots of a random row (one
+    address per 33 adds, the pattern of a tally flush at N = 16); best of four
+    launches."""
     import ctypes as C
     import torch
     from paper_1608_05238_amd import _lib as L
     lib = L.load()
     ncu = torch.cuda.get_device_properties(dev).multi_processor_count
-    nblk, block, iters = ncu * 16, 512, 128
+    nblk, block, iters = ncu * 8, 1024, 128
     sink = torch.empty(nblk, dtype=torch.float64, device=dev)
     stream = C.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
     best = float("inf")
     for _ in range(4):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        L.check("mb_lds_atomics", lib.mb_lds_atomics(L.MB_LDS_ADD_U64_ROW33, 64 * 1024, block, nblk, iters, 7,
+        L.check("mb_lds_atomics", lib.mb_lds_atomics(L.MB_LDS_ADD_U64_ROW33, 144 * 1024, block, nblk, iters, 7,
                                                      sink.data_ptr(), None, stream))
         e1.record()
         e1.synchronize()

@@ -137,12 +137,12 @@ typedef struct {
  *  job_packets    packets of one tile handed to one workgroup, 64 .. 2^20
  *                 (a run or batch whose pool holds fewer than 2^23 live
  *                 packets uses half that, to spread over more workgroups;
- *                 default 8192)
+ *                 default 16384)
  *  max_visits     visits in one tile before a packet pauses until the next
  *                 generation, >= 1 (default 64)
  *  tile           tile side in pixels, 1 .. 256 (default, or a tile whose
- *                 tally does not fit: the largest square tile that fits two
- *                 workgroups per CU)
+ *                 tally does not fit: the largest square tile whose tally
+ *                 fits the LDS of one workgroup per CU, 23 at N = 16)
  *  finish_packets once every packet is launched and at most this many remain
  *                 they finish without migration (default: the smaller of
  *                 2^16 and live_packets / 128)

@@ -30,12 +30,12 @@ from . import rmc
 
 DEFAULT_CANDIDATES = {
     "live_packets": (1 << 25, 1 << 26),
-    "job_packets": (4096, 8192, 16384),
+    "job_packets": (8192, 16384, 32768),
     "max_visits": (32, 64, 128),
     "tail_visits": (1, 2, 4),
     "quiet_percent": (35, 50, 75),
     "min_job_packets": (512, 1024, 2048),
-    "tile": (12, 16),
+    "tile": (16, 23),
 }
 
 

@@ -55,10 +55,13 @@ constexpr int kMaxProf = 2 * (2 * MC_NHARM_MAX + 1);  // profile coefficients ov
 // whole-grid mode: 12 waves share one LDS tally (8 for high orders, whose
 // harmonic vectors need more registers)
 constexpr int grid_block(int nh) { return nh <= 16 ? 1024 : 512; }
-constexpr int kBlockTile = 512;                        // tiled mode: 8 waves per workgroup, 2 workgroups per CU
+// tiled mode: one workgroup per CU, holding the largest tile tally that
+// fits its LDS; 16 waves (4 per SIMD) for orders up to 16, 8 for higher
+// orders (whose visit accumulators need twice the registers)
+constexpr int tile_block(int nh) { return nh <= 16 ? 1024 : 512; }
 constexpr uint64_t kChunk = 1ull << 22;                // whole-grid mode: packets per launch
 constexpr size_t kLdsGridMax = 144 * 1024;             // whole-grid mode: tally bytes in LDS
-constexpr size_t kLdsTileMax = 72 * 1024;              // tiled mode: tile tally + medium bytes (2 WGs/CU)
+constexpr size_t kLdsTileMax = 150 * 1024;             // tiled mode: tile tally + medium bytes (1 WG/CU)
 constexpr uint32_t kInvalidTile = 0xFFFFFFFFu;
 constexpr uint32_t kSlice = 256;                       // queue slots a wave reserves at a time (default)
 constexpr float kPi = 3.14159265358979323846f;
@@ -1232,7 +1235,7 @@ __global__ void __launch_bounds__(256) k_gen_scatter(Gen G, int g) {
 
 // ---- generation step 3: move the packets tile by tile
 template <int NH>
-__global__ void __launch_bounds__(kBlockTile) __attribute__((amdgpu_waves_per_eu(NH <= 16 ? 4 : 2)))
+__global__ void __launch_bounds__(tile_block(NH)) __attribute__((amdgpu_waves_per_eu(NH <= 16 ? 4 : 2)))
 k_transport_tile(Gen G, int g) {
     constexpr int K = 2 * NH + 1;
     // [tw*th][K] fixed-point sums: value * fx of the job's problem (fixed_add)
@@ -1313,7 +1316,7 @@ k_transport_tile(Gen G, int g) {
         // quiet_pct percent of its lanes' worth (min(cnt, lanes)); from then
         // on a packet pauses after tail_visits more visits, so the workgroup
         // is not held by its longest stays (they resume next generation).
-        const uint32_t quiet_at = (uint32_t)(((uint64_t)min(cnt, (uint32_t)kBlockTile) * G.quiet_pct) / 100u);
+        const uint32_t quiet_at = (uint32_t)(((uint64_t)min(cnt, (uint32_t)tile_block(NH)) * G.quiet_pct) / 100u);
         bool quiet = false;       // wave-uniform
         uint32_t tail_nvis = 0;   // visits of the current stay when the job turned quiet
         // (the last word is the packet id alone: a load whose destination
@@ -2076,11 +2079,13 @@ size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 // longer serialised on its cursors, generations got cheap enough for a
 // shorter tail and larger jobs: tail 1, jobs of 8192, smallest job 1024 run
 // forward + adjoint at 2.83e6 packets in 195 ms against 205 ms, and at 1e8
-// in 2382 ms against 2484 ms (results bitwise the same).
+// in 2382 ms against 2484 ms (results bitwise the same).  With one
+// 1024-thread workgroup per CU and 23x23 tiles, jobs of 16384: 174 ms and
+// 2289 ms.
 constexpr uint64_t kLiveMax = 1ull << 26;
 constexpr uint64_t kFinishMax = 1ull << 16;   // default finisher threshold: min(this, live / 128)
 constexpr uint64_t kGridMaxPackets = 1ull << 21;   // larger runs take the tiled transport
-constexpr uint32_t kJobSize = 8192;           // packets per job
+constexpr uint32_t kJobSize = 16384;          // packets per job
 constexpr uint64_t kSmallPool = 1ull << 23;   // pools below this many live packets use half-size jobs
 constexpr uint32_t kMaxVisitsPerStay = 64;    // a packet pauses after this many visits in one job
 // once a job has turned quiet, its packets pause after this many more visits,
@@ -2092,7 +2097,7 @@ constexpr uint32_t kTailVisits = 1;
 // live packets, ~720 for 1e9)
 constexpr uint32_t kGenBase = 448, kGenPerPool = 48;
 constexpr int kTileWavesMax = 256 * 16;       // bound on resident waves of the tiled kernel
-constexpr int kTileSlotsMax = kTileWavesMax / (kBlockTile / 64);   // and on its workgroups
+constexpr int kTileSlotsMax = kTileWavesMax / (tile_block(MC_NHARM_MAX) / 64);   // and on its workgroups
 constexpr uint32_t kJobMin = 1024;             // smallest job of a generation with few packets (see gen_scan)
 constexpr uint32_t kQuietPercent = 50;         // see the quiet rule of k_transport_tile
 
@@ -2101,7 +2106,7 @@ struct TileTuning {
     uint64_t live = kLiveMax;
     uint32_t job = kJobSize, maxvis = kMaxVisitsPerStay, tailvis = kTailVisits;
     uint64_t finish = 0;   // 0: min(2^17, live / 128)
-    int tile = 0;          // 0: largest square tile for two workgroups per CU
+    int tile = 0;          // 0: largest square tile whose tally fits one workgroup's LDS
     uint64_t grid_max = kGridMaxPackets;
     double flush_track = kFlushTrackMax;
     uint32_t max_gen = 0;      // 0: kGenBase + kGenPerPool per pool of live packets the run holds
@@ -2567,7 +2572,7 @@ mc_status run_batch(const BatchProblem *pb, int n, const TileTuning &tt, mc_time
 
     const TileFn fn = kernels().tile[N];
     if ((st = set_lds_limit(reinterpret_cast<const void *>(fn), B.tile_lds)) != MC_OK) return st;
-    const int occ = occupancy_blocks(reinterpret_cast<const void *>(fn), kBlockTile, B.tile_lds);
+    const int occ = occupancy_blocks(reinterpret_cast<const void *>(fn), tile_block(N), B.tile_lds);
     const int cus = device_cus();
     const unsigned tgrid = (unsigned)std::max(1, std::min(cus * occ, kTileSlotsMax));
     G.slots = tgrid;
@@ -2584,7 +2589,7 @@ mc_status run_batch(const BatchProblem *pb, int n, const TileTuning &tt, mc_time
         hipLaunchKernelGGL(k_gen_scatter, dim3(sgrid), dim3(256), scatter_lds, s, G, (int)g);
         LaunchTimer tm(timer);
         if ((st = tm.begin(s)) != MC_OK) return st;
-        hipLaunchKernelGGL(fn, dim3(tgrid), dim3(kBlockTile), B.tile_lds, s, G, (int)g);
+        hipLaunchKernelGGL(fn, dim3(tgrid), dim3(tile_block(N)), B.tile_lds, s, G, (int)g);
         if ((st = tm.end(s)) != MC_OK) return st;
         if (hipGetLastError() != hipSuccess) return MC_ERR_DEVICE;
     }

@@ -127,7 +127,7 @@ def test_tuning_is_per_call_and_checked():
     L, lib = _lib()
     from paper_1608_05238_amd import rmc
     d = rmc.default_tuning()
-    assert d == {"live_packets": 1 << 26, "job_packets": 8192, "max_visits": 64, "tile": 0,
+    assert d == {"live_packets": 1 << 26, "job_packets": 16384, "max_visits": 64, "tile": 0,
                  "finish_packets": 1 << 16, "grid_max_packets": 1 << 21, "flush_track": 65536.0,
                  "tail_visits": 1, "max_generations": 0, "min_job_packets": 1024, "quiet_percent": 50}
     m = _medium(L)
