@@ -166,7 +166,8 @@ typedef struct {
  *                 smaller jobs, down to this size, 64 .. 2^20 (default 1024)
  *  quiet_percent  a job turns quiet once the packets whose stay in its tile
  *                 has not ended number at most this percent of
- *                 min(job packets, 512); its packets then pause after
+ *                 min(job packets, threads of a tile workgroup: 1024 for
+ *                 N <= 16, else 512); its packets then pause after
  *                 tail_visits more visits, 1 .. 100 (default 50) */
 typedef struct {
     uint64_t live_packets;
