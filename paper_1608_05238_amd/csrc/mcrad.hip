@@ -757,18 +757,22 @@ __global__ void __launch_bounds__(grid_block(NH)) k_transport_grid(GridArgs A) {
 // do nothing and the finisher (k_finish) moves the rest to their end.
 
 // Device control block of a tiled run (zeroed at set-up).
+// The counters that every workgroup or wave of a generation updates with
+// device atomics each sit in a 128-byte line of their own: atomics on one
+// line are serialised, whichever word they address.
 struct GenCtl {
     uint32_t done;                // the finisher threshold was met: later generations do nothing
     uint32_t fin_pool, fin_nc, fin_nl;   // where the finisher finds the records when done
     uint32_t gen_done;            // generations run before the threshold was met
-    uint32_t wg_done;             // workgroups of k_gen_count that finished (the last one scans)
-    uint32_t nc[2];               // carried-region slots reserved in pool p
-    uint32_t nvalid[2];           // valid records among them
-    uint32_t nl[2];               // launch-region records of pool p
-    uint32_t n_rec, n_jobs, job_cursor;
+    uint32_t n_rec, n_jobs;
     uint32_t overflow;            // a queue or the job list would have overflowed (output NaN)
     uint32_t new_first_prob;      // first problem with packets left to launch
     uint64_t launched_total, todo_total;
+    alignas(128) uint32_t wg_done;      // workgroups of k_gen_count that finished (the last one scans)
+    alignas(128) uint32_t job_cursor;   // jobs claimed by the tile kernel's workgroups
+    alignas(128) uint32_t nc[2];        // carried-region slots reserved in pool p
+    alignas(128) uint32_t nvalid[2];    // valid records among them
+    alignas(128) uint32_t nl[2];        // launch-region records of pool p
 };
 
 // Batch-wide parameters of the tiled kernels (by value).
