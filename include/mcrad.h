@@ -155,8 +155,9 @@ typedef struct {
  *  tail_visits    once a job has turned quiet (quiet_percent), its packets
  *                 pause after this many more visits, 0 .. 2^30 (default 1)
  *  max_generations  tiled generations enqueued per call, 1 .. 65536
- *                 (default 0: 448 + 48 per pool of live_packets the run's
- *                 packets fill).  The host enqueues this many without
+ *                 (default 0: 100, plus 30 per tile along the longest
+ *                 grid side of any problem, plus 48 per pool of
+ *                 live_packets the run's packets fill).  The host enqueues this many without
  *                 waiting; a generation that finds the finisher threshold
  *                 reached does nothing.  Packets still in flight (or not yet
  *                 launched) after the last one are moved to their end by the

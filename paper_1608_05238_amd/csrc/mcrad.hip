@@ -2095,11 +2095,15 @@ constexpr uint32_t kMaxVisitsPerStay = 64;    // a packet pauses after this many
 // once a job has turned quiet, its packets pause after this many more visits,
 // so a wave does not idle behind its longest stay
 constexpr uint32_t kTailVisits = 1;
-// generations enqueued per call unless the caller says: a base for the drain
-// of the longest histories plus a share per pool turnover (measured on the
-// disc256 workload: ~210 generations for 2.8e6 packets, ~390 for 1e8 at 2^26
-// live packets, ~720 for 1e9)
-constexpr uint32_t kGenBase = 448, kGenPerPool = 48;
+// generations enqueued per call unless the caller says: a base, a share per
+// tile along the longest grid side (a packet's life in generations grows with
+// the grid measured in tiles) and a share per pool turnover.  Measured with
+// 23x23 tiles at 1e8 packets: 36 generations on the 32^2 pencil beam, 130 /
+// 189 / 290 / 491 on 128^2 / 192^2 / 256^2 / 512^2 disc phantoms over the
+// same 25.6 mm, up to 1.4x that at half the absorption; 434 for the 256^2
+// adjoint at 4e8.  A generation that finds the run finished costs ~6 us; one
+// too few leaves its packets to the slower finisher.
+constexpr uint32_t kGenBase = 100, kGenPerTile = 30, kGenPerPool = 48;
 constexpr int kTileWavesMax = 256 * 16;       // bound on resident waves of the tiled kernel
 constexpr int kTileSlotsMax = kTileWavesMax / (tile_block(MC_NHARM_MAX) / 64);   // and on its workgroups
 constexpr uint32_t kJobMin = 1024;             // smallest job of a generation with few packets (see gen_scan)
@@ -2292,8 +2296,12 @@ BatchLayout batch_layout(const BatchProblem *pb, int n, const TileTuning &tt) {
     // jobs of one generation: one per tile plus one per job_size records, or
     // (when job sizes shrink to fill the workgroups) at most two per workgroup
     B.max_jobs = (uint64_t)B.ntiles + std::max<uint64_t>(B.live / B.job, 2ull * kTileSlotsMax) + 2;
-    if (!B.tt.max_gen)
-        B.tt.max_gen = (uint32_t)std::min<uint64_t>(65536, kGenBase + kGenPerPool * ((B.total_packets + B.live - 1) / B.live));
+    if (!B.tt.max_gen) {
+        uint64_t side = 0;   // the longest grid side of any problem, in tiles
+        for (int i = 0; i < n; ++i) side = std::max<uint64_t>(side, std::max(B.ntx[i], B.ntz[i]));
+        B.tt.max_gen = (uint32_t)std::min<uint64_t>(
+            65536, kGenBase + kGenPerTile * side + kGenPerPool * ((B.total_packets + B.live - 1) / B.live));
+    }
     B.probs = off;
     off = align_up(off + (size_t)n * sizeof(ProbDev));
     B.tile_prob = off;
