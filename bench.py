@@ -479,7 +479,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--packets", type=float, default=1e8, help="packets per MC run (forward and adjoint each)")
     ap.add_argument("--cpu-packets", type=int, default=250_000, help="oracle sample size (0: skip)")
-    ap.add_argument("--hmeas-packets", type=float, default=2e7)
+    ap.add_argument("--hmeas-packets", type=float, default=1e8)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this size first (calibrates HBM counters)")
     ap.add_argument("--time-to-error", action="store_true",
