@@ -1,6 +1,8 @@
 """Device ceilings the transport kernels are priced against (include/microbench.h).
 
     python -m paper_1608_05238_amd.microbench          # table + one JSON line
+    python -m paper_1608_05238_amd.microbench --lds-only 1024   # LDS atomics in one shape only
+                                                               # (for counter runs of rocprofv3)
 
 Each kernel is launched once to warm up, then five times; the fastest launch
 (HIP events on the launch stream) gives the rate.  Rates per CU per clock
@@ -37,7 +39,14 @@ def _check(name, st):
         raise L.MCError(name, st)
 
 
-def run_all(dev: int = 0) -> dict:
+# Workgroup shapes of the LDS-atomic kernels: the tiled transport's (one
+# 1024-thread workgroup with a 23x23-pixel tile per CU; 144 KiB of the
+# kernel's 150 KiB here) and the earlier two 512-thread workgroups with 64 KiB
+# each per CU.  Both hold 16 waves per CU, 4 per SIMD.
+LDS_SHAPES = {1024: (1024, 144 * 1024, 8), 512: (512, 64 * 1024, 16)}   # block, LDS bytes, workgroups per CU
+
+
+def run_all(dev: int = 0, lds_shapes=(1024, 512), lds_only: bool = False) -> dict:
     lib = L.load()
     torch.cuda.set_device(dev)
     d = torch.device("cuda", dev)
@@ -54,21 +63,27 @@ def run_all(dev: int = 0) -> dict:
 
     out = {"device": props.name, "cus": ncu, "wall_clock_khz": khz.value, "lds": [], "global_atomics": []}
 
-    # LDS atomics: 512-thread workgroups with 64 KiB each (two per CU, 4 waves per SIMD, as the transport)
-    block, lds, nblk = 512, 64 * 1024, ncu * 2 * 8
-    sink = torch.empty(nblk, dtype=torch.float64, device=d)
+    # LDS atomics in each shape (several workgroups per CU slot in turn)
     kinds = [(L.MB_LDS_ADD_F64, "ds_add_f64 random", 2048, 1), (L.MB_LDS_ADD_F32, "ds_add_f32 random", 2048, 1),
              (L.MB_LDS_ADD_U64, "ds_add_u64 random", 2048, 1), (L.MB_LDS_ADD_U32, "ds_add_u32 random", 2048, 1),
              (L.MB_LDS_ADD_F64_ROW33, "ds_add_f64 rows of 33", 64, 33),
              (L.MB_LDS_ADD_U64_ROW33, "ds_add_u64 rows of 33", 64, 33),
              (L.MB_LDS_ADD_U64_PRE, "ds_add_u64, 8 addresses drawn once", 256, 8)]
-    for kind, name, iters, per in kinds:
-        t = _time(lambda: _check("mb_lds_atomics", lib.mb_lds_atomics(kind, lds, block, nblk, iters, 7,
-                                                                       sink.data_ptr(), clk.data_ptr(), stream)))
-        f = mhz()
-        ops = nblk * block * iters * per
-        out["lds"].append({"kind": name, "lane_ops_per_s": ops / t, "shader_mhz": f,
-                           "lane_ops_per_clk_per_cu": ops / t / (f * 1e6) / ncu, "seconds": t})
+    for shape in lds_shapes:
+        block, lds, per_cu = LDS_SHAPES[shape]
+        nblk = ncu * per_cu
+        sink = torch.empty(nblk, dtype=torch.float64, device=d)
+        for kind, name, iters, per in kinds:   # the same threads per launch in both shapes
+            t = _time(lambda: _check("mb_lds_atomics", lib.mb_lds_atomics(kind, lds, block, nblk, iters, 7,
+                                                                           sink.data_ptr(), clk.data_ptr(), stream)))
+            f = mhz()
+            ops = nblk * block * iters * per
+            out["lds"].append({"kind": name, "shape": f"{block} threads, {lds // 1024} KiB, {per_cu // 8} per CU",
+                               "block": block, "lane_ops_per_launch": ops, "lane_ops_per_s": ops / t,
+                               "shader_mhz": f, "lane_ops_per_clk_per_cu": ops / t / (f * 1e6) / ncu, "seconds": t})
+        del sink
+    if lds_only:
+        return out
 
     # random-address FP64 atomics on the tally sizes of the 32x32 (N = 8) and 256x256 (N = 16) grids
     for label, n in (("1024 px x 17 (139 KB)", 1024 * 17), ("65536 px x 33 (17.3 MB)", 65536 * 33)):
@@ -112,8 +127,10 @@ def table(r: dict) -> str:
     rows = [f"{r['device']}, {r['cus']} CUs, constant counter {r['wall_clock_khz']} kHz", "",
             "| ceiling | rate | per CU per clock | shader clock (MHz) |", "|---|---|---|---|"]
     for e in r["lds"]:
-        rows.append(f"| LDS {e['kind']} | {e['lane_ops_per_s']:.3e} lane-ops/s | {e['lane_ops_per_clk_per_cu']:.2f} | "
-                    f"{e['shader_mhz']:.0f} |")
+        rows.append(f"| LDS {e['kind']} ({e['shape']}) | {e['lane_ops_per_s']:.3e} lane-ops/s | "
+                    f"{e['lane_ops_per_clk_per_cu']:.2f} | {e['shader_mhz']:.0f} |")
+    if "fma_f32" not in r:
+        return "\n".join(rows)
     for e in r["global_atomics"]:
         rows.append(f"| global FP64 atomic, random, {e['buffer']} | {e['atomics_per_s']:.3e} /s | | |")
     e = r["global_atomics_rows"]
@@ -130,7 +147,12 @@ def main() -> int:
     if not torch.cuda.is_available():
         print("the microbenchmarks need the GPU", file=sys.stderr)
         return 2
-    r = run_all()
+    import argparse
+    ap = argparse.ArgumentParser(description="device ceilings of the transport kernels")
+    ap.add_argument("--lds-only", type=int, choices=sorted(LDS_SHAPES), default=None,
+                    help="only the LDS atomics, in this workgroup size")
+    a = ap.parse_args()
+    r = run_all(lds_shapes=(a.lds_only,), lds_only=True) if a.lds_only else run_all()
     print(table(r), flush=True)
     print(json.dumps(r), flush=True)
     return 0

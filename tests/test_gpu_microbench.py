@@ -12,12 +12,12 @@ def test_microbenchmarks_count_their_operations():
     lib = L.load()
     d = torch.device("cuda", 0)
     s = C.c_void_p(torch.cuda.current_stream(d).cuda_stream)
-    nblk, block, iters = 40, 256, 24
+    nblk, iters = 40, 24
     sink = torch.empty(nblk, dtype=torch.float64, device=d)
     clk = torch.zeros(4, dtype=torch.int64, device=d)
     for kind, per in ((L.MB_LDS_ADD_F64, 1), (L.MB_LDS_ADD_F32, 1), (L.MB_LDS_ADD_U64, 1), (L.MB_LDS_ADD_U32, 1),
                       (L.MB_LDS_ADD_F64_ROW33, 33), (L.MB_LDS_ADD_U64_ROW33, 33), (L.MB_LDS_ADD_U64_PRE, 8)):
-        for lds in (4096, 96 * 1024):
+        for block, lds in ((256, 4096), (256, 96 * 1024), (1024, 144 * 1024)):   # the last: the transport's shape
             assert lib.mb_lds_atomics(kind, lds, block, nblk, iters, 5, sink.data_ptr(), clk.data_ptr(), s) == 0
             torch.cuda.synchronize()
             assert torch.all(sink == block * iters * per), (kind, lds, sink[:4])
