@@ -936,24 +936,40 @@ __device__ __forceinline__ void count_tile(const Gen &G, uint32_t *hist, bool lo
 // The scan of a generation, by the last workgroup of k_gen_count: exclusive
 // scan of the tile counts into cursors and a job list; bookkeeping of the
 // launches; the finisher decision; reset of the other pool's counters.
+// Inclusive scan of one count per thread over the kGenBlock threads of the
+// workgroup, and the workgroup's total: within each wave by shuffles, then
+// over the waves' totals (two barriers instead of two per doubling step).
+// wsum: kGenBlock / 64 words of LDS.
+__device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t *wsum, uint32_t &total) {
+    const int lane = __lane_id(), wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t u = __shfl_up(v, off);
+        if (lane >= off) v += u;
+    }
+    if (lane == 63) wsum[wave] = v;
+    __syncthreads();
+    uint32_t pre = 0, all = 0;
+    for (int w = 0; w < kGenBlock / 64; ++w) {
+        const uint32_t x = wsum[w];
+        pre += w < wave ? x : 0u;
+        all += x;
+    }
+    __syncthreads();   // wsum is free for the next scan
+    total = all;
+    return v + pre;
+}
+
 __device__ void gen_scan(const Gen &G, int g, uint32_t *buf, int np, const uint32_t *a_prob, const uint32_t *a_new) {
     GenCtl *C = G.ctl;
     const int cur = g & 1;
     const int t = threadIdx.x;
-    uint32_t *s_rec = buf, *s_job = buf + kGenBlock;
     const int per = (G.ntiles + kGenBlock - 1) / kGenBlock;
     const int a = t * per, b = min(G.ntiles, a + per);
     uint32_t nrec = 0;
     for (int i = a; i < b; ++i) nrec += G.tile_count[i];
-    s_rec[t] = nrec;
-    __syncthreads();
-    for (int off = 1; off < kGenBlock; off <<= 1) {   // inclusive Hillis-Steele scan
-        const uint32_t vr = t >= off ? s_rec[t - off] : 0u;
-        __syncthreads();
-        s_rec[t] += vr;
-        __syncthreads();
-    }
-    const uint32_t total = s_rec[kGenBlock - 1];
+    uint32_t total = 0;
+    const uint32_t rec_incl = block_scan(nrec, buf, total);
     // job size: job_size, or smaller when the generation's records would not
     // give every workgroup two jobs (never below job_min): a generation with
     // few packets then spreads its larger tiles over several workgroups
@@ -961,17 +977,10 @@ __device__ void gen_scan(const Gen &G, int g, uint32_t *buf, int np, const uint3
     const uint32_t js = min(G.job_size, max(G.job_min, want));
     uint32_t njob = 0;
     for (int i = a; i < b; ++i) njob += (G.tile_count[i] + js - 1) / js;
-    s_job[t] = njob;
-    __syncthreads();
-    for (int off = 1; off < kGenBlock; off <<= 1) {
-        const uint32_t vj = t >= off ? s_job[t - off] : 0u;
-        __syncthreads();
-        s_job[t] += vj;
-        __syncthreads();
-    }
-    const uint32_t total_jobs = s_job[kGenBlock - 1];
+    uint32_t total_jobs = 0;
+    const uint32_t job_incl = block_scan(njob, buf, total_jobs);
     const bool fits = total <= G.live && total_jobs <= G.max_jobs;   // hold by construction
-    uint32_t roff = s_rec[t] - nrec, joff = s_job[t] - njob;
+    uint32_t roff = rec_incl - nrec, joff = job_incl - njob;
     for (int i = a; i < b; ++i) {
         const uint32_t c = G.tile_count[i];
         G.tile_cursor[(size_t)i * kCursorStride] = roff;
