@@ -57,9 +57,9 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
 # only for the kernel source it was measured on: reported as null once that
 # source changes.
 TRAFFIC = {
-    "source_sha256": "c689b707f18229838fcc0f9c4d8052becdd46c3269cb3aba39ba7c4c8b7439b1",
-    "fetch_kib_per_launch": 253155.4, "fetch_factor": 2.000,
-    "write_kib_per_launch": 364362.9, "write_factor": 1.000,
+    "source_sha256": "8bb39fd3887b04371c6d942347b4d62e84295b83b6cd1f108f5dbfd0a7129089",
+    "fetch_kib_per_launch": 253160.5, "fetch_factor": 2.000,
+    "write_kib_per_launch": 364187.4, "write_factor": 1.000,
     # VALU wave-instructions per pixel visit (rocprofv3 SQ_INSTS_VALU over the
     # same dispatches, divided by the step's pixel visits)
     "valu_per_visit": 13.147,
