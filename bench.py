@@ -50,8 +50,8 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
 
 # HBM traffic of the transport launches from two rocprofv3 counter passes
-# (FETCH_SIZE, then WRITE_SIZE, KiB summed over all 1092 transport dispatches
-# of one benchmark step and divided by the 1090 launches the timer brackets:
+# (FETCH_SIZE, then WRITE_SIZE, KiB summed over all 1116 transport dispatches
+# of one benchmark step and divided by the 1114 launches the timer brackets:
 # the two untimed finisher passes for unlaunched packets find none), each
 # scaled by what the same counter reads for a plain 1 GiB device copy.  Valid
 # only for the kernel source it was measured on: reported as null once that
