@@ -29,7 +29,9 @@ Besides the throughput the line carries:
                 (forward + residual + adjoint + gradient) at the smallest
                 packet count whose gradient errors, averaged over 4 seeds, are
                 within 5% (d eps/d mua) and 20% (d eps/d mus) relative L2 of a
-                1e9 + 1e9-packet reference;
+                1e9 + 1e9-packet reference, with equal forward and adjoint
+                packet counts; `split` holds the same search with
+                FWD_ADJ_RATIO forward packets per adjoint packet;
   cpu_baseline  the FP64 oracle on the host's cores (and on one thread) on a
                 bounded sample of the same workload.
 Other modes: --time-to-error, --batch, --pencil32 (one JSON line each).
@@ -196,6 +198,15 @@ def cpu_baseline(n_packets: int, threads: int, host: dict) -> dict:
                               "sample": f"{n1}+{n1} packets, {dt1:.1f} s"}}
 
 
+# Forward : adjoint packets of the second time-to-error search.  At these
+# counts the d eps/d mus error is dominated by the product of the forward and
+# adjoint noise (it falls about as 1 / sqrt(N_fwd N_adj)), so the cost
+# c_fwd N_fwd + c_adj N_adj of a fixed error is least at N_fwd / N_adj =
+# c_adj / c_fwd; an adjoint packet of disc256 costs about twice a forward one
+# (1.57 against 0.71 s per 1e8 packets).
+FWD_ADJ_RATIO = 2
+
+
 def time_to_error(args, seeds: int = 4) -> dict:
     """Second half of the headline metric: wall time of one gradient evaluation
     (forward + residual + adjoint + gradient, N = 16) at the smallest packet
@@ -203,10 +214,12 @@ def time_to_error(args, seeds: int = 4) -> dict:
     independent seeds, are within 5% (d eps/d mua) and 20% (d eps/d mus) of a
     reference gradient from args.ref_packets + args.ref_packets packets, over
     pixels at least 10 pixels from the boundary.  Search: doubling from
-    5e5 packets until the mean errors meet both targets, then three geometric
+    5e5 packets until the mean errors meet both targets, then four geometric
     bisection steps between the last count that missed and the first that met
     them.  The reported time is the mean wall time of one gradient at that
-    count (each timed alone, bracketed by device synchronisations)."""
+    count (each timed alone, bracketed by device synchronisations).  The same
+    search is then made with FWD_ADJ_RATIO forward packets per adjoint packet
+    (`split`), doubling from a quarter of the first search's count."""
     import numpy as np
     import torch
     import phantoms as P
@@ -219,63 +232,77 @@ def time_to_error(args, seeds: int = 4) -> dict:
     ht, _ = rmc.mc_forward(tmed, c.sources, rmc.make_run(int(args.hmeas_packets), N, seed=1), ledger=False)
     hmeas = rmc.mc_absorbed(tmed, ht)
 
-    def gradient(n, seed):
-        f, _ = rmc.mc_forward(med, c.sources, rmc.make_run(n, N, seed=seed), ledger=False)
+    def gradient(nf, na, seed):
+        f, _ = rmc.mc_forward(med, c.sources, rmc.make_run(nf, N, seed=seed), ledger=False)
         q, _ = rmc.mc_residual(med, f, hmeas)
-        a, _ = rmc.mc_adjoint(med, [rmc.Source("map", map=q)], rmc.make_run(n, N, seed=seed, stream_tag=1),
+        a, _ = rmc.mc_adjoint(med, [rmc.Source("map", map=q)], rmc.make_run(na, N, seed=seed, stream_tag=1),
                               ledger=False)
         return rmc.mc_gradient(med, N, f, a, hmeas)
 
     log(f"time to error: reference gradient from {args.ref_packets:.0e} + {args.ref_packets:.0e} packets")
     t0 = time.perf_counter()
-    ra, rs = gradient(int(args.ref_packets), 100)
+    ra, rs = gradient(int(args.ref_packets), int(args.ref_packets), 100)
     torch.cuda.synchronize()
     log(f"reference: {time.perf_counter() - t0:.1f} s")
     m = 10
     ra, rs = ra[m:-m, m:-m], rs[m:-m, m:-m]
-    rows = {}
 
-    def evaluate(n):
+    def evaluate(nf, na):
         ea, es, walls = [], [], []
         for k in range(seeds):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            ga, gs = gradient(n, 7 + 1000 * k)
+            ga, gs = gradient(nf, na, 7 + 1000 * k)
             torch.cuda.synchronize()
             walls.append((time.perf_counter() - t0) * 1e3)
             ea.append(float((ga[m:-m, m:-m] - ra).norm() / ra.norm()))
             es.append(float((gs[m:-m, m:-m] - rs).norm() / rs.norm()))
         se = lambda v: float(np.std(v, ddof=1) / np.sqrt(len(v)))
-        r = {"packets": n, "wall_ms": float(np.mean(walls)), "wall_ms_min": float(np.min(walls)),
-             "err_dmua": float(np.mean(ea)), "err_dmua_se": se(ea),
+        r = {"packets_forward": nf, "packets_adjoint": na, "wall_ms": float(np.mean(walls)),
+             "wall_ms_min": float(np.min(walls)), "err_dmua": float(np.mean(ea)), "err_dmua_se": se(ea),
              "err_dmus": float(np.mean(es)), "err_dmus_se": se(es)}
-        rows[n] = r
-        log(f"{n:.3e} packets: {r['wall_ms']:.1f} ms, error dmua {r['err_dmua']:.4f} +- {r['err_dmua_se']:.4f}, "
-            f"dmus {r['err_dmus']:.4f} +- {r['err_dmus_se']:.4f}")
-        return r["err_dmua"] <= 0.05 and r["err_dmus"] <= 0.20
+        log(f"{nf:.3e} + {na:.3e} packets: {r['wall_ms']:.1f} ms, error dmua {r['err_dmua']:.4f} +- "
+            f"{r['err_dmua_se']:.4f}, dmus {r['err_dmus']:.4f} +- {r['err_dmus_se']:.4f}")
+        return r
 
-    n, lo = 500_000, None
-    while not evaluate(n) and n < args.ref_packets // 8:
-        lo, n = n, 2 * n
-    hi = n
-    ok = rows[hi]["err_dmua"] <= 0.05 and rows[hi]["err_dmus"] <= 0.20
-    if ok and lo is not None:
-        for _ in range(3):
-            mid = int(round(math.sqrt(lo * hi) / 1e4)) * 10_000
-            if mid in rows or mid <= lo or mid >= hi:
-                break
-            if evaluate(mid):
-                hi = mid
-            else:
-                lo = mid
-    hit = rows[hi]
-    return {"value": hit["wall_ms"] if ok else None, "unit": "ms", "higher_is_better": False, "reached": ok,
-            "packets_forward": hi, "packets_adjoint": hi,
-            "err_dmua": hit["err_dmua"], "err_dmua_se": hit["err_dmua_se"],
-            "err_dmus": hit["err_dmus"], "err_dmus_se": hit["err_dmus_se"],
-            "targets": {"dmua": 0.05, "dmus": 0.20}, "seeds": seeds, "reference_packets": int(args.ref_packets),
-            "pixels": "interior, 10-pixel margin",
-            "sweep": [rows[k] for k in sorted(rows)]}
+    def search(ratio, start):
+        rows = {}
+
+        def hit(n):   # n adjoint packets, ratio * n forward
+            if n not in rows:
+                rows[n] = evaluate(ratio * n, n)
+            return rows[n]["err_dmua"] <= 0.05 and rows[n]["err_dmus"] <= 0.20
+
+        n, lo = start, None
+        while not hit(n) and n < args.ref_packets // 8:
+            lo, n = n, 2 * n
+        hi = n
+        ok = hit(hi)
+        if ok and lo is not None:
+            for _ in range(4):
+                mid = int(round(math.sqrt(lo * hi) / 1e4)) * 10_000
+                if mid in rows or mid <= lo or mid >= hi:
+                    break
+                if hit(mid):
+                    hi = mid
+                else:
+                    lo = mid
+        best = rows[hi]
+        return {"value": best["wall_ms"] if ok else None, "reached": ok,
+                "packets_forward": best["packets_forward"], "packets_adjoint": best["packets_adjoint"],
+                "err_dmua": best["err_dmua"], "err_dmua_se": best["err_dmua_se"],
+                "err_dmus": best["err_dmus"], "err_dmus_se": best["err_dmus_se"],
+                "sweep": [rows[k] for k in sorted(rows)]}
+
+    eq = search(1, 500_000)
+    log(f"time to error, forward : adjoint packets {FWD_ADJ_RATIO} : 1")
+    sp = search(FWD_ADJ_RATIO, max(10_000, int(round(eq["packets_adjoint"] / 4 / 1e4)) * 10_000))
+    sp["ratio"] = FWD_ADJ_RATIO
+    out = {"value": eq["value"], "unit": "ms", "higher_is_better": False, "reached": eq["reached"]}
+    out.update({k: v for k, v in eq.items() if k not in ("value", "reached")})
+    out.update({"targets": {"dmua": 0.05, "dmus": 0.20}, "seeds": seeds, "reference_packets": int(args.ref_packets),
+                "pixels": "interior, 10-pixel margin", "split": sp})
+    return out
 
 
 def single_gradient(args) -> dict:
